@@ -1,0 +1,152 @@
+"""Plain FP64 CPU oracle of the dSASA hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product path (the HIP
+library and its Python binding) never does, and shares no code with it.
+
+``run(xyz, radii, probe)`` returns an :class:`OracleResult` holding, for the
+weighted points (p_i, (r_i + probe)^2) of arXiv 2401.10462 (Methods):
+
+* the alpha = 0 dual complex K (vertices, edges, triangles, tetrahedra),
+  each simplex decided from its definition (Steps 1-2);
+* the exterior classification (GPU section, extraction of exterior simplices);
+* per-atom SASA by Eq. 1 and the Jacobian dA_i/dp_m by Eq. 2.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build(force=True)
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_run.restype = P
+        L.oracle_run.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double]
+        L.oracle_free.argtypes = [P]
+        L.oracle_count.restype = ctypes.c_int64
+        L.oracle_count.argtypes = [P, ctypes.c_int]
+        for name in ("oracle_area", "oracle_dadx"):
+            getattr(L, name).argtypes = [P, dp]
+        L.oracle_vjp.argtypes = [P, dp, dp]
+        L.oracle_jacobian.argtypes = [P, P, P, dp]
+        L.oracle_vertices.argtypes = [P, P, P]
+        L.oracle_edges.argtypes = [P, P, P]
+        L.oracle_triangles.argtypes = [P, P, P, P]
+        L.oracle_tetrahedra.argtypes = [P, P]
+        for name in ("oracle_solid_angle", "oracle_dihedral"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_double
+            f.argtypes = [dp, dp, dp, dp]
+        L.oracle_cap_area.restype = ctypes.c_double
+        L.oracle_cap_area.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double]
+        L.oracle_triple_term.restype = ctypes.c_double
+        L.oracle_triple_term.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double, dp, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _vp(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _v3(p):
+    return np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+
+
+class OracleResult:
+    """Result of one oracle run; arrays are numpy copies."""
+
+    def __init__(self, xyz, radii, probe):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+        if xyz.shape[0] != radii.shape[0]:
+            raise ValueError("xyz and radii disagree on the atom count")
+        L = lib()
+        self.n = n = xyz.shape[0]
+        h = L.oracle_run(n, _dp(xyz), _dp(radii), float(probe))
+        if not h:
+            raise ValueError("invalid oracle input")
+        try:
+            c = [L.oracle_count(h, k) for k in range(10)]
+            self.counts = dict(zip(
+                ["vertices", "edges", "triangles", "tetrahedra", "ext_vertices",
+                 "ext_edges", "ext_triangles", "jac_nnz", "near_ties", "degenerate"], c))
+            self.area = np.zeros(n)
+            L.oracle_area(h, _dp(self.area))
+            self.dadx = np.zeros((n, 3))
+            L.oracle_dadx(h, _dp(self.dadx))
+            nnz = c[7]
+            self.jac_rows = np.zeros(nnz, np.int32)
+            self.jac_cols = np.zeros(nnz, np.int32)
+            self.jac_vals = np.zeros((nnz, 3))
+            L.oracle_jacobian(h, _vp(self.jac_rows), _vp(self.jac_cols), _dp(self.jac_vals))
+            self.vert_in = np.zeros(n, np.uint8)
+            self.vert_ext = np.zeros(n, np.uint8)
+            L.oracle_vertices(h, _vp(self.vert_in), _vp(self.vert_ext))
+            self.edges = np.zeros((c[1], 2), np.int32)
+            self.edge_ext = np.zeros(c[1], np.uint8)
+            L.oracle_edges(h, _vp(self.edges), _vp(self.edge_ext))
+            self.tris = np.zeros((c[2], 3), np.int32)
+            self.tri_ntet = np.zeros(c[2], np.uint8)
+            self.tri_ext = np.zeros(c[2], np.uint8)
+            L.oracle_triangles(h, _vp(self.tris), _vp(self.tri_ntet), _vp(self.tri_ext))
+            self.tets = np.zeros((c[3], 4), np.int32)
+            L.oracle_tetrahedra(h, _vp(self.tets))
+        finally:
+            L.oracle_free(h)
+
+    def vjp(self, u):
+        """sum_i u_i dA_i/dp_m, from the stored Jacobian blocks (n x 3)."""
+        u = np.asarray(u, dtype=np.float64).reshape(-1)
+        g = np.zeros((self.n, 3))
+        np.add.at(g, self.jac_cols, u[self.jac_rows][:, None] * self.jac_vals)
+        return g
+
+    def jacobian_dense(self):
+        """dA_i/dp_m as an (n, n, 3) array (small n only)."""
+        J = np.zeros((self.n, self.n, 3))
+        J[self.jac_rows, self.jac_cols] = self.jac_vals
+        return J
+
+
+def run(xyz, radii, probe=1.4):
+    """Run the oracle on one molecule."""
+    return OracleResult(xyz, radii, probe)
+
+
+def solid_angle(pi, pj, pk, pl):
+    """Normalised solid angle at pi of tetrahedron (pi, pj, pk, pl)."""
+    return lib().oracle_solid_angle(*[_dp(_v3(p)) for p in (pi, pj, pk, pl)])
+
+
+def dihedral(pi, pj, pk, pl):
+    """Normalised dihedral angle along edge pi-pj between faces (i,j,k), (i,j,l)."""
+    return lib().oracle_dihedral(*[_dp(_v3(p)) for p in (pi, pj, pk, pl)])
+
+
+def cap_area(pi, Ri, pj, Rj):
+    """Area of sphere (pi, Ri) inside ball (pj, Rj)."""
+    a, b = _v3(pi), _v3(pj)
+    return lib().oracle_cap_area(_dp(a), float(Ri), _dp(b), float(Rj))
+
+
+def triple_term(pi, Ri, pj, Rj, pk, Rk):
+    """Area of sphere i inside both balls j and k (Eq. 6, both halves)."""
+    a, b, c = _v3(pi), _v3(pj), _v3(pk)
+    return lib().oracle_triple_term(_dp(a), float(Ri), _dp(b), float(Rj), _dp(c), float(Rk))

@@ -1,0 +1,29 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/libsasa_oracle.so.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use it.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sasa_oracle.cc")
+LIB = os.path.join(HERE, "libsasa_oracle.so")
+
+
+def build(force=True, march_native=False):
+    """Compile the oracle with g++ (plain -O2; -march=native only if asked)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    flags = ["-O2", "-std=c++17", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off"]
+    if march_native:
+        flags.append("-march=native")
+    tmp = LIB + ".tmp"
+    cmd = ["g++", *flags, SRC, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force=True, march_native="--native" in sys.argv))

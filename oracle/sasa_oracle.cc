@@ -1,0 +1,686 @@
+// sasa_oracle.cc -- plain FP64 CPU reference of the dSASA hot path.
+//
+// TEST INFRASTRUCTURE ONLY (see sasa_oracle.h).  Deliberately simple and slow:
+// brute-force neighbour search, the dual complex decided from its definition
+// simplex by simplex, and derivatives by forward-mode dual numbers.  It shares
+// no code with the HIP library.
+//
+// Notation follows the paper (arXiv 2401.10462, Methods): p_i atom centre,
+// R_i = r_i + probe, weight d_i = R_i^2 (called w here), power distance
+// pi_i(x) = |x - p_i|^2 - w_i, Laguerre cell L_i = {x : pi_i(x) <= pi_j(x) all j},
+// ball B_i = {pi_i <= 0}.
+
+#include "sasa_oracle.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kNearTie = 1e-9;  // A^2: margins below this are counted as near-degenerate
+
+// ---------------------------------------------------------------- plain vectors
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 scl(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 crs(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double nrm2(V3 a) { return dot(a, a); }
+
+// ---------------------------------------------------------- forward-mode duals
+// A value with its gradient with respect to the 12 coordinates of (at most)
+// four atoms; slot s covers coordinates 3s..3s+2.
+constexpr int NG = 12;
+struct D {
+  double v;
+  double g[NG];
+};
+inline D cst(double v) {
+  D r;
+  r.v = v;
+  std::memset(r.g, 0, sizeof(r.g));
+  return r;
+}
+inline D operator+(const D& a, const D& b) {
+  D r;
+  r.v = a.v + b.v;
+  for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] + b.g[k];
+  return r;
+}
+inline D operator-(const D& a, const D& b) {
+  D r;
+  r.v = a.v - b.v;
+  for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] - b.g[k];
+  return r;
+}
+inline D operator*(const D& a, const D& b) {
+  D r;
+  r.v = a.v * b.v;
+  for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] * b.v + a.v * b.g[k];
+  return r;
+}
+inline D operator*(const D& a, double s) {
+  D r;
+  r.v = a.v * s;
+  for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] * s;
+  return r;
+}
+inline D operator/(const D& a, const D& b) {
+  D r;
+  r.v = a.v / b.v;
+  for (int k = 0; k < NG; ++k) r.g[k] = (a.g[k] * b.v - a.v * b.g[k]) / (b.v * b.v);
+  return r;
+}
+inline D dsqrt(const D& a) {
+  D r;
+  r.v = std::sqrt(a.v);
+  for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] / (2.0 * r.v);
+  return r;
+}
+inline D dabs(const D& a) { return a.v < 0 ? a * -1.0 : a; }
+inline D datan2(const D& y, const D& x) {
+  D r;
+  r.v = std::atan2(y.v, x.v);
+  const double den = x.v * x.v + y.v * y.v;
+  for (int k = 0; k < NG; ++k) r.g[k] = (x.v * y.g[k] - y.v * x.g[k]) / den;
+  return r;
+}
+
+struct DV {
+  D x, y, z;
+};
+inline DV dsub(const DV& a, const DV& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline DV dadd(const DV& a, const DV& b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline DV dscl(const DV& a, const D& s) { return {a.x * s, a.y * s, a.z * s}; }
+inline D ddot(const DV& a, const DV& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline DV dcrs(const DV& a, const DV& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline D dnorm(const DV& a) { return dsqrt(ddot(a, a)); }
+
+// A point whose three coordinates are the independent variables of slot s.
+inline DV seed(V3 p, int s) {
+  DV r{cst(p.x), cst(p.y), cst(p.z)};
+  r.x.g[3 * s + 0] = 1.0;
+  r.y.g[3 * s + 1] = 1.0;
+  r.z.g[3 * s + 2] = 1.0;
+  return r;
+}
+inline DV fixed(V3 p) { return {cst(p.x), cst(p.y), cst(p.z)}; }
+
+// ------------------------------------------------------------ formula pieces
+
+// Normalised inner solid angle at p_i of the tetrahedron (p_i, p_j, p_k, p_l)
+// in the Van Oosterom--Strackee form (Methods, solid angle after Eq. 3),
+// written with atan2 so that it stays correct past a right angle:
+//   omega = atan2(|a.(b x c)|, abc + (a.b)c + (a.c)b + (b.c)a) / (2 pi),
+// a = p_j - p_i, b = p_k - p_i, c = p_l - p_i.  omega is the fraction of the
+// full sphere around p_i that the tetrahedron subtends.
+D solid_angle(const DV& pi, const DV& pj, const DV& pk, const DV& pl) {
+  const DV a = dsub(pj, pi), b = dsub(pk, pi), c = dsub(pl, pi);
+  const D la = dnorm(a), lb = dnorm(b), lc = dnorm(c);
+  const D num = dabs(ddot(a, dcrs(b, c)));
+  const D den = la * lb * lc + ddot(a, b) * lc + ddot(a, c) * lb + ddot(b, c) * la;
+  return datan2(num, den) * (1.0 / (2.0 * kPi));
+}
+
+// Normalised inner dihedral angle of the tetrahedron (p_i, p_j, p_k, p_l) along
+// its edge p_i p_j, i.e. the angle between the faces (i,j,k) and (i,j,l), over
+// 2 pi (Eq. 4).  The normals are n_k = e x (p_k - p_i), n_l = e x (p_l - p_i)
+// with e = p_j - p_i, so the angle between them is the interior angle; it is
+// taken as atan2(|n_k x n_l|, n_k . n_l) rather than arccos of the normalised
+// dot product, which is the same angle without the loss of accuracy near 0, pi.
+D dihedral(const DV& pi, const DV& pj, const DV& pk, const DV& pl) {
+  const DV e = dsub(pj, pi);
+  const DV nk = dcrs(e, dsub(pk, pi));
+  const DV nl = dcrs(e, dsub(pl, pi));
+  return datan2(dnorm(dcrs(nk, nl)), ddot(nk, nl)) * (1.0 / (2.0 * kPi));
+}
+
+// Area of the cap of sphere i that lies inside ball j: S_ij^(i) = 2 pi sqrt(d_i) h_i
+// (edge term after Eq. 3).  h_i is the height of that cap: the plane of the
+// two spheres' intersection circle lies at distance a_i = (d^2 + w_i - w_j)/(2d)
+// from p_i along p_j - p_i, so h_i = R_i - a_i.
+D cap_area(const DV& pi, double Ri, const DV& pj, double Rj) {
+  const D d = dnorm(dsub(pj, pi));
+  const D ai = (d * d + cst(Ri * Ri - Rj * Rj)) / (d * 2.0);
+  return (cst(Ri) - ai) * (2.0 * kPi * Ri);
+}
+
+// One of the two triple points x common to the spheres i, j, k (Eq. 6): x lies
+// on the line of equal power of the three weighted points, at power distance 0.
+// y is the point of that line in the plane of the three centres; s = pi_i(y) < 0
+// when the three spheres meet; x = y + sqrt(-s) n / |n|, n the plane normal.
+// Returns false if the spheres have no common point.
+bool triple_point(const DV& pi, double wi, const DV& pj, double wj, const DV& pk, double wk, DV* x) {
+  const DV a = dsub(pj, pi), b = dsub(pk, pi);
+  // Equal-power conditions relative to p_i: 2 a.y = |a|^2 - w_j + w_i, same for b.
+  const D ba = ddot(a, a) + cst(wi - wj);
+  const D bb = ddot(b, b) + cst(wi - wk);
+  const D aa = ddot(a, a) * 2.0, ab = ddot(a, b) * 2.0, bbb = ddot(b, b) * 2.0;
+  const D det = aa * bbb - ab * ab;
+  const D alpha = (ba * bbb - bb * ab) / det;
+  const D beta = (aa * bb - ab * ba) / det;
+  const DV y = dadd(dscl(a, alpha), dscl(b, beta));
+  const D s = ddot(y, y) - cst(wi);
+  if (!(s.v < 0)) return false;
+  const DV n = dcrs(a, b);
+  const D t = dsqrt(cst(0.0) - s) / dnorm(n);
+  *x = dadd(pi, dadd(y, dscl(n, t)));
+  return true;
+}
+
+// Contribution S_ijk^(i) of the triple intersection to sphere i (Eq. 6):
+//   S/2 = phi_ij(T_x) S_ij^(i) + phi_ik(T_x) S_ik^(i) - omega_i(T_x) 4 pi w_i,
+// with T_x = (p_i, p_j, p_k, x), phi_ij(T_x) the normalised dihedral angle of
+// T_x along edge ij, omega_i(T_x) its normalised solid angle at p_i.
+D triple_term(const DV& pi, double Ri, const DV& pj, double Rj, const DV& pk, double Rk) {
+  DV x;
+  if (!triple_point(pi, Ri * Ri, pj, Rj * Rj, pk, Rk * Rk, &x)) return cst(0.0);
+  const D phij = dihedral(pi, pj, pk, x);
+  const D phik = dihedral(pi, pk, pj, x);
+  const D om = solid_angle(pi, pj, pk, x);
+  const D half = phij * cap_area(pi, Ri, pj, Rj) + phik * cap_area(pi, Ri, pk, Rk) -
+                 om * (4.0 * kPi * Ri * Ri);
+  return half * 2.0;
+}
+
+// ------------------------------------------------------------------ the run
+using Tri = std::array<int, 3>;
+using Tet = std::array<int, 4>;
+
+}  // namespace
+
+struct oracle_result {
+  int64_t n = 0;
+  std::vector<V3> p;
+  std::vector<double> R, w;
+  std::vector<std::vector<int>> nb;  // overlapping neighbours, ascending
+  std::vector<uint8_t> vin, vext;
+  std::vector<std::array<int, 2>> edges;
+  std::vector<uint8_t> eext;
+  std::vector<Tri> tris;
+  std::vector<uint8_t> tnt, text;
+  std::vector<Tet> tets;
+  std::vector<double> area;
+  std::vector<std::map<int, V3>> jac;  // jac[i][m] = dA_i/dp_m
+  int64_t near_ties = 0, degenerate = 0;
+
+  bool ov(int i, int j) const { return std::binary_search(nb[i].begin(), nb[i].end(), j); }
+  // g_m(x) = pi_m(x) - pi_i(x) for x given relative to p_i; >= 0 means x is
+  // not cut away from L_i by atom m.
+  double gap(int i, int m, V3 xr) const {
+    const V3 a = sub(p[m], p[i]);
+    return nrm2(a) - w[m] + w[i] - 2.0 * dot(a, xr);
+  }
+  void tie(double margin) {
+    if (std::fabs(margin) < kNearTie) ++near_ties;
+  }
+};
+
+namespace {
+
+void neighbours(oracle_result& r) {
+  // Only balls that overlap can cut L_i cap B_i: for disjoint balls the radical
+  // plane separates them, so pi_i < pi_j everywhere in B_i.
+  const int n = (int)r.n;
+  r.nb.assign(n, {});
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double s = r.R[i] + r.R[j];
+      if (nrm2(sub(r.p[j], r.p[i])) < s * s) {
+        r.nb[i].push_back(j);
+        r.nb[j].push_back(i);
+      }
+    }
+  for (auto& v : r.nb) std::sort(v.begin(), v.end());
+}
+
+// Tetrahedron (i,j,k,l) is in K iff its orthocentre z (the point of equal power
+// to all four) is a vertex of the Laguerre diagram inside the balls: pi_i(z) <= 0
+// and pi_m(z) >= pi_i(z) for every other atom m.  An atom m that violates the
+// second condition while pi_i(z) <= 0 has z inside B_m and so overlaps B_i;
+// checking the neighbours of i is therefore the whole test.
+void tetrahedra(oracle_result& r) {
+  const int n = (int)r.n;
+  for (int i = 0; i < n; ++i) {
+    const auto& N = r.nb[i];
+    for (size_t a = 0; a < N.size(); ++a) {
+      const int j = N[a];
+      if (j < i) continue;
+      for (size_t b = a + 1; b < N.size(); ++b) {
+        const int k = N[b];
+        if (!r.ov(j, k)) continue;
+        for (size_t c = b + 1; c < N.size(); ++c) {
+          const int l = N[c];
+          if (!r.ov(j, l) || !r.ov(k, l)) continue;
+          // Solve 2 a_q . z = |a_q|^2 - w_q + w_i for q = j, k, l (z relative to p_i).
+          const V3 aj = sub(r.p[j], r.p[i]), ak = sub(r.p[k], r.p[i]), al = sub(r.p[l], r.p[i]);
+          const double bj = nrm2(aj) - r.w[j] + r.w[i];
+          const double bk = nrm2(ak) - r.w[k] + r.w[i];
+          const double bl = nrm2(al) - r.w[l] + r.w[i];
+          const V3 ckl = crs(ak, al), clj = crs(al, aj), cjk = crs(aj, ak);
+          const double det = 2.0 * dot(aj, ckl);
+          if (std::fabs(det) < 1e-12) {
+            ++r.degenerate;
+            continue;
+          }
+          const V3 z = scl(add(add(scl(ckl, bj), scl(clj, bk)), scl(cjk, bl)), 1.0 / det);
+          const double pz = nrm2(z) - r.w[i];
+          r.tie(pz);
+          if (pz > 0) continue;
+          bool empty = true;
+          for (int m : N) {
+            if (m == j || m == k || m == l) continue;
+            const double g = r.gap(i, m, z);
+            r.tie(g);
+            if (g < 0) {
+              empty = false;
+              break;
+            }
+          }
+          if (empty) r.tets.push_back({i, j, k, l});
+        }
+      }
+    }
+  }
+  std::sort(r.tets.begin(), r.tets.end());
+}
+
+// Triangle (i,j,k) is in K iff the Laguerre edge shared by L_i, L_j, L_k meets
+// the balls.  That edge lies on the line of equal power y + s n^ (y in the plane
+// of the centres); on it pi_i = s_t + s^2 with s_t = pi_i(y), so the ball part
+// is |s| <= sqrt(-s_t), and each other neighbour m keeps the half-line
+// g_m(y + s n^) >= 0.  The triangle is in K iff the intersection of these
+// intervals is not empty.
+void triangles(oracle_result& r) {
+  const int n = (int)r.n;
+  for (int i = 0; i < n; ++i) {
+    const auto& N = r.nb[i];
+    for (size_t a = 0; a < N.size(); ++a) {
+      const int j = N[a];
+      if (j < i) continue;
+      for (size_t b = a + 1; b < N.size(); ++b) {
+        const int k = N[b];
+        if (!r.ov(j, k)) continue;
+        const V3 aj = sub(r.p[j], r.p[i]), ak = sub(r.p[k], r.p[i]);
+        const double bj = nrm2(aj) - r.w[j] + r.w[i];
+        const double bk = nrm2(ak) - r.w[k] + r.w[i];
+        const double g11 = 2 * dot(aj, aj), g12 = 2 * dot(aj, ak), g22 = 2 * dot(ak, ak);
+        const double det = g11 * g22 - g12 * g12;
+        if (std::fabs(det) < 1e-12 * g11 * g22) {
+          ++r.degenerate;
+          continue;
+        }
+        const double al = (bj * g22 - bk * g12) / det, be = (g11 * bk - g12 * bj) / det;
+        const V3 y = add(scl(aj, al), scl(ak, be));
+        const double st = nrm2(y) - r.w[i];
+        r.tie(st);
+        if (st > 0) continue;
+        V3 nn = crs(aj, ak);
+        nn = scl(nn, 1.0 / std::sqrt(nrm2(nn)));
+        double lo = -std::sqrt(-st), hi = std::sqrt(-st);
+        for (int m : N) {
+          if (m == j || m == k) continue;
+          // g_m(y + s n) = g_m(y) - 2 (a_m . n) s >= 0
+          const V3 am = sub(r.p[m], r.p[i]);
+          const double g0 = r.gap(i, m, y);
+          const double g1 = -2.0 * dot(am, nn);
+          if (g1 == 0.0) {
+            if (g0 < 0) lo = 1, hi = 0;
+            continue;
+          }
+          const double root = -g0 / g1;
+          if (g1 > 0) lo = std::max(lo, root);
+          else hi = std::min(hi, root);
+          if (lo > hi) break;
+        }
+        r.tie(hi - lo);
+        if (lo <= hi) r.tris.push_back({i, j, k});
+      }
+    }
+  }
+  std::sort(r.tris.begin(), r.tris.end());
+}
+
+// Edge (i,j) is in K iff the Laguerre facet shared by L_i and L_j meets the
+// balls: the disk cut from B_i by the radical plane, intersected with the
+// facet, is not empty.  Both are convex, so either the facet boundary crosses
+// the disk -- then a triangle (i,j,k) of K exists -- or the disk centre y_e lies
+// in the facet, i.e. in L_i, and the disk is real (pi_i(y_e) <= 0).
+void edges(oracle_result& r) {
+  const int n = (int)r.n;
+  std::vector<std::vector<int>> has_tri(n);  // j in has_tri[i] if (i,j) is on a K-triangle
+  for (const auto& t : r.tris) {
+    has_tri[t[0]].push_back(t[1]);
+    has_tri[t[0]].push_back(t[2]);
+    has_tri[t[1]].push_back(t[2]);
+  }
+  for (auto& v : has_tri) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  for (int i = 0; i < n; ++i) {
+    for (int j : r.nb[i]) {
+      if (j < i) continue;
+      if (std::binary_search(has_tri[i].begin(), has_tri[i].end(), j)) {
+        r.edges.push_back({i, j});
+        continue;
+      }
+      const V3 aj = sub(r.p[j], r.p[i]);
+      const double bj = nrm2(aj) - r.w[j] + r.w[i];
+      const V3 ye = scl(aj, bj / (2.0 * nrm2(aj)));
+      const double se = nrm2(ye) - r.w[i];
+      r.tie(se);
+      if (se > 0) continue;
+      bool inside = true;
+      for (int m : r.nb[i]) {
+        if (m == j) continue;
+        const double g = r.gap(i, m, ye);
+        r.tie(g);
+        if (g < 0) {
+          inside = false;
+          break;
+        }
+      }
+      if (inside) r.edges.push_back({i, j});
+    }
+  }
+  std::sort(r.edges.begin(), r.edges.end());
+}
+
+// Vertex i is in K iff L_i cap B_i is not empty: either a facet of L_i meets
+// B_i (a K-edge at i), or no facet does and then B_i lies inside L_i, which
+// holds iff p_i itself is in L_i (pi_m(p_i) >= -w_i for all m).
+void vertices(oracle_result& r) {
+  const int n = (int)r.n;
+  r.vin.assign(n, 0);
+  for (const auto& e : r.edges) r.vin[e[0]] = r.vin[e[1]] = 1;
+  for (int i = 0; i < n; ++i) {
+    if (r.vin[i]) continue;
+    bool inside = true;
+    for (int m : r.nb[i]) {
+      const double g = r.gap(i, m, V3{0, 0, 0});
+      r.tie(g);
+      if (g < 0) {
+        inside = false;
+        break;
+      }
+    }
+    r.vin[i] = inside;
+  }
+}
+
+// Classification (GPU section, extraction of exterior simplices).  A triangle
+// with at most one K-tetrahedron on it is exterior; its coefficient is
+// c_t = 1 - n_t / 2.  An edge is exterior iff it lies on an exterior triangle or
+// on no K-triangle at all: otherwise the K-tetrahedra close up around it and
+// its outer dihedral coefficient is exactly 0.  A vertex is exterior iff it has
+// an exterior K-edge or no K-edge (then it is an isolated ball); otherwise its
+// outer solid angle is exactly 0.  Both rules imply the paper's "an edge is
+// exterior only if both its vertices are".
+void classify(oracle_result& r) {
+  const int n = (int)r.n;
+  std::map<Tri, int> nt;
+  for (const auto& t : r.tris) nt[t] = 0;
+  for (const auto& T : r.tets) {
+    const Tri faces[4] = {{T[1], T[2], T[3]}, {T[0], T[2], T[3]}, {T[0], T[1], T[3]}, {T[0], T[1], T[2]}};
+    for (const auto& f : faces) nt[f] += 1;  // a K-tet's faces are in K
+  }
+  r.tnt.resize(r.tris.size());
+  r.text.resize(r.tris.size());
+  std::map<std::array<int, 2>, int> e_state;  // 0: no triangle yet, 1: only interior, 2: exterior
+  for (const auto& e : r.edges) e_state[e] = 0;
+  for (size_t t = 0; t < r.tris.size(); ++t) {
+    const auto& T = r.tris[t];
+    r.tnt[t] = (uint8_t)nt[T];
+    r.text[t] = r.tnt[t] <= 1;
+    const std::array<int, 2> es[3] = {{T[0], T[1]}, {T[0], T[2]}, {T[1], T[2]}};
+    for (const auto& e : es) {
+      int& s = e_state[e];
+      s = std::max(s, r.text[t] ? 2 : 1);
+    }
+  }
+  r.eext.resize(r.edges.size());
+  r.vext.assign(n, 0);
+  std::vector<uint8_t> has_edge(n, 0);
+  for (size_t k = 0; k < r.edges.size(); ++k) {
+    const int s = e_state[r.edges[k]];
+    r.eext[k] = (s == 0 || s == 2);
+    has_edge[r.edges[k][0]] = has_edge[r.edges[k][1]] = 1;
+    if (r.eext[k]) r.vext[r.edges[k][0]] = r.vext[r.edges[k][1]] = 1;
+  }
+  for (int i = 0; i < n; ++i)
+    if (r.vin[i] && !has_edge[i]) r.vext[i] = 1;
+}
+
+void add_grad(std::map<int, V3>& row, int atom, const D& f, int slot, double scale) {
+  V3& g = row[atom];
+  g.x += scale * f.g[3 * slot + 0];
+  g.y += scale * f.g[3 * slot + 1];
+  g.z += scale * f.g[3 * slot + 2];
+}
+
+// Per-atom area, Eq. 1, and its gradient, Eq. 2:
+//   A_i = Omega_i 4 pi w_i - sum_{ext e=ij} Phi_ij S_ij^(i) + sum_{ext t=ijk} c_ijk S_ijk^(i)
+//   Omega_i = 1 - sum_{K-tets T at i} omega_i(T)            (Eq. 3)
+//   Phi_ij  = 1 - sum_{K-tets T on ij} phi_ij(T)             (Eqs. 4, 5)
+// Each piece is a dual number over the atoms it depends on, so the product rule
+// of Eq. 2 and the chain rule through the triple point of Eq. 7 are exact.
+void areas(oracle_result& r) {
+  const int n = (int)r.n;
+  r.area.assign(n, 0.0);
+  r.jac.assign(n, {});
+  std::vector<std::vector<int>> tets_at(n);
+  for (size_t t = 0; t < r.tets.size(); ++t)
+    for (int v : r.tets[t]) tets_at[v].push_back((int)t);
+  std::vector<std::vector<int>> edges_at(n), tris_at(n);
+  for (size_t e = 0; e < r.edges.size(); ++e)
+    if (r.eext[e]) {
+      edges_at[r.edges[e][0]].push_back((int)e);
+      edges_at[r.edges[e][1]].push_back((int)e);
+    }
+  for (size_t t = 0; t < r.tris.size(); ++t)
+    if (r.text[t])
+      for (int v : r.tris[t]) tris_at[v].push_back((int)t);
+
+  for (int i = 0; i < n; ++i) {
+    if (!r.vin[i] || !r.vext[i]) continue;  // interior or hidden atoms: A_i = 0
+    auto& row = r.jac[i];
+    row[i] = V3{0, 0, 0};
+    const double Si = 4.0 * kPi * r.w[i];
+    double A = 0.0;
+    // Vertex term.
+    double Omega = 1.0;
+    for (int t : tets_at[i]) {
+      const Tet& T = r.tets[t];
+      int o[3], c = 0;
+      for (int v : T)
+        if (v != i) o[c++] = v;
+      const D om = solid_angle(seed(r.p[i], 0), seed(r.p[o[0]], 1), seed(r.p[o[1]], 2), seed(r.p[o[2]], 3));
+      Omega -= om.v;
+      add_grad(row, i, om, 0, -Si);
+      for (int s = 0; s < 3; ++s) add_grad(row, o[s], om, s + 1, -Si);
+    }
+    A += Omega * Si;
+    // Edge terms.
+    for (int e : edges_at[i]) {
+      const int j = r.edges[e][0] == i ? r.edges[e][1] : r.edges[e][0];
+      const D S = cap_area(seed(r.p[i], 0), r.R[i], seed(r.p[j], 1), r.R[j]);
+      double Phi = 1.0;
+      for (int t : tets_at[i]) {
+        const Tet& T = r.tets[t];
+        if (std::find(T.begin(), T.end(), j) == T.end()) continue;
+        int o[2], c = 0;
+        for (int v : T)
+          if (v != i && v != j) o[c++] = v;
+        const D ph = dihedral(seed(r.p[i], 0), seed(r.p[j], 1), seed(r.p[o[0]], 2), seed(r.p[o[1]], 3));
+        Phi -= ph.v;
+        // d(Phi S) gets -S dphi
+        add_grad(row, i, ph, 0, S.v);
+        add_grad(row, j, ph, 1, S.v);
+        add_grad(row, o[0], ph, 2, S.v);
+        add_grad(row, o[1], ph, 3, S.v);
+      }
+      A -= Phi * S.v;
+      add_grad(row, i, S, 0, -Phi);
+      add_grad(row, j, S, 1, -Phi);
+    }
+    // Triangle terms.
+    for (int t : tris_at[i]) {
+      const Tri& T = r.tris[t];
+      int o[2], c = 0;
+      for (int v : T)
+        if (v != i) o[c++] = v;
+      const double ct = 1.0 - 0.5 * r.tnt[t];
+      const D St = triple_term(seed(r.p[i], 0), r.R[i], seed(r.p[o[0]], 1), r.R[o[0]], seed(r.p[o[1]], 2),
+                               r.R[o[1]]);
+      A += ct * St.v;
+      add_grad(row, i, St, 0, ct);
+      add_grad(row, o[0], St, 1, ct);
+      add_grad(row, o[1], St, 2, ct);
+    }
+    r.area[i] = A;
+  }
+}
+
+V3 load(const double* q) { return {q[0], q[1], q[2]}; }
+
+}  // namespace
+
+extern "C" {
+
+oracle_result* oracle_run(int64_t n, const double* xyz, const double* radii, double probe) {
+  if (n < 0 || (n > 0 && (!xyz || !radii)) || !(probe >= 0) || !std::isfinite(probe)) return nullptr;
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return nullptr;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(radii[i] > 0) || !std::isfinite(radii[i])) return nullptr;
+  auto* r = new oracle_result;
+  r->n = n;
+  r->p.resize(n);
+  r->R.resize(n);
+  r->w.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    r->p[i] = load(xyz + 3 * i);
+    r->R[i] = radii[i] + probe;  // probe-inflated sphere
+    r->w[i] = r->R[i] * r->R[i];  // weight d_i = (r_i + probe)^2
+  }
+  neighbours(*r);
+  tetrahedra(*r);
+  triangles(*r);
+  edges(*r);
+  vertices(*r);
+  classify(*r);
+  areas(*r);
+  return r;
+}
+
+void oracle_free(oracle_result* r) { delete r; }
+
+int64_t oracle_count(const oracle_result* r, int what) {
+  switch (what) {
+    case 0: return std::count(r->vin.begin(), r->vin.end(), 1);
+    case 1: return (int64_t)r->edges.size();
+    case 2: return (int64_t)r->tris.size();
+    case 3: return (int64_t)r->tets.size();
+    case 4: {
+      int64_t c = 0;
+      for (int64_t i = 0; i < r->n; ++i) c += r->vin[i] && r->vext[i];
+      return c;
+    }
+    case 5: return std::count(r->eext.begin(), r->eext.end(), 1);
+    case 6: return std::count(r->text.begin(), r->text.end(), 1);
+    case 7: {
+      int64_t c = 0;
+      for (const auto& row : r->jac) c += (int64_t)row.size();
+      return c;
+    }
+    case 8: return r->near_ties;
+    case 9: return r->degenerate;
+  }
+  return -1;
+}
+
+void oracle_area(const oracle_result* r, double* area) {
+  std::copy(r->area.begin(), r->area.end(), area);
+}
+
+void oracle_vjp(const oracle_result* r, const double* u, double* g) {
+  std::fill(g, g + 3 * r->n, 0.0);
+  for (int64_t i = 0; i < r->n; ++i)
+    for (const auto& kv : r->jac[i]) {
+      g[3 * kv.first + 0] += u[i] * kv.second.x;
+      g[3 * kv.first + 1] += u[i] * kv.second.y;
+      g[3 * kv.first + 2] += u[i] * kv.second.z;
+    }
+}
+
+void oracle_dadx(const oracle_result* r, double* g) {
+  std::vector<double> ones(r->n, 1.0);
+  oracle_vjp(r, ones.data(), g);
+}
+
+void oracle_jacobian(const oracle_result* r, int32_t* rows, int32_t* cols, double* vals3) {
+  int64_t c = 0;
+  for (int64_t i = 0; i < r->n; ++i)
+    for (const auto& kv : r->jac[i]) {
+      rows[c] = (int32_t)i;
+      cols[c] = kv.first;
+      vals3[3 * c + 0] = kv.second.x;
+      vals3[3 * c + 1] = kv.second.y;
+      vals3[3 * c + 2] = kv.second.z;
+      ++c;
+    }
+}
+
+void oracle_vertices(const oracle_result* r, uint8_t* in_k, uint8_t* exterior) {
+  for (int64_t i = 0; i < r->n; ++i) {
+    in_k[i] = r->vin[i];
+    exterior[i] = r->vin[i] && r->vext[i];
+  }
+}
+
+void oracle_edges(const oracle_result* r, int32_t* e2, uint8_t* exterior) {
+  for (size_t k = 0; k < r->edges.size(); ++k) {
+    e2[2 * k] = r->edges[k][0];
+    e2[2 * k + 1] = r->edges[k][1];
+    exterior[k] = r->eext[k];
+  }
+}
+
+void oracle_triangles(const oracle_result* r, int32_t* t3, uint8_t* n_tet, uint8_t* exterior) {
+  for (size_t k = 0; k < r->tris.size(); ++k) {
+    for (int c = 0; c < 3; ++c) t3[3 * k + c] = r->tris[k][c];
+    n_tet[k] = r->tnt[k];
+    exterior[k] = r->text[k];
+  }
+}
+
+void oracle_tetrahedra(const oracle_result* r, int32_t* t4) {
+  for (size_t k = 0; k < r->tets.size(); ++k)
+    for (int c = 0; c < 4; ++c) t4[4 * k + c] = r->tets[k][c];
+}
+
+double oracle_solid_angle(const double* pi, const double* pj, const double* pk, const double* pl) {
+  return solid_angle(fixed(load(pi)), fixed(load(pj)), fixed(load(pk)), fixed(load(pl))).v;
+}
+double oracle_dihedral(const double* pi, const double* pj, const double* pk, const double* pl) {
+  return dihedral(fixed(load(pi)), fixed(load(pj)), fixed(load(pk)), fixed(load(pl))).v;
+}
+double oracle_cap_area(const double* pi, double Ri, const double* pj, double Rj) {
+  return cap_area(fixed(load(pi)), Ri, fixed(load(pj)), Rj).v;
+}
+double oracle_triple_term(const double* pi, double Ri, const double* pj, double Rj, const double* pk, double Rk) {
+  return triple_term(fixed(load(pi)), Ri, fixed(load(pj)), Rj, fixed(load(pk)), Rk).v;
+}
+
+}  // extern "C"
