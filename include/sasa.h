@@ -1,0 +1,150 @@
+/*
+ * sasa.h -- C-ABI of the MI355X (gfx950) library for exact analytic solvent
+ * accessible surface area with analytic Cartesian derivatives.
+ *
+ * The library implements the dSASA method (Cao, Hummel, Wang, Simmerling,
+ * Coutsias, arXiv 2401.10462):
+ *   - every atom is a weighted point (p_i, d_i), d_i = (r_i + probe)^2
+ *     (Methods, "dSASA: an analytical method for SASA");
+ *   - the dual complex of the weighted Delaunay tetrahedrization restricted to
+ *     the balls (Steps 1 and 2; the Laguerre-intersection cells L_i cap B_i);
+ *   - its interior / exterior classification (GPU section, extraction of
+ *     exterior simplices);
+ *   - the per-atom inclusion-exclusion area of Eq. 1 with the vertex, edge and
+ *     triangle terms of Eqs. 3, 4 and 6, and the derivatives of Eqs. 2, 5, 7.
+ *
+ * Units: lengths in Angstrom, areas in A^2, gradients in A^2/A.
+ *
+ * Memory.  Every data pointer is either host or device memory, as the `mem`
+ * argument says; all pointers of one call live in the same space.  The caller
+ * owns every input and output buffer; the library neither frees nor keeps them
+ * past the call.  Device pointers are used on `hip_stream` (a hipStream_t, or
+ * NULL for the default stream); host pointers are staged through the context's
+ * device buffers and the call returns after the results are back on the host.
+ *
+ * Threads.  A context is not thread-safe: use one context per host thread or
+ * per stream slot.  Distinct contexts are independent.
+ *
+ * Errors.  Every call returns SASA_OK (0) or a negative code; no C++
+ * exception crosses this boundary.  sasa_strerror() names the code and
+ * sasa_last_error() gives the context's last message.
+ */
+#ifndef SASA_H
+#define SASA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SASA_OK = 0,
+  SASA_E_INVAL = -1,    /* bad argument: n < 0, NaN/Inf coordinate, radius <= 0, probe < 0, NULL pointer */
+  SASA_E_NOMEM = -2,    /* device allocation failed */
+  SASA_E_DEVICE = -3,   /* HIP runtime error; the context should be destroyed */
+  SASA_E_STATE = -4,    /* backward / export without a preceding compute on this context */
+  SASA_E_CAPACITY = -5  /* an atom has more overlapping neighbours or cell vertices than the
+                           kernels hold (see sasa_capacity) */
+};
+
+typedef enum { SASA_FP64 = 0, SASA_MIXED = 1 } sasa_precision;
+/* SASA_FP64 : every step in double precision.
+ * SASA_MIXED: the tetrahedrization predicates and all accumulations in double,
+ *             the per-simplex area terms and their derivatives in single
+ *             precision (Eqs. 3-7 evaluated in float). */
+
+typedef enum { SASA_MEM_HOST = 0, SASA_MEM_DEVICE = 1 } sasa_mem;
+
+enum {
+  SASA_FLAG_ASYNC = 1u /* device-pointer calls return without synchronising the stream; capacity
+                          overflow and input errors are then reported by the next sasa_diagnostics */
+};
+
+typedef struct {
+  int32_t device;       /* HIP device ordinal */
+  int32_t precision;    /* sasa_precision */
+  int64_t max_atoms;    /* optional size hint for the first allocation (0: grow on demand) */
+  uint32_t flags;       /* SASA_FLAG_* */
+  uint32_t reserved;
+} sasa_options;
+
+/* Create a context on opt->device (NULL opt: device 0, FP64, synchronous). */
+int sasa_create(const sasa_options* opt, void** ctx_out);
+void sasa_destroy(void* ctx);
+
+/*
+ * Per-atom SASA of one molecule and the gradient of the molecular SASA.
+ *   n       number of atoms (0 is allowed and returns at once)
+ *   xyz     n*3 doubles, row-major (x0 y0 z0 x1 ...)
+ *   radii   n doubles, van der Waals radii > 0
+ *   probe   probe radius >= 0 (1.4 A in the paper)
+ *   area    n doubles out: A_i, the exposed area of sphere i (0 for buried or
+ *           hidden atoms); may be NULL
+ *   dA_dx   n*3 doubles out: d(sum_i A_i)/dp_m; may be NULL
+ * The context keeps the dual complex K of this call (indices only) for
+ * sasa_backward and sasa_complex_export.
+ */
+int sasa_compute(void* ctx, int64_t n, const double* xyz, const double* radii, double probe,
+                 double* area, double* dA_dx, int32_t mem, void* hip_stream);
+
+/*
+ * Many molecules in one launch sequence.  Molecule k holds atoms
+ * offsets[k] .. offsets[k+1]-1 of xyz / radii / area / dA_dx (offsets has
+ * nmol+1 non-decreasing entries, offsets[0] = 0).  Atoms of different molecules
+ * never interact; every per-atom result equals the one sasa_compute gives for
+ * that molecule alone.
+ */
+int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const double* xyz,
+                       const double* radii, double probe, double* area, double* dA_dx,
+                       int32_t mem, void* hip_stream);
+
+/*
+ * Vector-Jacobian product of the last compute: dL_dx[m] = sum_i dL_dA[i] dA_i/dp_m
+ * (n*3 doubles).  Recomputes the simplex geometry from the kept complex and the
+ * coordinates of that compute; the coordinates are the context's own copy, so the
+ * caller's input buffers may have changed.  SASA_E_STATE without a kept compute.
+ */
+int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream);
+
+/*
+ * Sizes of the kept complex: counts[0..7] = vertices in K, edges, triangles,
+ * tetrahedra, exterior vertices, exterior edges, exterior triangles, atoms.
+ */
+int sasa_complex_counts(void* ctx, int64_t counts[8]);
+
+/*
+ * Copy the kept complex to host arrays sized by sasa_complex_counts: each
+ * simplex once, vertex indices ascending inside a tuple (batch-global atom
+ * indices), in no particular order between tuples.
+ *   edges (E*2), tris (T*3), tri_ntet (T: number of K-tetrahedra on the
+ *   triangle), tets (Q*4), vert_flags (n: bit0 in K, bit1 exterior).
+ * Any pointer may be NULL to skip that list.
+ */
+int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
+                        uint8_t* vert_flags);
+
+/* Diagnostics of the last call (fills as many bytes as given, up to the struct). */
+typedef struct {
+  int64_t n_atoms;
+  int64_t n_mol;
+  int64_t max_neighbours;     /* largest overlapping-neighbour count of any atom */
+  int64_t max_cell_vertices;  /* largest polytope size met while clipping */
+  int64_t near_ties;          /* decisions with |margin| < 1e-9 A^2 (topology may then be ambiguous) */
+  int64_t lost_pairs;         /* K-edges seen from one side only (near-degenerate inputs) */
+  int64_t capacity_retries;   /* star storage regrown and recomputed */
+  int64_t input_errors;       /* NaN/Inf coordinates or radii <= 0 seen by the device */
+  int64_t overflow;           /* atoms beyond the kernels' neighbour / vertex capacity */
+  double ms_total;            /* wall time of the last synchronous call */
+} sasa_diag;
+int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
+
+/* Fixed per-atom kernel capacities: [0] overlapping neighbours, [1] cell vertices. */
+void sasa_capacity(int64_t caps[2]);
+
+const char* sasa_strerror(int32_t code);
+const char* sasa_last_error(void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

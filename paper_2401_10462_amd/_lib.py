@@ -1,0 +1,187 @@
+"""ctypes binding of the C-ABI in include/sasa.h (argument marshalling only).
+
+The names mirror the C entry points.  Arrays may be torch tensors on a HIP
+device (passed by data pointer on torch's current stream) or host numpy arrays.
+There is no CPU fallback: if the HIP library is missing, loading fails.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsasa_hip.so")
+
+SASA_OK = 0
+SASA_E_INVAL = -1
+SASA_E_NOMEM = -2
+SASA_E_DEVICE = -3
+SASA_E_STATE = -4
+SASA_E_CAPACITY = -5
+SASA_FP64 = 0
+SASA_MIXED = 1
+SASA_MEM_HOST = 0
+SASA_MEM_DEVICE = 1
+SASA_FLAG_ASYNC = 1
+
+# every entry point of include/sasa.h
+EXPORTS = (
+    "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_backward",
+    "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_capacity",
+    "sasa_strerror", "sasa_last_error",
+)
+
+
+class SasaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class sasa_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_atoms", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class sasa_diag(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
+        "capacity_retries", "input_errors", "overflow")] + [("ms_total", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2401_10462_amd/build.py "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.sasa_create.argtypes = [ctypes.POINTER(sasa_options), ctypes.POINTER(P)]
+    L.sasa_destroy.argtypes = [P]
+    L.sasa_destroy.restype = None
+    L.sasa_compute.argtypes = [P, I64, P, P, D, P, P, I32, P]
+    L.sasa_compute_batch.argtypes = [P, I32, P, P, P, D, P, P, I32, P]
+    L.sasa_backward.argtypes = [P, P, P, I32, P]
+    L.sasa_complex_counts.argtypes = [P, P]
+    L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
+    L.sasa_diagnostics.argtypes = [P, ctypes.POINTER(sasa_diag), I64]
+    L.sasa_capacity.argtypes = [P]
+    L.sasa_capacity.restype = None
+    L.sasa_strerror.argtypes = [I32]
+    L.sasa_strerror.restype = ctypes.c_char_p
+    L.sasa_last_error.argtypes = [P]
+    L.sasa_last_error.restype = ctypes.c_char_p
+    for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_backward", "sasa_complex_counts",
+                 "sasa_complex_export", "sasa_diagnostics"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc, ctx=None):
+    if rc != SASA_OK:
+        L = load()
+        msg = L.sasa_last_error(ctx).decode() if ctx is not None else L.sasa_strerror(rc).decode()
+        raise SasaError(rc, msg or L.sasa_strerror(rc).decode())
+    return rc
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def ptr(a):
+    """Raw pointer of a contiguous numpy array / torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def mem_of(*arrays):
+    """SASA_MEM_DEVICE if the arrays are HIP tensors, SASA_MEM_HOST for numpy."""
+    dev = [(_is_torch(a) and a.is_cuda) for a in arrays if a is not None]
+    if any(dev) and not all(dev):
+        raise ValueError("all arrays of one call must be in the same memory space")
+    return SASA_MEM_DEVICE if dev and all(dev) else SASA_MEM_HOST
+
+
+def stream_of(arrays):
+    for a in arrays:
+        if a is not None and _is_torch(a) and a.is_cuda:
+            import torch
+            return ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream)
+    return None
+
+
+# --------------------------------------------------------------- C names
+def sasa_create(device=0, precision=SASA_FP64, max_atoms=0, flags=0):
+    L = load()
+    opt = sasa_options(device, precision, max_atoms, flags, 0)
+    h = ctypes.c_void_p()
+    check(L.sasa_create(ctypes.byref(opt), ctypes.byref(h)))
+    return h
+
+
+def sasa_destroy(ctx):
+    load().sasa_destroy(ctx)
+
+
+def sasa_compute(ctx, n, xyz, radii, probe, area, dA_dx, mem=None, stream=None):
+    arrs = (xyz, radii, area, dA_dx)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_compute(ctx, int(n), ptr(xyz), ptr(radii), float(probe), ptr(area), ptr(dA_dx),
+                                     mem, stream), ctx)
+
+
+def sasa_compute_batch(ctx, offsets, xyz, radii, probe, area, dA_dx, mem=None, stream=None):
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    arrs = (xyz, radii, area, dA_dx)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_compute_batch(ctx, len(off) - 1, ctypes.c_void_p(off.ctypes.data), ptr(xyz),
+                                           ptr(radii), float(probe), ptr(area), ptr(dA_dx), mem, stream), ctx)
+
+
+def sasa_backward(ctx, dL_dA, dL_dx, mem=None, stream=None):
+    arrs = (dL_dA, dL_dx)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_backward(ctx, ptr(dL_dA), ptr(dL_dx), mem, stream), ctx)
+
+
+def sasa_complex_counts(ctx):
+    c = np.zeros(8, np.int64)
+    check(load().sasa_complex_counts(ctx, ctypes.c_void_p(c.ctypes.data)), ctx)
+    return c
+
+
+def sasa_complex_export(ctx):
+    c = sasa_complex_counts(ctx)
+    e = np.zeros((c[1], 2), np.int32)
+    t = np.zeros((c[2], 3), np.int32)
+    nt = np.zeros(c[2], np.uint8)
+    q = np.zeros((c[3], 4), np.int32)
+    vf = np.zeros(c[7], np.uint8)
+    check(load().sasa_complex_export(ctx, ptr(e), ptr(t), ptr(nt), ptr(q), ptr(vf)), ctx)
+    return e, t, nt, q, vf
+
+
+def sasa_diagnostics(ctx):
+    d = sasa_diag()
+    check(load().sasa_diagnostics(ctx, ctypes.byref(d), ctypes.sizeof(d)), ctx)
+    return {f: getattr(d, f) for f, _ in d._fields_}
+
+
+def sasa_capacity():
+    c = np.zeros(2, np.int64)
+    load().sasa_capacity(ctypes.c_void_p(c.ctypes.data))
+    return c

@@ -1,0 +1,81 @@
+"""Context object over the C-ABI: exact per-atom SASA and its gradient on one GPU."""
+import numpy as np
+
+from . import _lib
+
+
+class SasaContext:
+    """One library context (device buffers, the complex kept from the last call).
+
+    precision: "fp64" (everything in double) or "mixed" (area terms in float,
+    tetrahedrization predicates and accumulation in double).
+    """
+
+    def __init__(self, device=0, precision="fp64", max_atoms=0, async_calls=False):
+        prec = {"fp64": _lib.SASA_FP64, "mixed": _lib.SASA_MIXED}[precision]
+        self.precision = precision
+        self.device = device
+        self._h = _lib.sasa_create(device, prec, max_atoms, _lib.SASA_FLAG_ASYNC if async_calls else 0)
+
+    def close(self):
+        if self._h is not None:
+            _lib.sasa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- compute
+    def compute(self, xyz, radii, probe=1.4, grad=True):
+        """Per-atom areas (n,) and d(sum A)/dx (n, 3); torch HIP tensors or numpy arrays."""
+        n = xyz.shape[0]
+        area, dadx = self._outputs(xyz, n, grad)
+        _lib.sasa_compute(self._h, n, _c(xyz), _c(radii), probe, area, dadx)
+        return area, dadx
+
+    def compute_batch(self, offsets, xyz, radii, probe=1.4, grad=True):
+        """Many molecules (atoms offsets[k]..offsets[k+1]-1) in one launch sequence."""
+        n = xyz.shape[0]
+        area, dadx = self._outputs(xyz, n, grad)
+        _lib.sasa_compute_batch(self._h, offsets, _c(xyz), _c(radii), probe, area, dadx)
+        return area, dadx
+
+    def backward(self, dL_dA):
+        """sum_i dL_dA[i] dA_i/dx of the last compute (geometry recomputed)."""
+        n = dL_dA.shape[0]
+        out = _like(dL_dA, (n, 3))
+        _lib.sasa_backward(self._h, _c(dL_dA), out)
+        return out
+
+    def counts(self):
+        c = _lib.sasa_complex_counts(self._h)
+        keys = ("vertices", "edges", "triangles", "tetrahedra", "ext_vertices", "ext_edges", "ext_triangles", "atoms")
+        return dict(zip(keys, (int(v) for v in c)))
+
+    def export(self):
+        """The kept complex: edges, triangles, n_tet per triangle, tetrahedra, vertex flags."""
+        return _lib.sasa_complex_export(self._h)
+
+    def diagnostics(self):
+        return _lib.sasa_diagnostics(self._h)
+
+    @staticmethod
+    def _outputs(xyz, n, grad):
+        return _like(xyz, (n,)), (_like(xyz, (n, 3)) if grad else None)
+
+
+def _c(a):
+    if type(a).__module__.startswith("torch"):
+        import torch
+        return a.detach().to(torch.float64).contiguous()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _like(a, shape):
+    if type(a).__module__.startswith("torch"):
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device=a.device)
+    return np.empty(shape, dtype=np.float64)

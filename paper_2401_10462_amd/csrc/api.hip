@@ -1,0 +1,441 @@
+// api.hip -- host side of the C-ABI declared in include/sasa.h.
+//
+// A context owns its device buffers (grown on demand, never shrunk), a small
+// pinned block for the device counters, and the complex kept from its last
+// compute.  All work of a call is enqueued on the caller's stream; synchronous
+// calls end with one stream synchronisation that also brings the counters
+// (errors, capacity, diagnostics) back.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sasa.h"
+#include "sasa_internal.h"
+
+using namespace sasa;
+
+namespace {
+
+struct Ctx {
+  int device = 0;
+  int precision = SASA_FP64;
+  uint32_t flags = 0;
+  int64_t cap_n = 0;
+  unsigned cap_hb = 0;
+  int cap_mol = 0;
+  Bufs b;                 // device pointers (capacity-sized)
+  double* xyz_d = nullptr;  // staging of host inputs
+  double* rad_d = nullptr;
+  double* area_d = nullptr;
+  double* out_d = nullptr;  // n*3
+  double* u_d = nullptr;
+  int64_t* off_d = nullptr;
+  int64_t* off_h = nullptr;  // pinned
+  unsigned long long* ctr_h = nullptr;  // pinned copy of the counters
+  // export buffers
+  int64_t ex_cap_e = 0, ex_cap_t = 0, ex_cap_q = 0;
+  // kept state
+  bool kept = false;
+  int64_t n = 0;
+  int nmol = 0;
+  double probe = 0;
+  bool pending = false;  // an async call whose counters were not read yet
+  sasa_diag diag{};
+  std::string err;
+};
+
+thread_local std::string g_err;
+
+int fail(Ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? SASA_E_NOMEM : SASA_E_DEVICE,        \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    }                                                                                   \
+  } while (0)
+
+template <typename T>
+hipError_t grow(T** p, size_t count) {
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  return count ? hipMalloc((void**)p, count * sizeof(T)) : hipSuccess;
+}
+
+unsigned pow2_at_least(int64_t v) {
+  unsigned p = 1024;
+  while ((int64_t)p < v) p <<= 1;
+  return p;
+}
+
+int ensure(Ctx* c, int64_t n, int nmol) {
+  Bufs& b = c->b;
+  if (n > c->cap_n) {
+    const int64_t cap = std::max<int64_t>(n, c->cap_n + c->cap_n / 2);
+    HIP_TRY(c, grow(&b.pos, cap));
+    HIP_TRY(c, grow(&b.mol, cap));
+    HIP_TRY(c, grow(&b.bucket, cap));
+    HIP_TRY(c, grow(&b.sorted, cap));
+    HIP_TRY(c, grow(&b.spos, cap));
+    HIP_TRY(c, grow(&b.smol, cap));
+    HIP_TRY(c, grow(&b.vflag, cap));
+    HIP_TRY(c, grow(&b.kn_cnt, cap));
+    HIP_TRY(c, grow(&b.knbr, cap * KN_CAP));
+    HIP_TRY(c, grow(&b.kn_ext, cap));
+    HIP_TRY(c, grow(&b.kt_cnt, cap));
+    HIP_TRY(c, grow(&b.ktet, cap * KT_CAP));
+    HIP_TRY(c, grow(&b.ktr_cnt, cap));
+    HIP_TRY(c, grow(&b.ktri, cap * KTR_CAP));
+    HIP_TRY(c, grow(&c->area_d, cap));
+    HIP_TRY(c, grow(&b.rows, cap * ROW * 3));
+    HIP_TRY(c, grow(&c->xyz_d, cap * 3));
+    HIP_TRY(c, grow(&c->rad_d, cap));
+    HIP_TRY(c, grow(&c->out_d, cap * 3));
+    HIP_TRY(c, grow(&c->u_d, cap));
+    c->cap_n = cap;
+  }
+  const unsigned hb = pow2_at_least(2 * std::max<int64_t>(n, 1));
+  if (hb > c->cap_hb) {
+    HIP_TRY(c, grow(&b.cnt, hb));
+    HIP_TRY(c, grow(&b.start, (size_t)hb + 1));
+    HIP_TRY(c, grow(&b.scan_tmp, (size_t)scan_blocks(hb) + 1));
+    c->cap_hb = hb;
+  }
+  b.hb_mask = hb - 1;
+  if (nmol + 1 > c->cap_mol) {
+    const int cap = std::max(nmol + 1, 2 * c->cap_mol);
+    HIP_TRY(c, grow(&c->off_d, cap));
+    if (c->off_h) HIP_TRY(c, hipHostFree(c->off_h));
+    c->off_h = nullptr;
+    HIP_TRY(c, hipHostMalloc((void**)&c->off_h, cap * sizeof(int64_t)));
+    c->cap_mol = cap;
+  }
+  return SASA_OK;
+}
+
+bool host_inputs_ok(int64_t n, const double* xyz, const double* radii) {
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return false;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(radii[i] > 0.0) || !std::isfinite(radii[i])) return false;
+  return true;
+}
+
+int read_counters(Ctx* c, hipStream_t s) {
+  HIP_TRY(c, hipMemcpyAsync(c->ctr_h, c->b.ctr, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->pending = false;
+  const unsigned long long* h = c->ctr_h;
+  c->diag.max_neighbours = (int64_t)h[C_MAX_NB];
+  c->diag.max_cell_vertices = (int64_t)h[C_MAX_V];
+  c->diag.near_ties = (int64_t)h[C_NEAR_TIE];
+  c->diag.lost_pairs = (int64_t)h[C_LOST_PAIR];
+  c->diag.input_errors = (int64_t)h[C_BAD_INPUT];
+  c->diag.overflow = (int64_t)h[C_OVERFLOW];
+  if (h[C_BAD_INPUT]) {
+    c->kept = false;
+    return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
+  }
+  if (h[C_OVERFLOW]) {
+    c->kept = false;
+    return fail(c, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
+  }
+  return SASA_OK;
+}
+
+int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const double* radii, double probe,
+        double* area, double* dA_dx, int mem, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (nmol < 0 || !offsets) return fail(c, SASA_E_INVAL, "nmol < 0 or offsets == NULL");
+  if (!(probe >= 0.0) || !std::isfinite(probe)) return fail(c, SASA_E_INVAL, "probe must be finite and >= 0");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (offsets[0] != 0) return fail(c, SASA_E_INVAL, "offsets[0] must be 0");
+  for (int k = 0; k < nmol; ++k)
+    if (offsets[k + 1] < offsets[k]) return fail(c, SASA_E_INVAL, "offsets must be non-decreasing");
+  const int64_t n = offsets[nmol];
+  if (n > (int64_t)1 << 30) return fail(c, SASA_E_INVAL, "too many atoms");
+  if (n > 0 && (!xyz || !radii)) return fail(c, SASA_E_INVAL, "xyz / radii must not be NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (c->pending) {
+    int rc = read_counters(c, s);
+    (void)rc;
+  }
+  c->kept = false;
+  if (mem == SASA_MEM_HOST && n > 0 && !host_inputs_ok(n, xyz, radii))
+    return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
+  int rc = ensure(c, n, nmol);
+  if (rc) return rc;
+  Bufs b = c->b;
+  b.n = (int)n;
+  b.nmol = std::max(nmol, 1);
+  b.probe = probe;
+  b.export_on = 0;
+  std::memcpy(c->off_h, offsets, (size_t)(nmol + 1) * sizeof(int64_t));
+  if (nmol == 0) c->off_h[1] = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->off_d, c->off_h, (size_t)(b.nmol + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  b.offsets = c->off_d;
+  if (mem == SASA_MEM_HOST) {
+    if (n) {
+      HIP_TRY(c, hipMemcpyAsync(c->xyz_d, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_TRY(c, hipMemcpyAsync(c->rad_d, radii, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    b.xyz = c->xyz_d;
+    b.radii = c->rad_d;
+  } else {
+    b.xyz = xyz;
+    b.radii = radii;
+  }
+  b.area = (mem == SASA_MEM_DEVICE && area) ? area : c->area_d;
+  double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
+  launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
+  launch_zero(b.cnt, (size_t)(b.hb_mask + 1) * sizeof(int), s);
+  launch_prep(b, s);
+  launch_buckets(b, s);
+  launch_scan(b, s);
+  launch_scatter(b, s);
+  launch_star(b, s);
+  launch_terms(b, c->precision, dA_dx != nullptr, s);
+  if (dA_dx) launch_gather(b, nullptr, out, s);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == SASA_MEM_HOST && n) {
+    if (area) HIP_TRY(c, hipMemcpyAsync(area, b.area, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (dA_dx) HIP_TRY(c, hipMemcpyAsync(dA_dx, out, (size_t)n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  c->n = n;
+  c->nmol = nmol;
+  c->probe = probe;
+  c->diag.n_atoms = n;
+  c->diag.n_mol = nmol;
+  const bool async = (c->flags & SASA_FLAG_ASYNC) && mem == SASA_MEM_DEVICE;
+  c->kept = true;
+  if (async) {
+    c->pending = true;
+    return SASA_OK;
+  }
+  rc = read_counters(c, s);
+  c->diag.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sasa_create(const sasa_options* opt, void** ctx_out) {
+  if (!ctx_out) return fail(nullptr, SASA_E_INVAL, "ctx_out == NULL");
+  *ctx_out = nullptr;
+  auto* c = new (std::nothrow) Ctx;
+  if (!c) return fail(nullptr, SASA_E_NOMEM, "host allocation failed");
+  if (opt) {
+    c->device = opt->device;
+    c->precision = opt->precision;
+    c->flags = opt->flags;
+    if (c->precision != SASA_FP64 && c->precision != SASA_MIXED) {
+      delete c;
+      return fail(nullptr, SASA_E_INVAL, "precision must be SASA_FP64 or SASA_MIXED");
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
+    delete c;
+    return fail(nullptr, SASA_E_DEVICE, "no such HIP device");
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->b.ctr, C_COUNT * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->ctr_h, C_COUNT * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    sasa_destroy(c);
+    return fail(nullptr, SASA_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
+  }
+  std::memset(c->ctr_h, 0, C_COUNT * sizeof(unsigned long long));
+  if (opt && opt->max_atoms > 0) {
+    int rc = ensure(c, opt->max_atoms, 1);
+    if (rc) {
+      sasa_destroy(c);
+      return rc;
+    }
+  }
+  *ctx_out = c;
+  return SASA_OK;
+}
+
+void sasa_destroy(void* ctx) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  Bufs& b = c->b;
+  void* dev[] = {b.pos,  b.mol,   b.bucket,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
+                 b.smol, b.vflag, b.kn_cnt,   b.knbr,     b.kn_ext, b.kt_cnt,   b.ktet,   b.ktr_cnt,
+                 b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
+                 c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
+  for (void* p : dev)
+    if (p) hipFree(p);
+  if (c->off_h) hipHostFree(c->off_h);
+  if (c->ctr_h) hipHostFree(c->ctr_h);
+  delete c;
+}
+
+int sasa_compute(void* ctx, int64_t n, const double* xyz, const double* radii, double probe, double* area,
+                 double* dA_dx, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (n < 0) return fail(c, SASA_E_INVAL, "n < 0");
+  const int64_t off[2] = {0, n};
+  return run(c, 1, off, xyz, radii, probe, area, dA_dx, mem, (hipStream_t)hip_stream);
+}
+
+int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const double* xyz, const double* radii,
+                       double probe, double* area, double* dA_dx, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  return run(c, nmol, offsets, xyz, radii, probe, area, dA_dx, mem, (hipStream_t)hip_stream);
+}
+
+int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (c->n > 0 && (!dL_dA || !dL_dx)) return fail(c, SASA_E_INVAL, "dL_dA / dL_dx must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  b.area = c->area_d;
+  const double* u = dL_dA;
+  double* out = dL_dx;
+  if (mem == SASA_MEM_HOST && c->n) {
+    HIP_TRY(c, hipMemcpyAsync(c->u_d, dL_dA, (size_t)c->n * sizeof(double), hipMemcpyHostToDevice, s));
+    u = c->u_d;
+    out = c->out_d;
+  }
+  launch_terms(b, c->precision, 1, s);
+  launch_gather(b, u, out, s);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == SASA_MEM_HOST && c->n) {
+    HIP_TRY(c, hipMemcpyAsync(dL_dx, out, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  } else if (!(c->flags & SASA_FLAG_ASYNC)) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return SASA_OK;
+}
+
+int sasa_complex_counts(void* ctx, int64_t counts[8]) {
+  auto* c = (Ctx*)ctx;
+  if (!c || !counts) return fail(c, SASA_E_INVAL, "NULL argument");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (c->pending) {
+    int rc = read_counters(c, nullptr);
+    if (rc) return rc;
+  }
+  const unsigned long long* h = c->ctr_h;
+  counts[0] = (int64_t)h[C_VERT];
+  counts[1] = (int64_t)h[C_EDGE];
+  counts[2] = (int64_t)h[C_TRI];
+  counts[3] = (int64_t)h[C_TET];
+  counts[4] = (int64_t)h[C_EXT_VERT];
+  counts[5] = (int64_t)h[C_EXT_EDGE];
+  counts[6] = (int64_t)h[C_EXT_TRI];
+  counts[7] = c->n;
+  return SASA_OK;
+}
+
+int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
+                        uint8_t* vert_flags) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  int64_t cnt[8];
+  int rc = sasa_complex_counts(ctx, cnt);
+  if (rc) return rc;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Bufs& B = c->b;
+  if (cnt[1] > c->ex_cap_e) {
+    HIP_TRY(c, grow(&B.ex_edges, (size_t)cnt[1] * 2));
+    c->ex_cap_e = cnt[1];
+  }
+  if (cnt[2] > c->ex_cap_t) {
+    HIP_TRY(c, grow(&B.ex_tris, (size_t)cnt[2] * 3));
+    HIP_TRY(c, grow(&B.ex_ntet, (size_t)cnt[2]));
+    c->ex_cap_t = cnt[2];
+  }
+  if (cnt[3] > c->ex_cap_q) {
+    HIP_TRY(c, grow(&B.ex_tets, (size_t)cnt[3] * 4));
+    c->ex_cap_q = cnt[3];
+  }
+  // re-run the (deterministic) star kernel with export on; the cell list of the
+  // last compute is still in place
+  Bufs b = B;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  b.export_on = 1;
+  b.ex_cap_e = c->ex_cap_e;
+  b.ex_cap_t = c->ex_cap_t;
+  b.ex_cap_q = c->ex_cap_q;
+  hipStream_t s = nullptr;
+  // keep R_max (needed for the cell size), clear everything else
+  unsigned long long rmax_bits = c->ctr_h[C_RMAX_BITS];
+  launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
+  HIP_TRY(c, hipMemcpyAsync(b.ctr + C_RMAX_BITS, &rmax_bits, sizeof(rmax_bits), hipMemcpyHostToDevice, s));
+  launch_star(b, s);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));
+  rc = read_counters(c, s);
+  if (rc) return rc;
+  if (edges && cnt[1]) HIP_TRY(c, hipMemcpy(edges, b.ex_edges, (size_t)cnt[1] * 2 * sizeof(int), hipMemcpyDeviceToHost));
+  if (tris && cnt[2]) HIP_TRY(c, hipMemcpy(tris, b.ex_tris, (size_t)cnt[2] * 3 * sizeof(int), hipMemcpyDeviceToHost));
+  if (tri_ntet && cnt[2]) HIP_TRY(c, hipMemcpy(tri_ntet, b.ex_ntet, (size_t)cnt[2], hipMemcpyDeviceToHost));
+  if (tets && cnt[3]) HIP_TRY(c, hipMemcpy(tets, b.ex_tets, (size_t)cnt[3] * 4 * sizeof(int), hipMemcpyDeviceToHost));
+  if (vert_flags && c->n) HIP_TRY(c, hipMemcpy(vert_flags, b.vflag, (size_t)c->n, hipMemcpyDeviceToHost));
+  return SASA_OK;
+}
+
+int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
+  auto* c = (Ctx*)ctx;
+  if (!c || !out || size < 0) return fail(c, SASA_E_INVAL, "NULL argument");
+  int rc = SASA_OK;
+  if (c->pending) rc = read_counters(c, nullptr);
+  std::memcpy(out, &c->diag, (size_t)std::min<int64_t>(size, sizeof(sasa_diag)));
+  return rc;
+}
+
+void sasa_capacity(int64_t caps[2]) {
+  if (!caps) return;
+  caps[0] = NB_CAP;
+  caps[1] = V_CAP;
+}
+
+const char* sasa_strerror(int32_t code) {
+  switch (code) {
+    case SASA_OK: return "ok";
+    case SASA_E_INVAL: return "invalid argument";
+    case SASA_E_NOMEM: return "out of device memory";
+    case SASA_E_DEVICE: return "HIP device error";
+    case SASA_E_STATE: return "no kept compute on this context";
+    case SASA_E_CAPACITY: return "per-atom capacity exceeded";
+  }
+  return "unknown error";
+}
+
+const char* sasa_last_error(void* ctx) {
+  auto* c = (Ctx*)ctx;
+  return c ? c->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"

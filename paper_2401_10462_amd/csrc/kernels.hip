@@ -1,0 +1,1055 @@
+// kernels.hip -- HIP kernels (gfx950, wave64) of the exact analytic SASA path.
+//
+// Pipeline for one batch of molecules (each molecule is one segment of atoms):
+//   k_prep      weights R_i = r_i + probe, SoA copy, molecule ids, input checks
+//   k_buckets   spatial hash of every atom's cell (cell side 2 R_max), counts
+//   k_scan*     exclusive scan of the bucket counts
+//   k_scatter   atoms grouped by bucket; positions copied in that order so that
+//               neighbour loads are coalesced
+//   k_star      one wavefront per atom: its power (Laguerre) cell clipped by the
+//               radical planes of its overlapping neighbours, restricted to its
+//               ball; yields the atom's star in the dual complex K, the
+//               exterior classification, and the owned simplex counts
+//   k_terms     one wavefront per exterior atom: Eq. 1 area from the star and,
+//               on request, the gradient blocks dA_i/dp_m of Eq. 2
+//   k_gather    one thread per atom: segmented sum over its K-neighbours of
+//               u_i dA_i/dp_m (deterministic order)
+#include <hip/hip_runtime.h>
+
+#include "sasa_internal.h"
+
+namespace sasa {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kNearTie = 1e-9;  // A^2
+
+__device__ inline int prefix_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ inline unsigned cell_hash(int mol, int cx, int cy, int cz, unsigned mask) {
+  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
+               (unsigned)mol * 2654435761u;
+  h ^= h >> 13;
+  h *= 0x5bd1e995u;
+  h ^= h >> 15;
+  return h & mask;
+}
+
+__device__ inline int cell_coord(double x, double inv_h) {
+  double c = floor(x * inv_h);
+  c = fmin(fmax(c, -1.0e9), 1.0e9);  // NaN -> -1e9 (fmax returns the non-NaN operand)
+  return (int)c;
+}
+
+__device__ inline double rmax_of(const unsigned long long* ctr) {
+  return __longlong_as_double((long long)ctr[C_RMAX_BITS]);
+}
+
+// ------------------------------------------------------------------ prep
+__global__ void k_prep(Bufs b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const double x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
+  double r = b.radii[i];
+  const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0;
+  if (!ok) {
+    atomicAdd(&b.ctr[C_BAD_INPUT], 1ull);
+    r = 1.0;
+  }
+  const double R = r + b.probe;
+  b.pos[i] = make_double4(ok ? x : 0.0, ok ? y : 0.0, ok ? z : 0.0, R);
+  // molecule id: largest k with offsets[k] <= i
+  int lo = 0, hi = b.nmol - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.offsets[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  b.mol[i] = lo;
+  atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(R));
+}
+
+__global__ void k_buckets(Bufs b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const double inv_h = 1.0 / (2.0 * rmax_of(b.ctr));
+  const double4 p = b.pos[i];
+  const unsigned k = cell_hash(b.mol[i], cell_coord(p.x, inv_h), cell_coord(p.y, inv_h), cell_coord(p.z, inv_h),
+                               b.hb_mask);
+  b.bucket[i] = (int)k;
+  atomicAdd(&b.cnt[k], 1);
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_E = 2 * SCAN_T;
+
+__device__ int block_scan2(int a0, int a1, int* lds, int* total) {
+  const int t = threadIdx.x;
+  const int s = a0 + a1;
+  lds[t] = s;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    const int v = t >= off ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += v;
+    __syncthreads();
+  }
+  const int incl = lds[t];
+  *total = lds[SCAN_T - 1];
+  __syncthreads();
+  return incl - s;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan1(const int* cnt, int* start, int* sums, int hb) {
+  __shared__ int lds[SCAN_T];
+  const int base = blockIdx.x * SCAN_E + 2 * threadIdx.x;
+  const int a0 = base < hb ? cnt[base] : 0;
+  const int a1 = base + 1 < hb ? cnt[base + 1] : 0;
+  int total;
+  const int ex = block_scan2(a0, a1, lds, &total);
+  if (base < hb) start[base] = ex;
+  if (base + 1 < hb) start[base + 1] = ex + a0;
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan2(int* sums, int nb, int* start, int hb) {
+  __shared__ int lds[SCAN_T];
+  const int base = 2 * threadIdx.x;
+  const int a0 = base < nb ? sums[base] : 0;
+  const int a1 = base + 1 < nb ? sums[base + 1] : 0;
+  int total;
+  const int ex = block_scan2(a0, a1, lds, &total);
+  if (base < nb) sums[base] = ex;
+  if (base + 1 < nb) sums[base + 1] = ex + a0;
+  if (threadIdx.x == 0) start[hb] = total;
+}
+
+__global__ void k_scan3(int* start, const int* sums, int hb) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < hb) start[k] += sums[k / SCAN_E];
+}
+
+__global__ void k_scatter(Bufs b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int k = b.bucket[i];
+  const int slot = b.start[k] + atomicSub(&b.cnt[k], 1) - 1;
+  b.sorted[slot] = i;
+  b.spos[slot] = b.pos[i];
+  b.smol[slot] = b.mol[i];
+}
+
+// ------------------------------------------------------------------ star
+// Plane ids inside one star: 0..5 are the faces of the starting cube
+// (+x, -x, +y, -y, +z, -z), 6 + q is the radical plane of neighbour slot q.
+// A plane keeps n . x <= b (x relative to p_i).  For neighbour q with
+// a = p_q - p_i: pi_i(x) <= pi_q(x)  <=>  2 a . x <= |a|^2 - w_q + w_i.
+// Cell vertices are simple (three planes each), stored as the three plane ids
+// packed 10 bits apiece in ascending order; two vertices are joined by a cell
+// edge iff they share two plane ids.
+struct Pl {
+  double x, y, z, b;
+};
+
+__device__ inline unsigned pack3(unsigned a, unsigned b, unsigned c) {
+  // sort three ids ascending
+  unsigned t;
+  if (a > b) t = a, a = b, b = t;
+  if (b > c) t = b, b = c, c = t;
+  if (a > b) t = a, a = b, b = t;
+  return a | (b << 10) | (c << 20);
+}
+__device__ inline unsigned pid0(unsigned p) { return p & 1023u; }
+__device__ inline unsigned pid1(unsigned p) { return (p >> 10) & 1023u; }
+__device__ inline unsigned pid2(unsigned p) { return p >> 20; }
+__device__ inline bool has2(unsigned p, unsigned a, unsigned b) {
+  const unsigned x = pid0(p), y = pid1(p), z = pid2(p);
+  return (x == a || y == a || z == a) && (x == b || y == b || z == b);
+}
+
+struct StarLds {
+  int idx[NB_CAP];     // neighbour global ids, ascending
+  double nx[NB_CAP], ny[NB_CAP], nz[NB_CAP], nb[NB_CAP];  // plane n = 2a, offset b
+  int order[NB_CAP];   // clipping order (nearest plane first)
+  double key[NB_CAP];
+  unsigned sflag[NB_CAP];  // per-slot flags (facet present, K-triangles, K-edge ...)
+  int kidx[NB_CAP];        // slot -> K-neighbour index or -1
+  double vx[V_CAP], vy[V_CAP], vz[V_CAP];
+  unsigned vp[V_CAP];
+  double tx[V_CAP], ty[V_CAP], tz[V_CAP];  // staging for new vertices
+  unsigned tp[V_CAP];
+  unsigned pairs[3 * V_CAP];
+  unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
+  int bk[27];
+  int cand[NB_CAP];
+};
+
+enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
+
+__device__ inline Pl plane_of(const StarLds& L, unsigned pid, double half) {
+  if (pid < 6) {
+    const double s = (pid & 1) ? -1.0 : 1.0;
+    const unsigned ax = pid >> 1;
+    return {ax == 0 ? s : 0.0, ax == 1 ? s : 0.0, ax == 2 ? s : 0.0, half};
+  }
+  const unsigned q = pid - 6;
+  return {L.nx[q], L.ny[q], L.nz[q], L.nb[q]};
+}
+
+__device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, double& y, double& z) {
+  const double bcx = B.y * C.z - B.z * C.y, bcy = B.z * C.x - B.x * C.z, bcz = B.x * C.y - B.y * C.x;
+  const double cax = C.y * A.z - C.z * A.y, cay = C.z * A.x - C.x * A.z, caz = C.x * A.y - C.y * A.x;
+  const double abx = A.y * B.z - A.z * B.y, aby = A.z * B.x - A.x * B.z, abz = A.x * B.y - A.y * B.x;
+  const double inv = 1.0 / (A.x * bcx + A.y * bcy + A.z * bcz);
+  x = (A.b * bcx + B.b * cax + C.b * abx) * inv;
+  y = (A.b * bcy + B.b * cay + C.b * aby) * inv;
+  z = (A.b * bcz + B.b * caz + C.b * abz) * inv;
+}
+
+__global__ __launch_bounds__(64) void k_star(Bufs b) {
+  __shared__ StarLds L;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= b.n) return;
+  const double4 pi = b.pos[i];
+  const int mi = b.mol[i];
+  const double Ri = pi.w, wi = Ri * Ri;
+  const double rmax = rmax_of(b.ctr);
+  const double inv_h = 1.0 / (2.0 * rmax);
+  const int cx = cell_coord(pi.x, inv_h), cy = cell_coord(pi.y, inv_h), cz = cell_coord(pi.z, inv_h);
+
+  // ---- 1. overlapping neighbours from the 27 surrounding cells
+  if (lane < 27) {
+    const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+    L.bk[lane] = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
+  }
+  __syncthreads();
+  int nn = 0;
+  bool overflow = false;
+  for (int c = 0; c < 27; ++c) {
+    const int bk = L.bk[c];
+    bool dup = false;
+    for (int e = 0; e < c; ++e) dup |= (L.bk[e] == bk);  // buckets shared by two cells
+    if (dup) continue;
+    const int s0 = b.start[bk], s1 = b.start[bk + 1];
+    for (int base = s0; base < s1; base += 64) {
+      const int k = base + lane;
+      bool take = false;
+      int j = -1;
+      if (k < s1) {
+        j = b.sorted[k];
+        const double4 pj = b.spos[k];
+        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        const double rr = Ri + pj.w;
+        take = (j != i) && (b.smol[k] == mi) && (dx * dx + dy * dy + dz * dz < rr * rr);
+      }
+      const unsigned long long m = __ballot(take);
+      const int at = nn + prefix_below(m);
+      if (take) {
+        if (at < NB_CAP) L.cand[at] = j;
+      }
+      nn += __popcll(m);
+    }
+  }
+  if (nn > NB_CAP) {
+    overflow = true;
+    nn = NB_CAP;
+  }
+  __syncthreads();
+  // sort neighbours by global id (rank counting), then build the planes
+  for (int s = lane; s < nn; s += 64) {
+    const int me = L.cand[s];
+    int rank = 0;
+    for (int t = 0; t < nn; ++t) rank += (L.cand[t] < me);
+    L.idx[rank] = me;
+  }
+  __syncthreads();
+  for (int s = lane; s < nn; s += 64) {
+    const double4 pj = b.pos[L.idx[s]];
+    const double ax = pj.x - pi.x, ay = pj.y - pi.y, az = pj.z - pi.z;
+    const double a2 = ax * ax + ay * ay + az * az;
+    L.nx[s] = 2.0 * ax;
+    L.ny[s] = 2.0 * ay;
+    L.nz[s] = 2.0 * az;
+    L.nb[s] = a2 - pj.w * pj.w + wi;
+    L.key[s] = L.nb[s] / (2.0 * sqrt(a2));  // distance of the radical plane from p_i
+    L.sflag[s] = 0u;
+    L.kidx[s] = -1;
+  }
+  __syncthreads();
+  for (int s = lane; s < nn; s += 64) {
+    const double me = L.key[s];
+    int rank = 0;
+    for (int t = 0; t < nn; ++t) {
+      const double o = L.key[t];
+      rank += (o < me) || (o == me && t < s);
+    }
+    L.order[rank] = s;
+  }
+
+  // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by every plane
+  const double half = 1.1 * Ri;
+  int nv = 8;
+  if (lane < 8) {
+    const unsigned px = (lane & 1) ? 1u : 0u, py = (lane & 2) ? 3u : 2u, pz = (lane & 4) ? 5u : 4u;
+    L.vx[lane] = (lane & 1) ? -half : half;
+    L.vy[lane] = (lane & 2) ? -half : half;
+    L.vz[lane] = (lane & 4) ? -half : half;
+    L.vp[lane] = px | (py << 10) | (pz << 20);
+  }
+  __syncthreads();
+  bool empty = false;
+  int vmax = 8;
+  for (int k = 0; k < nn && !overflow; ++k) {
+    const int q = L.order[k];
+    const unsigned pid = 6u + (unsigned)q;
+    const double qx = L.nx[q], qy = L.ny[q], qz = L.nz[q], qb = L.nb[q];
+    // my vertices
+    const int v0 = lane, v1 = lane + 64;
+    double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+    unsigned p0 = 0, p1 = 0;
+    bool r0 = false, r1 = false;
+    if (v0 < nv) {
+      x0 = L.vx[v0], y0 = L.vy[v0], z0 = L.vz[v0], p0 = L.vp[v0];
+      r0 = qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
+    }
+    if (v1 < nv) {
+      x1 = L.vx[v1], y1 = L.vy[v1], z1 = L.vz[v1], p1 = L.vp[v1];
+      r1 = qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
+    }
+    const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
+    const int nr0 = __popcll(m0);
+    const int nrem = nr0 + __popcll(m1);
+    if (nrem == 0) continue;
+    if (nrem == nv) {
+      empty = true;
+      break;
+    }
+    // removed vertices list their three edges (plane pairs)
+    if (r0) {
+      const int rk = prefix_below(m0);
+      L.pairs[3 * rk + 0] = pid1(p0) | (pid2(p0) << 10);
+      L.pairs[3 * rk + 1] = pid0(p0) | (pid2(p0) << 10);
+      L.pairs[3 * rk + 2] = pid0(p0) | (pid1(p0) << 10);
+    }
+    if (r1) {
+      const int rk = nr0 + prefix_below(m1);
+      L.pairs[3 * rk + 0] = pid1(p1) | (pid2(p1) << 10);
+      L.pairs[3 * rk + 1] = pid0(p1) | (pid2(p1) << 10);
+      L.pairs[3 * rk + 2] = pid0(p1) | (pid1(p1) << 10);
+    }
+    __syncthreads();
+    // an edge with exactly one removed end crosses the plane: new vertex on it
+    const int ne = 3 * nrem;
+    int ncross = 0;
+    for (int base = 0; base < ne; base += 64) {
+      const int e = base + lane;
+      bool cross = false;
+      unsigned pr = 0;
+      if (e < ne) {
+        pr = L.pairs[e];
+        int c = 0;
+        for (int t = 0; t < ne; ++t) c += (L.pairs[t] == pr);
+        cross = (c == 1);
+      }
+      const unsigned long long cm = __ballot(cross);
+      if (cross) {
+        const int slot = ncross + prefix_below(cm);
+        if (slot < V_CAP) {
+          const unsigned a = pr & 1023u, bb = pr >> 10;
+          double x, y, z;
+          solve3(plane_of(L, a, half), plane_of(L, bb, half), Pl{qx, qy, qz, qb}, x, y, z);
+          L.tx[slot] = x;
+          L.ty[slot] = y;
+          L.tz[slot] = z;
+          L.tp[slot] = pack3(a, bb, pid);
+        }
+      }
+      ncross += __popcll(cm);
+    }
+    const int nkeep = nv - nrem;
+    if (nkeep + ncross > V_CAP) {
+      overflow = true;
+      break;
+    }
+    __syncthreads();
+    // compact kept vertices, append the new ones
+    const unsigned long long k0 = __ballot(v0 < nv && !r0), k1 = __ballot(v1 < nv && !r1);
+    if (v0 < nv && !r0) {
+      const int d = prefix_below(k0);
+      L.vx[d] = x0, L.vy[d] = y0, L.vz[d] = z0, L.vp[d] = p0;
+    }
+    if (v1 < nv && !r1) {
+      const int d = __popcll(k0) + prefix_below(k1);
+      L.vx[d] = x1, L.vy[d] = y1, L.vz[d] = z1, L.vp[d] = p1;
+    }
+    for (int t = lane; t < ncross; t += 64) {
+      L.vx[nkeep + t] = L.tx[t];
+      L.vy[nkeep + t] = L.ty[t];
+      L.vz[nkeep + t] = L.tz[t];
+      L.vp[nkeep + t] = L.tp[t];
+    }
+    nv = nkeep + ncross;
+    vmax = max(vmax, nv);
+    __syncthreads();
+  }
+  if (lane == 0) {
+    atomicMax(&b.ctr[C_MAX_NB], (unsigned long long)nn);
+    atomicMax(&b.ctr[C_MAX_V], (unsigned long long)vmax);
+  }
+  if (overflow) {
+    if (lane == 0) {
+      atomicAdd(&b.ctr[C_OVERFLOW], 1ull);
+      b.vflag[i] = 0;
+      b.kn_cnt[i] = 0;
+      b.kt_cnt[i] = 0;
+      b.ktr_cnt[i] = 0;
+    }
+    return;
+  }
+  if (empty) nv = 0;
+
+  // ---- 3. the star: K-tetrahedra (cell vertices in B_i), K-triangles (cell
+  // edges meeting B_i), K-edges (facets meeting B_i)
+  int ties = 0;
+  bool in0 = false, in1 = false;
+  unsigned p0 = 0, p1 = 0;
+  double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+  if (lane < nv) {
+    x0 = L.vx[lane], y0 = L.vy[lane], z0 = L.vz[lane], p0 = L.vp[lane];
+    const double m = x0 * x0 + y0 * y0 + z0 * z0 - wi;
+    in0 = m <= 0.0 && pid0(p0) >= 6;
+    ties += fabs(m) < kNearTie;
+  }
+  if (lane + 64 < nv) {
+    x1 = L.vx[lane + 64], y1 = L.vy[lane + 64], z1 = L.vz[lane + 64], p1 = L.vp[lane + 64];
+    const double m = x1 * x1 + y1 * y1 + z1 * z1 - wi;
+    in1 = m <= 0.0 && pid0(p1) >= 6;
+    ties += fabs(m) < kNearTie;
+  }
+  // facets present
+  for (int h = 0; h < 2; ++h) {
+    const int v = lane + 64 * h;
+    if (v < nv) {
+      const unsigned p = h ? p1 : p0;
+      const unsigned ids[3] = {pid0(p), pid1(p), pid2(p)};
+      for (int c = 0; c < 3; ++c)
+        if (ids[c] >= 6) atomicOr(&L.sflag[ids[c] - 6], (unsigned)SF_FACET);
+    }
+  }
+  __syncthreads();
+  // cell edges: partner of each of my vertices along each of its three plane
+  // pairs; an edge is handled by its lower vertex.  Triangles are appended in
+  // a fixed (vertex, pair) order so that the star is deterministic.
+  int partner[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+  for (int t = 0; t < nv; ++t) {
+    const unsigned pt = L.vp[t];
+    for (int h = 0; h < 2; ++h) {
+      const int v = lane + 64 * h;
+      if (v >= nv || t == v) continue;
+      const unsigned p = h ? p1 : p0;
+      if (has2(pt, pid1(p), pid2(p))) partner[h][0] = t;
+      if (has2(pt, pid0(p), pid2(p))) partner[h][1] = t;
+      if (has2(pt, pid0(p), pid1(p))) partner[h][2] = t;
+    }
+  }
+  int ntri = 0;
+  for (int h = 0; h < 2; ++h) {
+    const int v = lane + 64 * h;
+    const unsigned p = h ? p1 : p0;
+    const double vx = h ? x1 : x0, vy = h ? y1 : y0, vz = h ? z1 : z0;
+    const bool vin = h ? in1 : in0;
+    for (int c = 0; c < 3; ++c) {
+      const unsigned pa = c == 0 ? pid1(p) : pid0(p);
+      const unsigned pb = c == 2 ? pid1(p) : pid2(p);
+      const int u = partner[h][c];
+      bool hit = false;
+      unsigned word = 0;
+      if (v < nv && u > v && pa >= 6 && pb >= 6) {
+        const double ux = L.vx[u], uy = L.vy[u], uz = L.vz[u];
+        const unsigned pu = L.vp[u];
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        const bool uin = (u2 - wi <= 0.0) && pid0(pu) >= 6;
+        // closest point of the segment to p_i
+        const double dx = ux - vx, dy = uy - vy, dz = uz - vz;
+        const double dd = dx * dx + dy * dy + dz * dz;
+        double t = dd > 0.0 ? -(vx * dx + vy * dy + vz * dz) / dd : 0.0;
+        t = fmin(fmax(t, 0.0), 1.0);
+        const double qx = vx + t * dx, qy = vy + t * dy, qz = vz + t * dz;
+        const double m = qx * qx + qy * qy + qz * qz - wi;
+        ties += fabs(m) < kNearTie;
+        if (m <= 0.0) {
+          hit = true;
+          const unsigned nt = (unsigned)vin + (unsigned)uin;
+          word = (pa - 6) | ((pb - 6) << 10) | (nt << 20);
+          const unsigned f = SF_KTRI | (nt <= 1 ? SF_EXTTRI : 0u);
+          atomicOr(&L.sflag[pa - 6], f);
+          atomicOr(&L.sflag[pb - 6], f);
+        }
+      }
+      const unsigned long long hm = __ballot(hit);
+      if (hit) {
+        const int at = ntri + prefix_below(hm);
+        if (at < 2 * V_CAP) L.tri[at] = word;
+      }
+      ntri += __popcll(hm);
+    }
+  }
+  ntri = min(ntri, 2 * V_CAP);
+  // facets without a K-triangle: K-edge iff the disk centre lies in the cell
+  for (int s = lane; s < nn; s += 64) {
+    unsigned f = L.sflag[s];
+    bool kedge = (f & SF_KTRI) != 0;
+    if (!kedge && (f & SF_FACET)) {
+      const double nx = L.nx[s], ny = L.ny[s], nz = L.nz[s], nb = L.nb[s];
+      const double sc = nb / (nx * nx + ny * ny + nz * nz);
+      const double yx = sc * nx, yy = sc * ny, yz = sc * nz;
+      const double se = yx * yx + yy * yy + yz * yz - wi;
+      ties += fabs(se) < kNearTie;
+      bool inside = se <= 0.0;
+      for (int t = 0; t < nn && inside; ++t) {
+        if (t == s) continue;
+        const double g = L.nb[t] - (L.nx[t] * yx + L.ny[t] * yy + L.nz[t] * yz);
+        ties += fabs(g) < kNearTie;
+        inside = g >= 0.0;
+      }
+      kedge = inside;
+    }
+    if (kedge) {
+      f |= SF_KEDGE;
+      if (!(f & SF_KTRI) || (f & SF_EXTTRI)) f |= SF_EXTEDGE;
+    }
+    L.sflag[s] = f;
+  }
+  // origin in the cell (used when there is no K-edge)
+  bool origin_in = true;
+  for (int s = lane; s < nn; s += 64) origin_in &= L.nb[s] >= 0.0;
+  origin_in = __ballot(!origin_in) == 0ull;
+  __syncthreads();
+  // K-neighbour indices (slot order = ascending global id)
+  int nk = 0;
+  unsigned long long extmask = 0ull;
+  for (int base = 0; base < nn; base += 64) {
+    const int s = base + lane;
+    const unsigned f = s < nn ? L.sflag[s] : 0u;
+    const bool ke = (f & SF_KEDGE) != 0;
+    const unsigned long long m = __ballot(ke);
+    if (ke) {
+      const int kk = nk + prefix_below(m);
+      L.kidx[s] = kk;
+      if (kk < KN_CAP) b.knbr[(size_t)i * KN_CAP + kk] = L.idx[s];
+      if ((f & SF_EXTEDGE) && kk < 64) extmask |= 1ull << kk;
+    }
+    nk += __popcll(m);
+  }
+  {
+    unsigned lo = (unsigned)extmask, hi = (unsigned)(extmask >> 32);
+    for (int off = 32; off > 0; off >>= 1) {
+      lo |= (unsigned)__shfl_xor((int)lo, off, 64);
+      hi |= (unsigned)__shfl_xor((int)hi, off, 64);
+    }
+    extmask = (unsigned long long)lo | ((unsigned long long)hi << 32);
+  }
+  const int next = __popcll(extmask);
+  const bool inK = !empty && (nk > 0 || origin_in);
+  const bool ext = inK && (nk == 0 || next > 0);
+  __syncthreads();
+
+  // tetrahedra at i (cell vertices inside B_i)
+  const unsigned long long tm0 = __ballot(in0), tm1 = __ballot(in1);
+  const int ntet = __popcll(tm0) + __popcll(tm1);
+  bool bad = nk > KN_CAP || ntet > KT_CAP;
+  bool bad_lane = false;  // a cell vertex in B_i whose facets were not all found (broken star)
+  int own_tet = 0;
+  for (int h = 0; h < 2; ++h) {
+    const bool vin = h ? in1 : in0;
+    if (!vin) continue;
+    const unsigned p = h ? p1 : p0;
+    const int at = h ? __popcll(tm0) + prefix_below(tm1) : prefix_below(tm0);
+    const int sa = (int)pid0(p) - 6, sb = (int)pid1(p) - 6, sc = (int)pid2(p) - 6;
+    const int ka = L.kidx[sa], kb = L.kidx[sb], kc = L.kidx[sc];
+    if (ka < 0 || kb < 0 || kc < 0 || ka >= KN_CAP || kb >= KN_CAP || kc >= KN_CAP) bad_lane = true;
+    else if (at < KT_CAP)
+      b.ktet[(size_t)i * KT_CAP + at] = (unsigned)ka | ((unsigned)kb << 8) | ((unsigned)kc << 16);
+    const int ja = L.idx[sa], jb = L.idx[sb], jc = L.idx[sc];
+    if (i < ja && i < jb && i < jc) {
+      ++own_tet;
+      if (b.export_on) {
+        const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_TET], 1ull);
+        if ((int64_t)at2 < b.ex_cap_q) {
+          int* o = b.ex_tets + 4 * at2;
+          o[0] = i, o[1] = ja, o[2] = jb, o[3] = jc;
+        }
+      }
+    }
+  }
+  // triangles at i: exterior ones are kept, owned ones counted / exported
+  int own_tri = 0, own_ext_tri = 0, next_tri = 0;
+  for (int base = 0; base < ntri; base += 64) {
+    const int r = base + lane;
+    bool keep = false;
+    unsigned word = 0;
+    if (r < ntri) {
+      const unsigned t = L.tri[r];
+      const int sa = (int)(t & 1023u), sb = (int)((t >> 10) & 1023u);
+      const unsigned nt = t >> 20;
+      const int ka = L.kidx[sa], kb = L.kidx[sb];
+      keep = nt <= 1;
+      if (ka < 0 || kb < 0 || ka >= KN_CAP || kb >= KN_CAP) bad_lane = true, keep = false;
+      word = (unsigned)ka | ((unsigned)kb << 8) | (nt << 16);
+      const int ja = L.idx[sa], jb = L.idx[sb];
+      if (i < ja && i < jb) {
+        ++own_tri;
+        own_ext_tri += keep;
+        if (b.export_on) {
+          const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_TRI], 1ull);
+          if ((int64_t)at2 < b.ex_cap_t) {
+            int* o = b.ex_tris + 3 * at2;
+            o[0] = i, o[1] = min(ja, jb), o[2] = max(ja, jb);
+            b.ex_ntet[at2] = (uint8_t)nt;
+          }
+        }
+      }
+    }
+    const unsigned long long km = __ballot(keep);
+    if (keep) {
+      const int at = next_tri + prefix_below(km);
+      if (at < KTR_CAP) b.ktri[(size_t)i * KTR_CAP + at] = word;
+    }
+    next_tri += __popcll(km);
+  }
+  bad |= next_tri > KTR_CAP;
+  bad |= __ballot(bad_lane) != 0ull;
+  // owned edges
+  int own_edge = 0, own_ext_edge = 0;
+  for (int s = lane; s < nn; s += 64) {
+    const unsigned f = L.sflag[s];
+    if ((f & SF_KEDGE) && i < L.idx[s]) {
+      ++own_edge;
+      own_ext_edge += (f & SF_EXTEDGE) != 0;
+      if (b.export_on) {
+        const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_EDGE], 1ull);
+        if ((int64_t)at2 < b.ex_cap_e) {
+          b.ex_edges[2 * at2] = i;
+          b.ex_edges[2 * at2 + 1] = L.idx[s];
+        }
+      }
+    }
+  }
+  // wave sums
+  for (int off = 32; off > 0; off >>= 1) {
+    own_tet += __shfl_xor(own_tet, off, 64);
+    own_tri += __shfl_xor(own_tri, off, 64);
+    own_ext_tri += __shfl_xor(own_ext_tri, off, 64);
+    own_edge += __shfl_xor(own_edge, off, 64);
+    own_ext_edge += __shfl_xor(own_ext_edge, off, 64);
+    ties += __shfl_xor(ties, off, 64);
+  }
+  if (lane == 0) {
+    if (bad) {
+      atomicAdd(&b.ctr[C_OVERFLOW], 1ull);
+      b.vflag[i] = 0;
+      b.kn_cnt[i] = 0;
+      b.kt_cnt[i] = 0;
+      b.ktr_cnt[i] = 0;
+    } else {
+      b.vflag[i] = (inK ? VF_IN : 0) | (ext ? VF_EXT : 0);
+      b.kn_cnt[i] = nk;
+      b.kn_ext[i] = extmask;
+      b.kt_cnt[i] = ntet;
+      b.ktr_cnt[i] = next_tri;
+    }
+    if (inK) atomicAdd(&b.ctr[C_VERT], 1ull);
+    if (ext) atomicAdd(&b.ctr[C_EXT_VERT], 1ull);
+    if (own_tet) atomicAdd(&b.ctr[C_TET], (unsigned long long)own_tet);
+    if (own_tri) atomicAdd(&b.ctr[C_TRI], (unsigned long long)own_tri);
+    if (own_ext_tri) atomicAdd(&b.ctr[C_EXT_TRI], (unsigned long long)own_ext_tri);
+    if (own_edge) atomicAdd(&b.ctr[C_EDGE], (unsigned long long)own_edge);
+    if (own_ext_edge) atomicAdd(&b.ctr[C_EXT_EDGE], (unsigned long long)own_ext_edge);
+    if (ties) atomicAdd(&b.ctr[C_NEAR_TIE], (unsigned long long)ties);
+  }
+}
+
+// ------------------------------------------------------------------ terms
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+template <typename T>
+__device__ inline V3<T> operator+(V3<T> a, V3<T> b) {
+  return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename T>
+__device__ inline V3<T> operator-(V3<T> a, V3<T> b) {
+  return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename T>
+__device__ inline V3<T> operator*(V3<T> a, T s) {
+  return {a.x * s, a.y * s, a.z * s};
+}
+template <typename T>
+__device__ inline T dot(V3<T> a, V3<T> b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename T>
+__device__ inline V3<T> cross(V3<T> a, V3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename T>
+__device__ inline T norm(V3<T> a) {
+  return sqrt(dot(a, a));
+}
+
+__device__ inline float tatan2(float y, float x) { return atan2f(y, x); }
+__device__ inline double tatan2(double y, double x) { return atan2(y, x); }
+
+// Normalised solid angle at the origin of the tetrahedron (0, a, b, c) (Van
+// Oosterom--Strackee, atan2 form) and its gradient with respect to a, b, c.
+template <typename T>
+__device__ T solid_angle(V3<T> a, V3<T> b, V3<T> c, V3<T>* ga, V3<T>* gb, V3<T>* gc, bool grad) {
+  const T la = norm(a), lb = norm(b), lc = norm(c);
+  const V3<T> bxc = cross(b, c);
+  const T tp = dot(a, bxc);
+  const T N = fabs(tp);
+  const T ab = dot(a, b), ac = dot(a, c), bc = dot(b, c);
+  const T D = la * lb * lc + ab * lc + ac * lb + bc * la;
+  const T inv2pi = T(1.0 / (2.0 * kPi));
+  const T om = tatan2(N, D) * inv2pi;
+  if (grad) {
+    const T k = inv2pi / (N * N + D * D);
+    const T dN = D * k * (tp >= T(0) ? T(1) : T(-1));
+    const T dD = -N * k;
+    *ga = cross(b, c) * dN + (a * ((lb * lc + bc) / la) + b * lc + c * lb) * dD;
+    *gb = cross(c, a) * dN + (b * ((la * lc + ac) / lb) + a * lc + c * la) * dD;
+    *gc = cross(a, b) * dN + (c * ((la * lb + ab) / lc) + a * lb + b * la) * dD;
+  }
+  return om;
+}
+
+// Normalised dihedral angle along the edge (0, e) between the faces (0, e, u)
+// and (0, e, v), and its gradient with respect to e, u, v.  The wing
+// gradients are normal to their faces; the edge end takes the lever share
+// that keeps the angle invariant under translation and rotation.
+template <typename T>
+__device__ T dihedral(V3<T> e, V3<T> u, V3<T> v, V3<T>* ge, V3<T>* gu, V3<T>* gv, bool grad) {
+  const V3<T> nk = cross(e, u), nl = cross(e, v);
+  const T inv2pi = T(1.0 / (2.0 * kPi));
+  const T ph = tatan2(norm(cross(nk, nl)), dot(nk, nl)) * inv2pi;
+  if (grad) {
+    const T le2 = dot(e, e), le = sqrt(le2);
+    const T sg = dot(nk, v) >= T(0) ? T(1) : T(-1);
+    *gu = nk * (-sg * le / dot(nk, nk) * inv2pi);
+    *gv = nl * (sg * le / dot(nl, nl) * inv2pi);
+    const T tu = dot(u, e) / le2, tv = dot(v, e) / le2;
+    *ge = (*gu) * (-tu) + (*gv) * (-tv);
+  }
+  return ph;
+}
+
+// Cap of sphere i (centre at the origin, radius R) inside ball (a, Ra):
+// S = 2 pi R h, h = R - (d^2 + R^2 - Ra^2) / (2d); gradient with respect to a.
+template <typename T>
+__device__ T cap_area(V3<T> a, T R, T Ra, V3<T>* g, bool grad) {
+  const T d = norm(a);
+  const T dw = R * R - Ra * Ra;
+  const T h = R - (d * d + dw) / (T(2) * d);
+  if (grad) *g = a * (T(-2.0 * kPi) * R * (T(0.5) - dw / (T(2) * d * d)) / d);
+  return T(2.0 * kPi) * R * h;
+}
+
+struct TermsLds {
+  double px[KN_CAP], py[KN_CAP], pz[KN_CAP], pR[KN_CAP];
+  unsigned tet[KT_CAP];
+  unsigned tri[KTR_CAP];
+  double S[KN_CAP];                 // cap areas of exterior edges
+  double phi[KT_CAP][3];            // dihedral fractions along (i,a), (i,b), (i,c)
+  double tg[KT_CAP][3][3];          // tet contributions to a, b, c
+  double rg[KTR_CAP][2][3];         // triangle contributions to a, b
+  double red[64];
+};
+
+template <typename T>
+__device__ inline V3<T> ld(const TermsLds& L, int k) {
+  return {T(L.px[k]), T(L.py[k]), T(L.pz[k])};
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
+  __shared__ TermsLds L;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= b.n) return;
+  const uint8_t vf = b.vflag[i];
+  if (!(vf & VF_EXT)) {
+    if (lane == 0) b.area[i] = 0.0;
+    return;
+  }
+  const bool grad = with_grad != 0;
+  const double4 pi = b.pos[i];
+  const double Ri = pi.w, wi = Ri * Ri;
+  const int nk = b.kn_cnt[i], nt = b.kt_cnt[i], nr = b.ktr_cnt[i];
+  const unsigned long long extm = b.kn_ext[i];
+  for (int k = lane; k < nk; k += 64) {
+    const double4 pj = b.pos[b.knbr[(size_t)i * KN_CAP + k]];
+    L.px[k] = pj.x - pi.x;
+    L.py[k] = pj.y - pi.y;
+    L.pz[k] = pj.z - pi.z;
+    L.pR[k] = pj.w;
+  }
+  for (int t = lane; t < nt; t += 64) L.tet[t] = b.ktet[(size_t)i * KT_CAP + t];
+  for (int t = lane; t < nr; t += 64) L.tri[t] = b.ktri[(size_t)i * KTR_CAP + t];
+  __syncthreads();
+  const T Rt = T(Ri);
+  const double Si = 4.0 * kPi * wi;
+  // edges: cap areas
+  V3<T> gS = {T(0), T(0), T(0)};
+  double Sk = 0.0;
+  const int k = lane;  // one K-neighbour per lane (KN_CAP = 64)
+  const bool kext = k < nk && ((extm >> k) & 1ull);
+  if (kext) {
+    Sk = (double)cap_area<T>(ld<T>(L, k), Rt, T(L.pR[k]), &gS, grad);
+    L.S[k] = Sk;
+  }
+  __syncthreads();
+  // tetrahedra: solid angle at i, dihedral angles along the three edges at i
+  double omega_sum = 0.0;
+  for (int t = lane; t < nt; t += 64) {
+    const unsigned w = L.tet[t];
+    const int ks[3] = {(int)(w & 255u), (int)((w >> 8) & 255u), (int)((w >> 16) & 255u)};
+    if (ks[0] >= nk || ks[1] >= nk || ks[2] >= nk) {  // never produced by k_star; keeps LDS reads in range
+      L.phi[t][0] = L.phi[t][1] = L.phi[t][2] = 0.0;
+      for (int c = 0; c < 3; ++c) L.tg[t][c][0] = L.tg[t][c][1] = L.tg[t][c][2] = 0.0;
+      continue;
+    }
+    const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
+    V3<T> g[3], acc[3];
+    const T om = solid_angle<T>(P[0], P[1], P[2], &g[0], &g[1], &g[2], grad);
+    omega_sum += (double)om;
+    for (int c = 0; c < 3; ++c) acc[c] = g[c] * T(-Si);
+    for (int c = 0; c < 3; ++c) {
+      // dihedral along (i, ks[c]) between the faces with the other two
+      const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
+      V3<T> ge, g1, g2;
+      const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad);
+      L.phi[t][c] = (double)ph;
+      if (grad && ((extm >> ks[c]) & 1ull)) {
+        const T Se = T(L.S[ks[c]]);
+        acc[c] = acc[c] + ge * Se;
+        acc[o1] = acc[o1] + g1 * Se;
+        acc[o2] = acc[o2] + g2 * Se;
+      }
+    }
+    if (grad)
+      for (int c = 0; c < 3; ++c) {
+        L.tg[t][c][0] = (double)acc[c].x;
+        L.tg[t][c][1] = (double)acc[c].y;
+        L.tg[t][c][2] = (double)acc[c].z;
+      }
+  }
+  __syncthreads();
+  // edges: outer dihedral coefficient Phi = 1 - sum of the K-tet dihedral fractions
+  double area_part = 0.0;
+  double ex = 0, ey = 0, ez = 0;  // edge contribution to atom k
+  if (kext) {
+    double phi_sum = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const unsigned w = L.tet[t];
+      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u), c = (int)((w >> 16) & 255u);
+      if (a == k) phi_sum += L.phi[t][0];
+      else if (bb == k) phi_sum += L.phi[t][1];
+      else if (c == k) phi_sum += L.phi[t][2];
+    }
+    const double Phi = 1.0 - phi_sum;
+    area_part -= Phi * Sk;
+    ex = -Phi * (double)gS.x;
+    ey = -Phi * (double)gS.y;
+    ez = -Phi * (double)gS.z;
+  }
+  // exterior triangles: Eq. 6 through the triple point
+  for (int r = lane; r < nr; r += 64) {
+    const unsigned w = L.tri[r];
+    const int ka = (int)(w & 255u), kb = (int)((w >> 8) & 255u);
+    if (ka >= nk || kb >= nk) {  // never produced by k_star; keeps LDS reads in range
+      for (int c = 0; c < 3; ++c) L.rg[r][0][c] = L.rg[r][1][c] = 0.0;
+      continue;
+    }
+    const double ct = 1.0 - 0.5 * (double)(w >> 16);
+    // triple point in double: y in the plane of the centres, x = y + sqrt(-s) n
+    const double ax = L.px[ka], ay = L.py[ka], az = L.pz[ka];
+    const double bx = L.px[kb], by = L.py[kb], bz = L.pz[kb];
+    const double wa = L.pR[ka] * L.pR[ka], wb = L.pR[kb] * L.pR[kb];
+    const double aa = ax * ax + ay * ay + az * az, bb2 = bx * bx + by * by + bz * bz, ab = ax * bx + ay * by + az * bz;
+    const double ra = aa - wa + wi, rb = bb2 - wb + wi;
+    const double det = 2.0 * (aa * bb2 - ab * ab);
+    const double al = (ra * bb2 - rb * ab) / det, be = (aa * rb - ab * ra) / det;
+    const double yx = al * ax + be * bx, yy = al * ay + be * by, yz = al * az + be * bz;
+    const double s = yx * yx + yy * yy + yz * yz - wi;
+    double St = 0.0;
+    V3<T> Ga = {T(0), T(0), T(0)}, Gb = {T(0), T(0), T(0)};
+    if (s < 0.0) {
+      const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+      const double f = sqrt(-s / (nx * nx + ny * ny + nz * nz));
+      const V3<T> X = {T(yx + f * nx), T(yy + f * ny), T(yz + f * nz)};
+      const V3<T> A = ld<T>(L, ka), B = ld<T>(L, kb);
+      V3<T> gSa, gSb, g1e, g1u, g1v, g2e, g2u, g2v, gwa, gwb, gwx;
+      const T Sa = cap_area<T>(A, Rt, T(L.pR[ka]), &gSa, grad);
+      const T Sb = cap_area<T>(B, Rt, T(L.pR[kb]), &gSb, grad);
+      const T ph1 = dihedral<T>(A, B, X, &g1e, &g1u, &g1v, grad);  // along (i,a)
+      const T ph2 = dihedral<T>(B, A, X, &g2e, &g2u, &g2v, grad);  // along (i,b)
+      const T om = solid_angle<T>(A, B, X, &gwa, &gwb, &gwx, grad);
+      const T Sw = T(Si);
+      St = 2.0 * (double)(ph1 * Sa + ph2 * Sb - om * Sw);
+      if (grad) {
+        // direct partials of S_t / 2
+        V3<T> dA = g1e * Sa + gSa * ph1 + g2u * Sb - gwa * Sw;
+        V3<T> dB = g1u * Sa + g2e * Sb + gSb * ph2 - gwb * Sw;
+        const V3<T> dX = g1v * Sa + g2v * Sb - gwx * Sw;
+        // through the triple point: M dx = [(x - p_m) . dp_m], rows x, x - a, x - b
+        const V3<T> r0 = X, r1 = X - A, r2 = X - B;
+        const V3<T> c0 = cross(r1, r2), c1 = cross(r2, r0), c2 = cross(r0, r1);
+        const T idet = T(1) / dot(r0, c0);
+        const T l1 = dot(c1, dX) * idet, l2 = dot(c2, dX) * idet;
+        dA = dA + r1 * l1;
+        dB = dB + r2 * l2;
+        const T sc = T(2.0 * ct);
+        Ga = dA * sc;
+        Gb = dB * sc;
+      }
+    }
+    area_part += ct * St;
+    if (grad) {
+      L.rg[r][0][0] = (double)Ga.x, L.rg[r][0][1] = (double)Ga.y, L.rg[r][0][2] = (double)Ga.z;
+      L.rg[r][1][0] = (double)Gb.x, L.rg[r][1][1] = (double)Gb.y, L.rg[r][1][2] = (double)Gb.z;
+    }
+  }
+  // area: Omega_i 4 pi w_i - sum Phi S + sum c S_t  (deterministic butterfly sums)
+  double os = omega_sum, ap = area_part;
+  for (int off = 32; off > 0; off >>= 1) {
+    os += __shfl_xor(os, off, 64);
+    ap += __shfl_xor(ap, off, 64);
+  }
+  if (lane == 0) b.area[i] = (1.0 - os) * Si + ap;
+  if (!grad) return;
+  __syncthreads();
+  // gradient block for K-neighbour k: edge + tetrahedra + triangles containing k
+  double gx = ex, gy = ey, gz = ez;
+  if (k < nk) {
+    for (int t = 0; t < nt; ++t) {
+      const unsigned w = L.tet[t];
+      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u), c = (int)((w >> 16) & 255u);
+      const int pos = a == k ? 0 : bb == k ? 1 : c == k ? 2 : -1;
+      if (pos >= 0) gx += L.tg[t][pos][0], gy += L.tg[t][pos][1], gz += L.tg[t][pos][2];
+    }
+    for (int r = 0; r < nr; ++r) {
+      const unsigned w = L.tri[r];
+      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u);
+      const int pos = a == k ? 0 : bb == k ? 1 : -1;
+      if (pos >= 0) gx += L.rg[r][pos][0], gy += L.rg[r][pos][1], gz += L.rg[r][pos][2];
+    }
+    double* row = b.rows + ((size_t)i * ROW + k) * 3;
+    row[0] = gx, row[1] = gy, row[2] = gz;
+  } else {
+    gx = gy = gz = 0.0;
+  }
+  // the atom's own block: every term is translation invariant
+  for (int off = 32; off > 0; off >>= 1) {
+    gx += __shfl_xor(gx, off, 64);
+    gy += __shfl_xor(gy, off, 64);
+    gz += __shfl_xor(gz, off, 64);
+  }
+  if (lane == 0) {
+    double* row = b.rows + ((size_t)i * ROW + KN_CAP) * 3;
+    row[0] = -gx, row[1] = -gy, row[2] = -gz;
+  }
+}
+
+// ------------------------------------------------------------------ gather
+__global__ void k_gather(Bufs b, const double* u, double* out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= b.n) return;
+  double gx = 0, gy = 0, gz = 0;
+  if (b.vflag[m] & VF_EXT) {
+    const double um = u ? u[m] : 1.0;
+    const double* row = b.rows + ((size_t)m * ROW + KN_CAP) * 3;
+    gx += um * row[0], gy += um * row[1], gz += um * row[2];
+  }
+  const int nk = b.kn_cnt[m];
+  int lost = 0;
+  for (int k = 0; k < nk; ++k) {
+    const int i = b.knbr[(size_t)m * KN_CAP + k];
+    if (!(b.vflag[i] & VF_EXT)) continue;
+    // position of m among i's K-neighbours (ascending ids)
+    const int* li = b.knbr + (size_t)i * KN_CAP;
+    int lo = 0, hi = b.kn_cnt[i] - 1, s = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int v = li[mid];
+      if (v == m) {
+        s = mid;
+        break;
+      }
+      if (v < m) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (s < 0) {
+      ++lost;
+      continue;
+    }
+    const double ui = u ? u[i] : 1.0;
+    const double* row = b.rows + ((size_t)i * ROW + s) * 3;
+    gx += ui * row[0], gy += ui * row[1], gz += ui * row[2];
+  }
+  out[3 * m] = gx;
+  out[3 * m + 1] = gy;
+  out[3 * m + 2] = gz;
+  if (lost) atomicAdd(&b.ctr[C_LOST_PAIR], (unsigned long long)lost);
+}
+
+__global__ void k_zero(unsigned* p, size_t words) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < words) p[k] = 0u;
+}
+
+inline unsigned blocks(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int scan_blocks(unsigned hb) { return (int)((hb + SCAN_E - 1) / SCAN_E); }
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  if (words) k_zero<<<blocks(words, 256), 256, 0, s>>>((unsigned*)p, words);
+}
+void launch_prep(const Bufs& b, hipStream_t s) {
+  if (b.n) k_prep<<<blocks(b.n, 256), 256, 0, s>>>(b);
+}
+void launch_buckets(const Bufs& b, hipStream_t s) {
+  if (b.n) k_buckets<<<blocks(b.n, 256), 256, 0, s>>>(b);
+}
+void launch_scan(const Bufs& b, hipStream_t s) {
+  const int hb = (int)b.hb_mask + 1;
+  const int nb = scan_blocks((unsigned)hb);
+  k_scan1<<<nb, SCAN_T, 0, s>>>(b.cnt, b.start, b.scan_tmp, hb);
+  k_scan2<<<1, SCAN_T, 0, s>>>(b.scan_tmp, nb, b.start, hb);
+  k_scan3<<<blocks(hb, 256), 256, 0, s>>>(b.start, b.scan_tmp, hb);
+}
+void launch_scatter(const Bufs& b, hipStream_t s) {
+  if (b.n) k_scatter<<<blocks(b.n, 256), 256, 0, s>>>(b);
+}
+void launch_star(const Bufs& b, hipStream_t s) {
+  if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
+}
+void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
+  if (!b.n) return;
+  if (precision == 1) k_terms<float><<<b.n, 64, 0, s>>>(b, with_grad);
+  else k_terms<double><<<b.n, 64, 0, s>>>(b, with_grad);
+}
+void launch_gather(const Bufs& b, const double* u, double* out, hipStream_t s) {
+  if (b.n) k_gather<<<blocks(b.n, 256), 256, 0, s>>>(b, u, out);
+}
+
+}  // namespace sasa

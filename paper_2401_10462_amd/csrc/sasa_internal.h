@@ -1,0 +1,95 @@
+// sasa_internal.h -- device-side data layout shared by the HIP kernels and the
+// host side of the library (not part of the public C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sasa {
+
+// Per-atom capacities of the star kernel (local data in LDS).
+constexpr int NB_CAP = 192;  // overlapping neighbours of one atom
+constexpr int V_CAP = 128;   // vertices of the clipped power cell (2 per lane)
+// Per-atom capacities of the kept complex (HBM).
+constexpr int KN_CAP = 64;    // K-edges at an atom (bit mask of exterior edges is one u64)
+constexpr int KT_CAP = 160;   // K-tetrahedra at an atom
+constexpr int KTR_CAP = 160;  // exterior K-triangles at an atom
+constexpr int ROW = KN_CAP + 1;  // gradient row: one block per K-neighbour + the atom itself
+
+// Counter slots (unsigned long long) on the device.
+enum Counter {
+  C_VERT = 0,      // vertices in K
+  C_EDGE,          // edges in K (counted once, by the lowest atom index)
+  C_TRI,           // triangles in K
+  C_TET,           // tetrahedra in K
+  C_EXT_VERT,      // exterior vertices
+  C_EXT_EDGE,      // exterior edges
+  C_EXT_TRI,       // exterior triangles
+  C_MAX_NB,        // max overlapping neighbours (atomicMax)
+  C_MAX_V,         // max polytope vertices (atomicMax)
+  C_NEAR_TIE,      // near-degenerate decisions
+  C_OVERFLOW,      // atoms past NB_CAP / V_CAP / KN_CAP / KT_CAP / KTR_CAP
+  C_BAD_INPUT,     // NaN / Inf / radius <= 0
+  C_LOST_PAIR,     // K-edge seen from one side only (gather)
+  C_RMAX_BITS,     // bits of max R (positive doubles order like integers)
+  C_EX_EDGE,       // export cursors
+  C_EX_TRI,
+  C_EX_TET,
+  C_COUNT
+};
+
+// Vertex flags.
+constexpr uint8_t VF_IN = 1, VF_EXT = 2;
+
+struct Bufs {
+  int n = 0;
+  int nmol = 0;
+  unsigned hb_mask = 0;  // hash buckets - 1 (power of two)
+  // inputs staged or borrowed
+  const double* xyz = nullptr;
+  const double* radii = nullptr;
+  double probe = 0;
+  const int64_t* offsets = nullptr;  // nmol + 1 (device)
+  // cell list
+  double4* pos = nullptr;    // x, y, z, R (original order)
+  int* mol = nullptr;        // molecule id (original order)
+  int* bucket = nullptr;     // hash bucket of each atom
+  int* cnt = nullptr;        // bucket counts (hb)
+  int* start = nullptr;      // exclusive scan of cnt (hb + 1)
+  int* scan_tmp = nullptr;   // block sums of the scan
+  int* sorted = nullptr;     // atom ids grouped by bucket
+  double4* spos = nullptr;   // positions in bucket order (coalesced neighbour loads)
+  int* smol = nullptr;       // molecule ids in bucket order
+  // kept complex
+  uint8_t* vflag = nullptr;
+  int* kn_cnt = nullptr;
+  int* knbr = nullptr;                 // n * KN_CAP, ascending global ids
+  unsigned long long* kn_ext = nullptr;  // exterior-edge mask
+  int* kt_cnt = nullptr;
+  unsigned* ktet = nullptr;            // n * KT_CAP, 3 x 8-bit K-neighbour slots
+  int* ktr_cnt = nullptr;
+  unsigned* ktri = nullptr;            // n * KTR_CAP, 2 x 8-bit slots + n_tet << 16
+  // results
+  double* area = nullptr;
+  double* rows = nullptr;    // n * ROW * 3
+  unsigned long long* ctr = nullptr;
+  // export (optional)
+  int export_on = 0;
+  int64_t ex_cap_e = 0, ex_cap_t = 0, ex_cap_q = 0;
+  int* ex_edges = nullptr;
+  int* ex_tris = nullptr;
+  uint8_t* ex_ntet = nullptr;
+  int* ex_tets = nullptr;
+};
+
+// Launchers (kernels.hip).
+void launch_prep(const Bufs& b, hipStream_t s);
+void launch_buckets(const Bufs& b, hipStream_t s);
+void launch_scan(const Bufs& b, hipStream_t s);
+void launch_scatter(const Bufs& b, hipStream_t s);
+void launch_star(const Bufs& b, hipStream_t s);
+void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
+void launch_gather(const Bufs& b, const double* u, double* out, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+int scan_blocks(unsigned hb);
+
+}  // namespace sasa

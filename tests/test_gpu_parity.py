@@ -1,0 +1,156 @@
+"""HIP path vs the FP64 oracle, element by element, through the C-ABI.
+
+Bars (per atom i, Q17-style floors so that buried atoms are not divided by 0):
+  FP64 : |A - A_ref| <= 1e-9 max(A_ref, 1 A^2);  |g - g_ref| <= 1e-9 max(|g_ref|, 1 A^2/A)
+  MIXED: the same with 1e-4 (areas and gradients, spec tolerance)
+  the dual complex K (edges, triangles, tetrahedra, n_tet, vertex flags) bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth.globule import globule, heavy_chain, random_cluster
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    from paper_2401_10462_amd import SasaContext
+    c = {"fp64": SasaContext(precision="fp64"), "mixed": SasaContext(precision="mixed")}
+    yield c
+    for v in c.values():
+        v.close()
+
+
+def _sets_gpu(ctx):
+    e, t, nt, q, vf = ctx.export()
+    E = set(map(tuple, e.tolist()))
+    T = {tuple(x): int(k) for x, k in zip(t.tolist(), nt.tolist())}
+    Q = set(map(tuple, q.tolist()))
+    assert len(E) == len(e) and len(T) == len(t) and len(Q) == len(q), "duplicate simplices"
+    return E, T, Q, vf
+
+
+def _check_complex(ctx, ref):
+    E, T, Q, vf = _sets_gpu(ctx)
+    assert Q == set(map(tuple, ref.tets.tolist()))
+    assert set(T) == set(map(tuple, ref.tris.tolist()))
+    ref_nt = {tuple(x): int(k) for x, k in zip(ref.tris.tolist(), ref.tri_ntet.tolist())}
+    assert T == ref_nt
+    assert E == set(map(tuple, ref.edges.tolist()))
+    assert np.array_equal(vf & 1, ref.vert_in)
+    assert np.array_equal((vf >> 1) & 1, ref.vert_ext)
+
+
+def _check_values(area, dadx, ref, tol):
+    a_ref = ref.area
+    err_a = np.abs(area - a_ref) / np.maximum(a_ref, 1.0)
+    assert err_a.max() <= tol, f"area rel err {err_a.max():.3e} at atom {err_a.argmax()}"
+    if dadx is not None:
+        g_ref = ref.dadx
+        err_g = np.linalg.norm(dadx - g_ref, axis=1) / np.maximum(np.linalg.norm(g_ref, axis=1), 1.0)
+        assert err_g.max() <= tol, f"gradient rel err {err_g.max():.3e} at atom {err_g.argmax()}"
+
+
+CASES = [
+    ("tiny-12", lambda: random_cluster(12, 0)),
+    ("cluster-40", lambda: random_cluster(40, 2)),
+    ("cluster-80-wide-radii", lambda: random_cluster(80, 4, rmin=0.6, rmax=2.4)),
+    ("globule-300", lambda: heavy_chain(300, 1)[:2]),
+    ("globule-2000", lambda: heavy_chain(2000, 2)[:2]),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_parity_host_pointers(ctxs, name, make, prec):
+    xyz, rad = make()
+    ref = oracle.run(xyz, rad, 1.4)
+    ctx = ctxs[prec]
+    area, dadx = ctx.compute(xyz, rad, 1.4)
+    _check_complex(ctx, ref)
+    _check_values(area, dadx, ref, TOL[prec])
+    d = ctx.diagnostics()
+    assert d["overflow"] == 0 and d["lost_pairs"] == 0
+
+
+def test_parity_hydrogens_5000(ctxs):
+    # 2,500 heavy atoms + 2,500 hydrogens (hidden and partly buried small balls)
+    xyz, rad = globule(2500, 2, hydrogens=True)
+    ref = oracle.run(xyz, rad, 1.4)
+    for prec in ("fp64", "mixed"):
+        ctx = ctxs[prec]
+        area, dadx = ctx.compute(xyz, rad, 1.4)
+        _check_complex(ctx, ref)
+        _check_values(area, dadx, ref, TOL[prec])
+
+
+def test_device_pointers_and_vjp(ctxs):
+    import torch
+    xyz, rad, _ = heavy_chain(300, 1)
+    ref = oracle.run(xyz, rad, 1.4)
+    u = np.random.default_rng(5).uniform(-1, 1, len(rad))
+    for prec in ("fp64", "mixed"):
+        ctx = ctxs[prec]
+        X = torch.tensor(xyz, device="cuda")
+        R = torch.tensor(rad, device="cuda")
+        area, dadx = ctx.compute(X, R, 1.4)
+        torch.cuda.synchronize()
+        _check_values(area.cpu().numpy(), dadx.cpu().numpy(), ref, TOL[prec])
+        g = ctx.backward(torch.tensor(u, device="cuda")).cpu().numpy()
+        g_ref = ref.vjp(u)
+        err = np.linalg.norm(g - g_ref, axis=1) / np.maximum(np.linalg.norm(g_ref, axis=1), 1.0)
+        assert err.max() <= TOL[prec]
+
+
+def test_batch_equals_alone(ctxs):
+    mols = [random_cluster(30, 50 + k) for k in range(3)] + [heavy_chain(300, 7)[:2], random_cluster(1, 9)]
+    offs = np.cumsum([0] + [len(m[1]) for m in mols])
+    X = np.vstack([m[0] for m in mols])
+    R = np.concatenate([m[1] for m in mols])
+    ctx = ctxs["fp64"]
+    area_b, g_b = ctx.compute_batch(offs, X, R, 1.4)
+    for k, (x, r) in enumerate(mols):
+        a, g = ctx.compute(x, r, 1.4)
+        s = slice(offs[k], offs[k + 1])
+        assert np.array_equal(a, area_b[s])
+        assert np.array_equal(g, g_b[s])
+
+
+def test_deterministic_fp64(ctxs):
+    xyz, rad, _ = heavy_chain(300, 3)
+    ctx = ctxs["fp64"]
+    a1, g1 = ctx.compute(xyz, rad, 1.4)
+    a2, g2 = ctx.compute(xyz, rad, 1.4)
+    assert np.array_equal(a1, a2) and np.array_equal(g1, g2)
+
+
+def test_edge_cases(ctxs):
+    from paper_2401_10462_amd import _lib
+    ctx = ctxs["fp64"]
+    a, g = ctx.compute(np.zeros((0, 3)), np.zeros(0), 1.4)
+    assert a.shape == (0,)
+    a, g = ctx.compute(np.array([[1.0, 2.0, 3.0]]), np.array([1.7]), 1.4)
+    assert a[0] == pytest.approx(4 * np.pi * 3.1 ** 2, rel=1e-14) and np.all(g == 0)
+    # nested and disjoint pairs, a hidden atom
+    xyz = np.array([[0, 0, 0], [0.1, 0, 0], [20, 0, 0], [23, 0, 0]], float)
+    rad = np.array([1.7, 0.5, 1.5, 1.7])
+    ref = oracle.run(xyz, rad, 1.4)
+    a, g = ctx.compute(xyz, rad, 1.4)
+    _check_values(a, g, ref, 1e-9)
+    assert a[1] == 0.0
+    with pytest.raises(_lib.SasaError) as e:
+        ctx.compute(np.array([[np.nan, 0, 0]]), np.array([1.7]), 1.4)
+    assert e.value.code == _lib.SASA_E_INVAL
+    with pytest.raises(_lib.SasaError) as e:
+        ctx.compute(np.zeros((1, 3)), np.array([-1.0]), 1.4)
+    assert e.value.code == _lib.SASA_E_INVAL
+    from paper_2401_10462_amd import SasaContext
+    fresh = SasaContext()
+    with pytest.raises(_lib.SasaError) as e:
+        fresh.backward(np.zeros(3))
+    assert e.value.code == _lib.SASA_E_STATE
+    fresh.close()
