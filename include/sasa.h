@@ -56,8 +56,9 @@ typedef enum { SASA_FP64 = 0, SASA_MIXED = 1 } sasa_precision;
 typedef enum { SASA_MEM_HOST = 0, SASA_MEM_DEVICE = 1 } sasa_mem;
 
 enum {
-  SASA_FLAG_ASYNC = 1u /* device-pointer calls return without synchronising the stream; capacity
-                          overflow and input errors are then reported by the next sasa_diagnostics */
+  SASA_FLAG_ASYNC = 1u, /* device-pointer calls return without synchronising the stream; capacity
+                           overflow and input errors are then reported by the next sasa_diagnostics */
+  SASA_FLAG_TIMING = 2u /* record HIP events around every stage of a call (stage times in sasa_diag) */
 };
 
 typedef struct {
@@ -135,6 +136,15 @@ typedef struct {
   int64_t input_errors;       /* NaN/Inf coordinates or radii <= 0 seen by the device */
   int64_t overflow;           /* atoms beyond the kernels' neighbour / vertex capacity */
   double ms_total;            /* wall time of the last synchronous call */
+  /* stage times of the last call (SASA_FLAG_TIMING; HIP events on the call's stream) */
+  double ms_cells;            /* weights, spatial hash, scan, scatter */
+  double ms_star;             /* per-atom power-cell clipping and the star in K */
+  double ms_terms;            /* Eq. 1 area terms (and gradient blocks) */
+  double ms_gather;           /* segmented gradient sums */
+  /* algorithmic work of the last call's star kernel */
+  int64_t plane_tests;        /* (vertex, plane) side tests while clipping */
+  int64_t new_vertices;       /* cell vertices created (three-plane solves) */
+  int64_t candidates;         /* neighbour-candidate distance tests */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

@@ -23,6 +23,7 @@ SASA_MIXED = 1
 SASA_MEM_HOST = 0
 SASA_MEM_DEVICE = 1
 SASA_FLAG_ASYNC = 1
+SASA_FLAG_TIMING = 2
 
 # every entry point of include/sasa.h
 EXPORTS = (
@@ -46,7 +47,9 @@ class sasa_options(ctypes.Structure):
 class sasa_diag(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
-        "capacity_retries", "input_errors", "overflow")] + [("ms_total", ctypes.c_double)]
+        "capacity_retries", "input_errors", "overflow")] + [
+        (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_terms", "ms_gather")] + [
+        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates")]
 
 
 _lib = None
@@ -57,6 +60,13 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # One HIP runtime per process: when torch is installed, its bundled
+    # libamdhip64 must be the one this library binds to (torch streams and
+    # device pointers are then shared), so torch is loaded first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2401_10462_amd/build.py "
                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")

@@ -16,6 +16,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-mcode-object-version=5",
     # packed FP32 instructions stay off (hipcc pass-through to the device compiler)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,

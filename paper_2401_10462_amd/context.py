@@ -11,11 +11,12 @@ class SasaContext:
     tetrahedrization predicates and accumulation in double).
     """
 
-    def __init__(self, device=0, precision="fp64", max_atoms=0, async_calls=False):
+    def __init__(self, device=0, precision="fp64", max_atoms=0, async_calls=False, timing=False):
         prec = {"fp64": _lib.SASA_FP64, "mixed": _lib.SASA_MIXED}[precision]
         self.precision = precision
         self.device = device
-        self._h = _lib.sasa_create(device, prec, max_atoms, _lib.SASA_FLAG_ASYNC if async_calls else 0)
+        flags = (_lib.SASA_FLAG_ASYNC if async_calls else 0) | (_lib.SASA_FLAG_TIMING if timing else 0)
+        self._h = _lib.sasa_create(device, prec, max_atoms, flags)
 
     def close(self):
         if self._h is not None:

@@ -45,6 +45,8 @@ struct Ctx {
   int nmol = 0;
   double probe = 0;
   bool pending = false;  // an async call whose counters were not read yet
+  hipEvent_t ev[5] = {};  // stage boundaries (SASA_FLAG_TIMING)
+  bool timed = false;     // events of the last call were recorded
   sasa_diag diag{};
   std::string err;
 };
@@ -146,6 +148,18 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.lost_pairs = (int64_t)h[C_LOST_PAIR];
   c->diag.input_errors = (int64_t)h[C_BAD_INPUT];
   c->diag.overflow = (int64_t)h[C_OVERFLOW];
+  c->diag.plane_tests = (int64_t)h[C_PLANE_TESTS];
+  c->diag.new_vertices = (int64_t)h[C_NEW_VERTS];
+  c->diag.candidates = (int64_t)h[C_CANDIDATES];
+  if (c->timed) {
+    float ms[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    c->diag.ms_cells = ms[0];
+    c->diag.ms_star = ms[1];
+    c->diag.ms_terms = ms[2];
+    c->diag.ms_gather = ms[3];
+    c->timed = false;
+  }
   if (h[C_BAD_INPUT]) {
     c->kept = false;
     return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
@@ -201,15 +215,22 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   }
   b.area = (mem == SASA_MEM_DEVICE && area) ? area : c->area_d;
   double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
+  const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
   launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
   launch_zero(b.cnt, (size_t)(b.hb_mask + 1) * sizeof(int), s);
   launch_prep(b, s);
   launch_buckets(b, s);
   launch_scan(b, s);
   launch_scatter(b, s);
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   launch_star(b, s);
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
   launch_terms(b, c->precision, dA_dx != nullptr, s);
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
   if (dA_dx) launch_gather(b, nullptr, out, s);
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[4], s));
+  c->timed = timing;
   HIP_TRY(c, hipGetLastError());
   if (mem == SASA_MEM_HOST && n) {
     if (area) HIP_TRY(c, hipMemcpyAsync(area, b.area, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -262,6 +283,12 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
     return fail(nullptr, SASA_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
   }
   std::memset(c->ctr_h, 0, C_COUNT * sizeof(unsigned long long));
+  if (c->flags & SASA_FLAG_TIMING)
+    for (auto& ev : c->ev)
+      if (hipEventCreate(&ev) != hipSuccess) {
+        sasa_destroy(c);
+        return fail(nullptr, SASA_E_DEVICE, "hipEventCreate failed");
+      }
   if (opt && opt->max_atoms > 0) {
     int rc = ensure(c, opt->max_atoms, 1);
     if (rc) {
@@ -286,6 +313,8 @@ void sasa_destroy(void* ctx) {
   for (void* p : dev)
     if (p) hipFree(p);
   if (c->off_h) hipHostFree(c->off_h);
+  for (auto& ev : c->ev)
+    if (ev) hipEventDestroy(ev);
   if (c->ctr_h) hipHostFree(c->ctr_h);
   delete c;
 }
@@ -396,6 +425,7 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   launch_star(b, s);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(s));
+  c->timed = false;
   rc = read_counters(c, s);
   if (rc) return rc;
   if (edges && cnt[1]) HIP_TRY(c, hipMemcpy(edges, b.ex_edges, (size_t)cnt[1] * 2 * sizeof(int), hipMemcpyDeviceToHost));

@@ -230,12 +230,14 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __syncthreads();
   int nn = 0;
   bool overflow = false;
+  long long cand_tests = 0, plane_tests = 0, new_verts = 0;
   for (int c = 0; c < 27; ++c) {
     const int bk = L.bk[c];
     bool dup = false;
     for (int e = 0; e < c; ++e) dup |= (L.bk[e] == bk);  // buckets shared by two cells
     if (dup) continue;
     const int s0 = b.start[bk], s1 = b.start[bk + 1];
+    cand_tests += s1 - s0;
     for (int base = s0; base < s1; base += 64) {
       const int k = base + lane;
       bool take = false;
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       x1 = L.vx[v1], y1 = L.vy[v1], z1 = L.vz[v1], p1 = L.vp[v1];
       r1 = qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
     }
+    plane_tests += nv;
     const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
     const int nr0 = __popcll(m0);
     const int nrem = nr0 + __popcll(m1);
@@ -372,6 +375,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       ncross += __popcll(cm);
     }
     const int nkeep = nv - nrem;
+    new_verts += ncross;
     if (nkeep + ncross > V_CAP) {
       overflow = true;
       break;
@@ -400,6 +404,9 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   if (lane == 0) {
     atomicMax(&b.ctr[C_MAX_NB], (unsigned long long)nn);
     atomicMax(&b.ctr[C_MAX_V], (unsigned long long)vmax);
+    atomicAdd(&b.ctr[C_CANDIDATES], (unsigned long long)cand_tests);
+    atomicAdd(&b.ctr[C_PLANE_TESTS], (unsigned long long)plane_tests);
+    atomicAdd(&b.ctr[C_NEW_VERTS], (unsigned long long)new_verts);
   }
   if (overflow) {
     if (lane == 0) {
@@ -777,6 +784,96 @@ __device__ inline V3<T> ld(const TermsLds& L, int k) {
   return {T(L.px[k]), T(L.py[k]), T(L.pz[k])};
 }
 
+// One K-tetrahedron (i, a, b, c) at atom i (i at the origin): the solid angle
+// at i, the three dihedral fractions along (i,a), (i,b), (i,c), and -- with
+// grad -- its contributions to dA_i/dp for a, b, c: -4 pi w_i d(omega) from the
+// vertex term and +S_e d(phi_e) for each exterior edge e at i (Eqs. 3, 5).
+template <typename T>
+__device__ double tet_item(const TermsLds& L, const int ks[3], unsigned long long extm, double Si, bool grad,
+                           double phi[3], double acc_out[3][3]) {
+  const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
+  V3<T> acc[3];
+  // The vertex term 4 pi w_i omega is the largest single term and cancels
+  // against its neighbours' for nearly buried atoms: its solid angle is always
+  // evaluated in double.
+  V3<double> g[3];
+  const double om = solid_angle<double>(ld<double>(L, ks[0]), ld<double>(L, ks[1]), ld<double>(L, ks[2]), &g[0],
+                                        &g[1], &g[2], grad);
+  for (int c = 0; c < 3; ++c) acc[c] = V3<T>{T(-Si * g[c].x), T(-Si * g[c].y), T(-Si * g[c].z)};
+  for (int c = 0; c < 3; ++c) {
+    const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
+    V3<T> ge, g1, g2;
+    const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad);
+    phi[c] = (double)ph;
+    if (grad && ((extm >> ks[c]) & 1ull)) {
+      const T Se = T(L.S[ks[c]]);
+      acc[c] = acc[c] + ge * Se;
+      acc[o1] = acc[o1] + g1 * Se;
+      acc[o2] = acc[o2] + g2 * Se;
+    }
+  }
+  if (grad)
+    for (int c = 0; c < 3; ++c) {
+      acc_out[c][0] = (double)acc[c].x;
+      acc_out[c][1] = (double)acc[c].y;
+      acc_out[c][2] = (double)acc[c].z;
+    }
+  return om;
+}
+
+// One exterior K-triangle (i, a, b) at atom i, Eq. 6: S/2 = phi_ia(T_x) S_ia +
+// phi_ib(T_x) S_ib - omega_i(T_x) 4 pi w_i with T_x = (p_i, p_a, p_b, x); its
+// gradient (Eq. 7) includes the chain rule through the triple point x, whose
+// derivative follows from |x - p_m|^2 = w_m:  M dx = [(x - p_m) . dp_m]_m with
+// rows of M = (x - p_m)^T, so dS/dp_m += lambda_m (x - p_m), M^T lambda = dS/dx.
+template <typename T>
+__device__ double tri_item(const TermsLds& L, int ka, int kb, double X0, double X1, double X2, double Ri,
+                           double Si, bool grad, double G[2][3]) {
+  const V3<T> X = {T(X0), T(X1), T(X2)};
+  const V3<T> A = ld<T>(L, ka), B = ld<T>(L, kb);
+  const T Rt = T(Ri);
+  V3<T> gSa, gSb, g1e, g1u, g1v, g2e, g2u, g2v, gwa, gwb, gwx;
+  const T Sa = cap_area<T>(A, Rt, T(L.pR[ka]), &gSa, grad);
+  const T Sb = cap_area<T>(B, Rt, T(L.pR[kb]), &gSb, grad);
+  const T ph1 = dihedral<T>(A, B, X, &g1e, &g1u, &g1v, grad);  // along (i,a)
+  const T ph2 = dihedral<T>(B, A, X, &g2e, &g2u, &g2v, grad);  // along (i,b)
+  // solid angle in double, as in tet_item
+  V3<double> hwa, hwb, hwx;
+  const double om = solid_angle<double>(ld<double>(L, ka), ld<double>(L, kb), V3<double>{X0, X1, X2}, &hwa, &hwb,
+                                        &hwx, grad);
+  const double St = 2.0 * ((double)(ph1 * Sa) + (double)(ph2 * Sb) - om * Si);
+  if (grad) {
+    gwa = V3<T>{T(Si * hwa.x), T(Si * hwa.y), T(Si * hwa.z)};
+    gwb = V3<T>{T(Si * hwb.x), T(Si * hwb.y), T(Si * hwb.z)};
+    gwx = V3<T>{T(Si * hwx.x), T(Si * hwx.y), T(Si * hwx.z)};
+    V3<T> dA = g1e * Sa + gSa * ph1 + g2u * Sb - gwa;
+    V3<T> dB = g1u * Sa + g2e * Sb + gSb * ph2 - gwb;
+    const V3<T> dX = g1v * Sa + g2v * Sb - gwx;
+    const V3<T> r0 = X, r1 = X - A, r2 = X - B;
+    const V3<T> c0 = cross(r1, r2), c1 = cross(r2, r0), c2 = cross(r0, r1);
+    const T idet = T(1) / dot(r0, c0);
+    const T l1 = dot(c1, dX) * idet, l2 = dot(c2, dX) * idet;
+    dA = dA + r1 * l1;
+    dB = dB + r2 * l2;
+    G[0][0] = 2.0 * (double)dA.x, G[0][1] = 2.0 * (double)dA.y, G[0][2] = 2.0 * (double)dA.z;
+    G[1][0] = 2.0 * (double)dB.x, G[1][1] = 2.0 * (double)dB.y, G[1][2] = 2.0 * (double)dB.z;
+  }
+  return St;
+}
+
+// Conditioning of a tetrahedron seen from the origin: |a.(b x c)| / (|a||b||c|),
+// small for slivers, whose angle derivatives lose accuracy in float.
+__device__ inline double tet_quality(double ax, double ay, double az, double bx, double by, double bz, double cx,
+                                     double cy, double cz) {
+  const double tp = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+  const double l = sqrt((ax * ax + ay * ay + az * az) * (bx * bx + by * by + bz * bz) * (cx * cx + cy * cy + cz * cz));
+  return fabs(tp) / l;
+}
+
+// In MIXED precision, items below these qualities are evaluated in double.
+constexpr double kTetQualityMin = 0.05;
+constexpr double kTripleDepthMin = 0.02;  // -s_t / w_i: triple points close to the centres' plane
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   __shared__ TermsLds L;
@@ -825,30 +922,15 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
       for (int c = 0; c < 3; ++c) L.tg[t][c][0] = L.tg[t][c][1] = L.tg[t][c][2] = 0.0;
       continue;
     }
-    const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
-    V3<T> g[3], acc[3];
-    const T om = solid_angle<T>(P[0], P[1], P[2], &g[0], &g[1], &g[2], grad);
-    omega_sum += (double)om;
-    for (int c = 0; c < 3; ++c) acc[c] = g[c] * T(-Si);
-    for (int c = 0; c < 3; ++c) {
-      // dihedral along (i, ks[c]) between the faces with the other two
-      const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
-      V3<T> ge, g1, g2;
-      const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad);
-      L.phi[t][c] = (double)ph;
-      if (grad && ((extm >> ks[c]) & 1ull)) {
-        const T Se = T(L.S[ks[c]]);
-        acc[c] = acc[c] + ge * Se;
-        acc[o1] = acc[o1] + g1 * Se;
-        acc[o2] = acc[o2] + g2 * Se;
-      }
-    }
-    if (grad)
-      for (int c = 0; c < 3; ++c) {
-        L.tg[t][c][0] = (double)acc[c].x;
-        L.tg[t][c][1] = (double)acc[c].y;
-        L.tg[t][c][2] = (double)acc[c].z;
-      }
+    bool dbl = sizeof(T) == sizeof(double);
+    if (!dbl)
+      dbl = tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]], L.px[ks[2]],
+                        L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin;
+    double ph[3];
+    const double om = dbl ? tet_item<double>(L, ks, extm, Si, grad, ph, L.tg[t])
+                          : tet_item<T>(L, ks, extm, Si, grad, ph, L.tg[t]);
+    omega_sum += om;
+    L.phi[t][0] = ph[0], L.phi[t][1] = ph[1], L.phi[t][2] = ph[2];
   }
   __syncthreads();
   // edges: outer dihedral coefficient Phi = 1 - sum of the K-tet dihedral fractions
@@ -889,42 +971,20 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
     const double yx = al * ax + be * bx, yy = al * ay + be * by, yz = al * az + be * bz;
     const double s = yx * yx + yy * yy + yz * yz - wi;
     double St = 0.0;
-    V3<T> Ga = {T(0), T(0), T(0)}, Gb = {T(0), T(0), T(0)};
+    double G[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (s < 0.0) {
       const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
       const double f = sqrt(-s / (nx * nx + ny * ny + nz * nz));
-      const V3<T> X = {T(yx + f * nx), T(yy + f * ny), T(yz + f * nz)};
-      const V3<T> A = ld<T>(L, ka), B = ld<T>(L, kb);
-      V3<T> gSa, gSb, g1e, g1u, g1v, g2e, g2u, g2v, gwa, gwb, gwx;
-      const T Sa = cap_area<T>(A, Rt, T(L.pR[ka]), &gSa, grad);
-      const T Sb = cap_area<T>(B, Rt, T(L.pR[kb]), &gSb, grad);
-      const T ph1 = dihedral<T>(A, B, X, &g1e, &g1u, &g1v, grad);  // along (i,a)
-      const T ph2 = dihedral<T>(B, A, X, &g2e, &g2u, &g2v, grad);  // along (i,b)
-      const T om = solid_angle<T>(A, B, X, &gwa, &gwb, &gwx, grad);
-      const T Sw = T(Si);
-      St = 2.0 * (double)(ph1 * Sa + ph2 * Sb - om * Sw);
-      if (grad) {
-        // direct partials of S_t / 2
-        V3<T> dA = g1e * Sa + gSa * ph1 + g2u * Sb - gwa * Sw;
-        V3<T> dB = g1u * Sa + g2e * Sb + gSb * ph2 - gwb * Sw;
-        const V3<T> dX = g1v * Sa + g2v * Sb - gwx * Sw;
-        // through the triple point: M dx = [(x - p_m) . dp_m], rows x, x - a, x - b
-        const V3<T> r0 = X, r1 = X - A, r2 = X - B;
-        const V3<T> c0 = cross(r1, r2), c1 = cross(r2, r0), c2 = cross(r0, r1);
-        const T idet = T(1) / dot(r0, c0);
-        const T l1 = dot(c1, dX) * idet, l2 = dot(c2, dX) * idet;
-        dA = dA + r1 * l1;
-        dB = dB + r2 * l2;
-        const T sc = T(2.0 * ct);
-        Ga = dA * sc;
-        Gb = dB * sc;
-      }
+      const double X0 = yx + f * nx, X1 = yy + f * ny, X2 = yz + f * nz;
+      bool dbl = sizeof(T) == sizeof(double);
+      if (!dbl)
+        dbl = (-s < kTripleDepthMin * wi) || tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin;
+      St = dbl ? tri_item<double>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
+               : tri_item<T>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
     }
     area_part += ct * St;
-    if (grad) {
-      L.rg[r][0][0] = (double)Ga.x, L.rg[r][0][1] = (double)Ga.y, L.rg[r][0][2] = (double)Ga.z;
-      L.rg[r][1][0] = (double)Gb.x, L.rg[r][1][1] = (double)Gb.y, L.rg[r][1][2] = (double)Gb.z;
-    }
+    if (grad)
+      for (int c = 0; c < 3; ++c) L.rg[r][0][c] = ct * G[0][c], L.rg[r][1][c] = ct * G[1][c];
   }
   // area: Omega_i 4 pi w_i - sum Phi S + sum c S_t  (deterministic butterfly sums)
   double os = omega_sum, ap = area_part;

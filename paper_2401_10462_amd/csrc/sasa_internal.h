@@ -34,6 +34,9 @@ enum Counter {
   C_EX_EDGE,       // export cursors
   C_EX_TRI,
   C_EX_TET,
+  C_PLANE_TESTS,   // algorithmic work counters of the star kernel
+  C_NEW_VERTS,
+  C_CANDIDATES,
   C_COUNT
 };
 

@@ -183,30 +183,34 @@ def heavy_chain(n, seed):
 
 
 def add_hydrogens(xyz, radii, elements, seed):
-    """One hydrogen per heavy atom at U(1.0, 1.1) A from a random heavy parent."""
+    """One hydrogen per heavy atom at U(1.0, 1.1) A from a random heavy parent.
+
+    Up to 100 directions are tried per hydrogen; the first one at least 1.5 A
+    from every atom other than the parent (hydrogens placed so far included)
+    is kept, else the last one.
+    """
     rng = np.random.Generator(np.random.PCG64(seed + 7919))
     n = len(xyz)
-    out = [p for p in xyz]
-    tree_pts = list(xyz)
-    hs = []
     tree = cKDTree(xyz)
-    for _ in range(n):
+    grid = _Grid(1.5)
+    hs = np.zeros((n, 3))
+    for k in range(n):
         parent = int(rng.integers(0, n))
-        for _try in range(100):
-            d = rng.uniform(1.0, 1.1)
-            p = xyz[parent] + d * _unit(rng, 1)[0]
-            near = tree.query_ball_point(p, 1.5)
-            near = [j for j in near if j != parent]
-            if hs:
-                hd = np.linalg.norm(np.array(hs) - p, axis=1)
-                clash = (hd < 1.5).any()
-            else:
-                clash = False
-            if not near and not clash:
-                break
-        hs.append(p)
-        out.append(p)
-    xyz2 = np.array(out)
+        d = rng.uniform(1.0, 1.1, size=100)
+        cand = xyz[parent] + d[:, None] * _unit(rng, 100)
+        near = tree.query_ball_point(cand, 1.5)
+        pick = 99
+        for t in range(100):
+            if any(j != parent for j in near[t]):
+                continue
+            hn = grid.near(cand[t])
+            if hn and (np.linalg.norm(hs[hn] - cand[t], axis=1) < 1.5).any():
+                continue
+            pick = t
+            break
+        hs[k] = cand[pick]
+        grid.add(k, hs[k])
+    xyz2 = np.vstack([xyz, hs])
     radii2 = np.concatenate([radii, np.full(n, RADII["H"])])
     return np.ascontiguousarray(xyz2), radii2, list(elements) + ["H"] * n
 
