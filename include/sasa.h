@@ -100,6 +100,17 @@ int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const do
                        int32_t mem, void* hip_stream);
 
 /*
+ * Non-polar solvation forces: the nonpolar energy is gamma * SASA with one
+ * surface tension gamma for all atoms (Methods, "Theory and estimations for
+ * nonpolar solvation"), so F_m = -gamma d(sum_i A_i)/dp_m.  Same as
+ * sasa_compute with dA_dx scaled by -gamma in the gradient kernel.
+ *   gamma   surface tension (e.g. 0.005 kcal/mol/A^2); forces in its energy unit per A
+ *   forces  n*3 doubles out (required)
+ */
+int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* radii, double probe,
+                        double gamma, double* area, double* forces, int32_t mem, void* hip_stream);
+
+/*
  * Vector-Jacobian product of the last compute: dL_dx[m] = sum_i dL_dA[i] dA_i/dp_m
  * (n*3 doubles).  Recomputes the simplex geometry from the kept complex and the
  * coordinates of that compute; the coordinates are the context's own copy, so the
@@ -145,8 +156,20 @@ typedef struct {
   int64_t plane_tests;        /* (vertex, plane) side tests while clipping */
   int64_t new_vertices;       /* cell vertices created (three-plane solves) */
   int64_t candidates;         /* neighbour-candidate distance tests */
+  /* shader clock cycles of the star kernel's phases, summed over all wavefronts */
+  int64_t cycles_gather;      /* neighbour search in the 27 cells */
+  int64_t cycles_sort;        /* neighbour ordering and plane set-up */
+  int64_t cycles_clip;        /* power-cell clipping */
+  int64_t cycles_final;       /* star extraction, classification, stores */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
+
+/*
+ * Device bytes a context needs for a call of n atoms in total (all molecules of
+ * a batch): the admission model of a server that packs requests by HBM
+ * footprint.  Host-pointer calls add no device memory beyond this.
+ */
+int sasa_footprint(int64_t n, int64_t* bytes);
 
 /* Fixed per-atom kernel capacities: [0] overlapping neighbours, [1] cell vertices. */
 void sasa_capacity(int64_t caps[2]);

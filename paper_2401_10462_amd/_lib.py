@@ -27,8 +27,8 @@ SASA_FLAG_TIMING = 2
 
 # every entry point of include/sasa.h
 EXPORTS = (
-    "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_backward",
-    "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_capacity",
+    "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
+    "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_footprint", "sasa_capacity",
     "sasa_strerror", "sasa_last_error",
 )
 
@@ -49,7 +49,8 @@ class sasa_diag(ctypes.Structure):
         "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
         "capacity_retries", "input_errors", "overflow")] + [
         (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_terms", "ms_gather")] + [
-        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates")]
+        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "cycles_gather",
+                                            "cycles_sort", "cycles_clip", "cycles_final")]
 
 
 _lib = None
@@ -77,17 +78,21 @@ def load():
     L.sasa_destroy.restype = None
     L.sasa_compute.argtypes = [P, I64, P, P, D, P, P, I32, P]
     L.sasa_compute_batch.argtypes = [P, I32, P, P, P, D, P, P, I32, P]
+    L.sasa_compute_forces.argtypes = [P, I64, P, P, D, D, P, P, I32, P]
     L.sasa_backward.argtypes = [P, P, P, I32, P]
     L.sasa_complex_counts.argtypes = [P, P]
     L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
     L.sasa_diagnostics.argtypes = [P, ctypes.POINTER(sasa_diag), I64]
+    L.sasa_footprint.argtypes = [I64, P]
+    L.sasa_footprint.restype = ctypes.c_int
     L.sasa_capacity.argtypes = [P]
     L.sasa_capacity.restype = None
     L.sasa_strerror.argtypes = [I32]
     L.sasa_strerror.restype = ctypes.c_char_p
     L.sasa_last_error.argtypes = [P]
     L.sasa_last_error.restype = ctypes.c_char_p
-    for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_backward", "sasa_complex_counts",
+    for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
+                 "sasa_complex_counts",
                  "sasa_complex_export", "sasa_diagnostics"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -161,6 +166,14 @@ def sasa_compute_batch(ctx, offsets, xyz, radii, probe, area, dA_dx, mem=None, s
                                            ptr(radii), float(probe), ptr(area), ptr(dA_dx), mem, stream), ctx)
 
 
+def sasa_compute_forces(ctx, n, xyz, radii, probe, gamma, area, forces, mem=None, stream=None):
+    arrs = (xyz, radii, area, forces)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_compute_forces(ctx, int(n), ptr(xyz), ptr(radii), float(probe), float(gamma), ptr(area),
+                                            ptr(forces), mem, stream), ctx)
+
+
 def sasa_backward(ctx, dL_dA, dL_dx, mem=None, stream=None):
     arrs = (dL_dA, dL_dx)
     mem = mem_of(*arrs) if mem is None else mem
@@ -189,6 +202,12 @@ def sasa_diagnostics(ctx):
     d = sasa_diag()
     check(load().sasa_diagnostics(ctx, ctypes.byref(d), ctypes.sizeof(d)), ctx)
     return {f: getattr(d, f) for f, _ in d._fields_}
+
+
+def sasa_footprint(n):
+    b = np.zeros(1, np.int64)
+    check(load().sasa_footprint(int(n), ctypes.c_void_p(b.ctypes.data)))
+    return int(b[0])
 
 
 def sasa_capacity():

@@ -44,6 +44,13 @@ class SasaContext:
         _lib.sasa_compute_batch(self._h, offsets, _c(xyz), _c(radii), probe, area, dadx)
         return area, dadx
 
+    def forces(self, xyz, radii, gamma, probe=1.4):
+        """Per-atom areas and nonpolar forces F = -gamma dA/dx (one molecule)."""
+        n = xyz.shape[0]
+        area, f = self._outputs(xyz, n, True)
+        _lib.sasa_compute_forces(self._h, n, _c(xyz), _c(radii), probe, gamma, area, f)
+        return area, f
+
     def backward(self, dL_dA):
         """sum_i dL_dA[i] dA_i/dx of the last compute (geometry recomputed)."""
         n = dL_dA.shape[0]

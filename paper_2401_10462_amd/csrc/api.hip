@@ -45,6 +45,7 @@ struct Ctx {
   int nmol = 0;
   double probe = 0;
   bool pending = false;  // an async call whose counters were not read yet
+  hipStream_t last_stream = nullptr;  // stream of the last call (pending counters are read there)
   hipEvent_t ev[5] = {};  // stage boundaries (SASA_FLAG_TIMING)
   bool timed = false;     // events of the last call were recorded
   sasa_diag diag{};
@@ -151,6 +152,10 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.plane_tests = (int64_t)h[C_PLANE_TESTS];
   c->diag.new_vertices = (int64_t)h[C_NEW_VERTS];
   c->diag.candidates = (int64_t)h[C_CANDIDATES];
+  c->diag.cycles_gather = (int64_t)h[C_CYC_GATHER];
+  c->diag.cycles_sort = (int64_t)h[C_CYC_SORT];
+  c->diag.cycles_clip = (int64_t)h[C_CYC_CLIP];
+  c->diag.cycles_final = (int64_t)h[C_CYC_FINAL];
   if (c->timed) {
     float ms[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
@@ -172,7 +177,7 @@ int read_counters(Ctx* c, hipStream_t s) {
 }
 
 int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const double* radii, double probe,
-        double* area, double* dA_dx, int mem, hipStream_t s) {
+        double* area, double* dA_dx, int mem, hipStream_t s, double scale = 1.0) {
   const auto t0 = std::chrono::steady_clock::now();
   if (nmol < 0 || !offsets) return fail(c, SASA_E_INVAL, "nmol < 0 or offsets == NULL");
   if (!(probe >= 0.0) || !std::isfinite(probe)) return fail(c, SASA_E_INVAL, "probe must be finite and >= 0");
@@ -228,7 +233,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
   launch_terms(b, c->precision, dA_dx != nullptr, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
-  if (dA_dx) launch_gather(b, nullptr, out, s);
+  if (dA_dx) launch_gather(b, nullptr, out, scale, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[4], s));
   c->timed = timing;
   HIP_TRY(c, hipGetLastError());
@@ -243,6 +248,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   c->diag.n_mol = nmol;
   const bool async = (c->flags & SASA_FLAG_ASYNC) && mem == SASA_MEM_DEVICE;
   c->kept = true;
+  c->last_stream = s;
   if (async) {
     c->pending = true;
     return SASA_OK;
@@ -335,6 +341,17 @@ int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const do
   return run(c, nmol, offsets, xyz, radii, probe, area, dA_dx, mem, (hipStream_t)hip_stream);
 }
 
+int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* radii, double probe, double gamma,
+                        double* area, double* forces, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (n < 0) return fail(c, SASA_E_INVAL, "n < 0");
+  if (!std::isfinite(gamma)) return fail(c, SASA_E_INVAL, "gamma must be finite");
+  if (n > 0 && !forces) return fail(c, SASA_E_INVAL, "forces must not be NULL");
+  const int64_t off[2] = {0, n};
+  return run(c, 1, off, xyz, radii, probe, area, forces, mem, (hipStream_t)hip_stream, -gamma);
+}
+
 int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream) {
   auto* c = (Ctx*)ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
@@ -355,7 +372,7 @@ int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, vo
     out = c->out_d;
   }
   launch_terms(b, c->precision, 1, s);
-  launch_gather(b, u, out, s);
+  launch_gather(b, u, out, 1.0, s);
   HIP_TRY(c, hipGetLastError());
   if (mem == SASA_MEM_HOST && c->n) {
     HIP_TRY(c, hipMemcpyAsync(dL_dx, out, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -371,7 +388,7 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]) {
   if (!c || !counts) return fail(c, SASA_E_INVAL, "NULL argument");
   if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
   if (c->pending) {
-    int rc = read_counters(c, nullptr);
+    int rc = read_counters(c, c->last_stream);
     if (rc) return rc;
   }
   const unsigned long long* h = c->ctr_h;
@@ -440,9 +457,19 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
   auto* c = (Ctx*)ctx;
   if (!c || !out || size < 0) return fail(c, SASA_E_INVAL, "NULL argument");
   int rc = SASA_OK;
-  if (c->pending) rc = read_counters(c, nullptr);
+  if (c->pending) rc = read_counters(c, c->last_stream);
   std::memcpy(out, &c->diag, (size_t)std::min<int64_t>(size, sizeof(sasa_diag)));
   return rc;
+}
+
+int sasa_footprint(int64_t n, int64_t* bytes) {
+  if (n < 0 || !bytes) return fail(nullptr, SASA_E_INVAL, "n < 0 or bytes == NULL");
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * 4 + 1 + sizeof(int) * (KN_CAP + 3) +
+                           sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
+                           sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
+  const int64_t hb = pow2_at_least(2 * std::max<int64_t>(n, 1));
+  *bytes = n * per_atom + hb * 2 * (int64_t)sizeof(int) + 4096;
+  return SASA_OK;
 }
 
 void sasa_capacity(int64_t caps[2]) {

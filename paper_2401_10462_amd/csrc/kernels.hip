@@ -172,20 +172,17 @@ __device__ inline bool has2(unsigned p, unsigned a, unsigned b) {
 }
 
 struct StarLds {
-  int idx[NB_CAP];     // neighbour global ids, ascending
+  int idx[NB_CAP];  // neighbour global ids, slot order = clipping order (nearest plane first)
   double nx[NB_CAP], ny[NB_CAP], nz[NB_CAP], nb[NB_CAP];  // plane n = 2a, offset b
-  int order[NB_CAP];   // clipping order (nearest plane first)
-  double key[NB_CAP];
+  double key[NB_CAP];      // signed distance of each plane from p_i
   unsigned sflag[NB_CAP];  // per-slot flags (facet present, K-triangles, K-edge ...)
-  int kidx[NB_CAP];        // slot -> K-neighbour index or -1
+  int kidx[NB_CAP];        // slot -> K-neighbour index or -1; candidate ids while gathering
   double vx[V_CAP], vy[V_CAP], vz[V_CAP];
   unsigned vp[V_CAP];
-  double tx[V_CAP], ty[V_CAP], tz[V_CAP];  // staging for new vertices
-  unsigned tp[V_CAP];
   unsigned pairs[3 * V_CAP];
   unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
-  int bk[27];
-  int cand[NB_CAP];
+  int kslot[KN_CAP];        // K-edge slots in slot order
+  int bk_s0[27], bk_n[27], bk_pre[28];
 };
 
 enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
@@ -210,64 +207,100 @@ __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, 
   z = (A.b * bcz + B.b * caz + C.b * abz) * inv;
 }
 
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __shared__ StarLds L;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   if (i >= b.n) return;
+  const long long cyc0 = clock64();
   const double4 pi = b.pos[i];
   const int mi = b.mol[i];
   const double Ri = pi.w, wi = Ri * Ri;
-  const double rmax = rmax_of(b.ctr);
-  const double inv_h = 1.0 / (2.0 * rmax);
+  const double inv_h = 1.0 / (2.0 * rmax_of(b.ctr));
   const int cx = cell_coord(pi.x, inv_h), cy = cell_coord(pi.y, inv_h), cz = cell_coord(pi.z, inv_h);
 
-  // ---- 1. overlapping neighbours from the 27 surrounding cells
+  // ---- 1. overlapping neighbours from the 27 surrounding cells: all bucket
+  // ranges are read at once, then the candidates are scanned as one flat list
+  int bkv = -1, bs0 = 0, bn = 0;
   if (lane < 27) {
     const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-    L.bk[lane] = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
+    bkv = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
+    bs0 = b.start[bkv];
+    bn = b.start[bkv + 1] - bs0;
   }
+  // a bucket shared by two of the cells is scanned once (first occurrence)
+  for (int e = 0; e < 26; ++e) {
+    const int other = __shfl(bkv, e, 64);
+    if (lane < 27 && e < lane && other == bkv) bn = 0;
+  }
+  // inclusive prefix of the bucket sizes over lanes 0..26
+  int pre = bn;
+  for (int off = 1; off < 32; off <<= 1) {
+    const int t = __shfl_up(pre, off, 64);
+    if (lane >= off) pre += t;
+  }
+  if (lane < 27) {
+    L.bk_s0[lane] = bs0;
+    L.bk_n[lane] = bn;
+    L.bk_pre[lane + 1] = pre;
+  }
+  if (lane == 0) L.bk_pre[0] = 0;
+  const int total = __shfl(pre, 26, 64);
   __syncthreads();
   int nn = 0;
   bool overflow = false;
-  long long cand_tests = 0, plane_tests = 0, new_verts = 0;
-  for (int c = 0; c < 27; ++c) {
-    const int bk = L.bk[c];
-    bool dup = false;
-    for (int e = 0; e < c; ++e) dup |= (L.bk[e] == bk);  // buckets shared by two cells
-    if (dup) continue;
-    const int s0 = b.start[bk], s1 = b.start[bk + 1];
-    cand_tests += s1 - s0;
-    for (int base = s0; base < s1; base += 64) {
-      const int k = base + lane;
-      bool take = false;
-      int j = -1;
-      if (k < s1) {
-        j = b.sorted[k];
-        const double4 pj = b.spos[k];
-        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-        const double rr = Ri + pj.w;
-        take = (j != i) && (b.smol[k] == mi) && (dx * dx + dy * dy + dz * dz < rr * rr);
-      }
-      const unsigned long long m = __ballot(take);
-      const int at = nn + prefix_below(m);
-      if (take) {
-        if (at < NB_CAP) L.cand[at] = j;
-      }
-      nn += __popcll(m);
+  long long plane_tests = 0, new_verts = 0;
+  for (int base = 0; base < total; base += 64) {
+    const int f = base + lane;
+    bool take = false;
+    int j = -1;
+    double key = 0.0;
+    if (f < total) {
+      int c = 0;
+      while (L.bk_pre[c + 1] <= f) ++c;
+      const int k = L.bk_s0[c] + (f - L.bk_pre[c]);
+      j = b.sorted[k];
+      const double4 pj = b.spos[k];
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      const double rr = Ri + pj.w;
+      take = (j != i) && (b.smol[k] == mi) && (d2 < rr * rr);
+      // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
+      // neighbour at the same centre has no plane (it empties the cell or
+      // cuts nothing) and goes first
+      key = d2 > 0.0 ? (d2 + wi - pj.w * pj.w) / (2.0 * sqrt(d2)) : -1e300;
     }
+    const unsigned long long m = __ballot(take);
+    if (take) {
+      const int at = nn + prefix_below(m);
+      if (at < NB_CAP) {
+        L.kidx[at] = j;
+        L.key[at] = key;
+      }
+    }
+    nn += __popcll(m);
   }
   if (nn > NB_CAP) {
     overflow = true;
     nn = NB_CAP;
   }
   __syncthreads();
-  // sort neighbours by global id (rank counting), then build the planes
+  const long long cyc1 = clock64();
+  // ---- slots in clipping order: nearest plane first, ties by atom id
   for (int s = lane; s < nn; s += 64) {
-    const int me = L.cand[s];
+    const double me = L.key[s];
+    const int id = L.kidx[s];
     int rank = 0;
-    for (int t = 0; t < nn; ++t) rank += (L.cand[t] < me);
-    L.idx[rank] = me;
+    for (int t = 0; t < nn; ++t) {
+      const double o = L.key[t];
+      rank += (o < me) || (o == me && L.kidx[t] < id);
+    }
+    L.idx[rank] = id;
   }
   __syncthreads();
   for (int s = lane; s < nn; s += 64) {
@@ -278,51 +311,37 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     L.ny[s] = 2.0 * ay;
     L.nz[s] = 2.0 * az;
     L.nb[s] = a2 - pj.w * pj.w + wi;
-    L.key[s] = L.nb[s] / (2.0 * sqrt(a2));  // distance of the radical plane from p_i
+    L.key[s] = a2 > 0.0 ? L.nb[s] / (2.0 * sqrt(a2)) : -1e300;
     L.sflag[s] = 0u;
     L.kidx[s] = -1;
   }
-  __syncthreads();
-  for (int s = lane; s < nn; s += 64) {
-    const double me = L.key[s];
-    int rank = 0;
-    for (int t = 0; t < nn; ++t) {
-      const double o = L.key[t];
-      rank += (o < me) || (o == me && t < s);
-    }
-    L.order[rank] = s;
-  }
+  const long long cyc2 = clock64();
 
-  // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by every plane
+  // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
+  // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
+  // registers; LDS holds the cell only across a cut.
   const double half = 1.1 * Ri;
   int nv = 8;
+  double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+  unsigned p0 = 0, p1 = 0;
   if (lane < 8) {
-    const unsigned px = (lane & 1) ? 1u : 0u, py = (lane & 2) ? 3u : 2u, pz = (lane & 4) ? 5u : 4u;
-    L.vx[lane] = (lane & 1) ? -half : half;
-    L.vy[lane] = (lane & 2) ? -half : half;
-    L.vz[lane] = (lane & 4) ? -half : half;
-    L.vp[lane] = px | (py << 10) | (pz << 20);
+    x0 = (lane & 1) ? -half : half;
+    y0 = (lane & 2) ? -half : half;
+    z0 = (lane & 4) ? -half : half;
+    p0 = ((lane & 1) ? 1u : 0u) | (((lane & 2) ? 3u : 2u) << 10) | (((lane & 4) ? 5u : 4u) << 20);
   }
-  __syncthreads();
+  double rho2 = 3.0 * half * half;  // largest |v|^2 of the current cell
   bool empty = false;
   int vmax = 8;
+  __syncthreads();
   for (int k = 0; k < nn && !overflow; ++k) {
-    const int q = L.order[k];
-    const unsigned pid = 6u + (unsigned)q;
-    const double qx = L.nx[q], qy = L.ny[q], qz = L.nz[q], qb = L.nb[q];
-    // my vertices
-    const int v0 = lane, v1 = lane + 64;
-    double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
-    unsigned p0 = 0, p1 = 0;
-    bool r0 = false, r1 = false;
-    if (v0 < nv) {
-      x0 = L.vx[v0], y0 = L.vy[v0], z0 = L.vz[v0], p0 = L.vp[v0];
-      r0 = qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
-    }
-    if (v1 < nv) {
-      x1 = L.vx[v1], y1 = L.vy[v1], z1 = L.vz[v1], p1 = L.vp[v1];
-      r1 = qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
-    }
+    const double qx = L.nx[k], qy = L.ny[k], qz = L.nz[k], qb = L.nb[k];
+    const double key = L.key[k];
+    // security radius: no later plane (farther from p_i) can reach the cell;
+    // the margin covers the last-bit differences between the sort key and this one
+    if (key >= 0.0 && key * key >= rho2 * (1.0 + 1e-9) + 1e-12) break;
+    const bool r0 = lane < nv && qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
+    const bool r1 = lane + 64 < nv && qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
     plane_tests += nv;
     const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
     const int nr0 = __popcll(m0);
@@ -332,6 +351,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       empty = true;
       break;
     }
+    const unsigned pid = 6u + (unsigned)k;
     // removed vertices list their three edges (plane pairs)
     if (r0) {
       const int rk = prefix_below(m0);
@@ -346,7 +366,20 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       L.pairs[3 * rk + 2] = pid0(p1) | (pid1(p1) << 10);
     }
     __syncthreads();
-    // an edge with exactly one removed end crosses the plane: new vertex on it
+    const int nkeep = nv - nrem;
+    // kept vertices move to their compacted slots (old LDS contents are dead:
+    // every lane holds its vertices in registers)
+    const unsigned long long k0 = __ballot(lane < nv && !r0), k1 = __ballot(lane + 64 < nv && !r1);
+    if (lane < nv && !r0) {
+      const int d = prefix_below(k0);
+      L.vx[d] = x0, L.vy[d] = y0, L.vz[d] = z0, L.vp[d] = p0;
+    }
+    if (lane + 64 < nv && !r1) {
+      const int d = __popcll(k0) + prefix_below(k1);
+      L.vx[d] = x1, L.vy[d] = y1, L.vz[d] = z1, L.vp[d] = p1;
+    }
+    // an edge with exactly one removed end crosses the plane: new vertex on it,
+    // solved from its three planes in ascending id order (canonical)
     const int ne = 3 * nrem;
     int ncross = 0;
     for (int base = 0; base < ne; base += 64) {
@@ -361,50 +394,50 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       }
       const unsigned long long cm = __ballot(cross);
       if (cross) {
-        const int slot = ncross + prefix_below(cm);
+        const int slot = nkeep + ncross + prefix_below(cm);
         if (slot < V_CAP) {
-          const unsigned a = pr & 1023u, bb = pr >> 10;
+          const unsigned tri3 = pack3(pr & 1023u, pr >> 10, pid);
           double x, y, z;
-          solve3(plane_of(L, a, half), plane_of(L, bb, half), Pl{qx, qy, qz, qb}, x, y, z);
-          L.tx[slot] = x;
-          L.ty[slot] = y;
-          L.tz[slot] = z;
-          L.tp[slot] = pack3(a, bb, pid);
+          solve3(plane_of(L, pid0(tri3), half), plane_of(L, pid1(tri3), half), plane_of(L, pid2(tri3), half), x,
+                 y, z);
+          L.vx[slot] = x;
+          L.vy[slot] = y;
+          L.vz[slot] = z;
+          L.vp[slot] = tri3;
         }
       }
       ncross += __popcll(cm);
     }
-    const int nkeep = nv - nrem;
     new_verts += ncross;
-    if (nkeep + ncross > V_CAP) {
+    nv = nkeep + ncross;
+    if (nv > V_CAP) {
       overflow = true;
       break;
     }
-    __syncthreads();
-    // compact kept vertices, append the new ones
-    const unsigned long long k0 = __ballot(v0 < nv && !r0), k1 = __ballot(v1 < nv && !r1);
-    if (v0 < nv && !r0) {
-      const int d = prefix_below(k0);
-      L.vx[d] = x0, L.vy[d] = y0, L.vz[d] = z0, L.vp[d] = p0;
-    }
-    if (v1 < nv && !r1) {
-      const int d = __popcll(k0) + prefix_below(k1);
-      L.vx[d] = x1, L.vy[d] = y1, L.vz[d] = z1, L.vp[d] = p1;
-    }
-    for (int t = lane; t < ncross; t += 64) {
-      L.vx[nkeep + t] = L.tx[t];
-      L.vy[nkeep + t] = L.ty[t];
-      L.vz[nkeep + t] = L.tz[t];
-      L.vp[nkeep + t] = L.tp[t];
-    }
-    nv = nkeep + ncross;
     vmax = max(vmax, nv);
     __syncthreads();
+    x0 = y0 = z0 = x1 = y1 = z1 = 0.0;
+    p0 = p1 = 0u;
+    double r2 = 0.0;
+    if (lane < nv) {
+      x0 = L.vx[lane], y0 = L.vy[lane], z0 = L.vz[lane], p0 = L.vp[lane];
+      r2 = x0 * x0 + y0 * y0 + z0 * z0;
+    }
+    if (lane + 64 < nv) {
+      x1 = L.vx[lane + 64], y1 = L.vy[lane + 64], z1 = L.vz[lane + 64], p1 = L.vp[lane + 64];
+      r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
+    }
+    rho2 = wave_max(r2);
+    __syncthreads();  // the next cut overwrites pairs / vertices only after everyone has read
   }
+  const long long cyc3 = clock64();
   if (lane == 0) {
+    atomicAdd(&b.ctr[C_CYC_GATHER], (unsigned long long)(cyc1 - cyc0));
+    atomicAdd(&b.ctr[C_CYC_SORT], (unsigned long long)(cyc2 - cyc1));
+    atomicAdd(&b.ctr[C_CYC_CLIP], (unsigned long long)(cyc3 - cyc2));
     atomicMax(&b.ctr[C_MAX_NB], (unsigned long long)nn);
     atomicMax(&b.ctr[C_MAX_V], (unsigned long long)vmax);
-    atomicAdd(&b.ctr[C_CANDIDATES], (unsigned long long)cand_tests);
+    atomicAdd(&b.ctr[C_CANDIDATES], (unsigned long long)total);
     atomicAdd(&b.ctr[C_PLANE_TESTS], (unsigned long long)plane_tests);
     atomicAdd(&b.ctr[C_NEW_VERTS], (unsigned long long)new_verts);
   }
@@ -419,21 +452,19 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     return;
   }
   if (empty) nv = 0;
+  if (lane >= nv) x0 = y0 = z0 = 0.0, p0 = 0u;
+  if (lane + 64 >= nv) x1 = y1 = z1 = 0.0, p1 = 0u;
 
   // ---- 3. the star: K-tetrahedra (cell vertices in B_i), K-triangles (cell
   // edges meeting B_i), K-edges (facets meeting B_i)
   int ties = 0;
   bool in0 = false, in1 = false;
-  unsigned p0 = 0, p1 = 0;
-  double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
   if (lane < nv) {
-    x0 = L.vx[lane], y0 = L.vy[lane], z0 = L.vz[lane], p0 = L.vp[lane];
     const double m = x0 * x0 + y0 * y0 + z0 * z0 - wi;
     in0 = m <= 0.0 && pid0(p0) >= 6;
     ties += fabs(m) < kNearTie;
   }
   if (lane + 64 < nv) {
-    x1 = L.vx[lane + 64], y1 = L.vy[lane + 64], z1 = L.vz[lane + 64], p1 = L.vp[lane + 64];
     const double m = x1 * x1 + y1 * y1 + z1 * z1 - wi;
     in1 = m <= 0.0 && pid0(p1) >= 6;
     ties += fabs(m) < kNearTie;
@@ -507,6 +538,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     }
   }
   ntri = min(ntri, 2 * V_CAP);
+  __syncthreads();
   // facets without a K-triangle: K-edge iff the disk centre lies in the cell
   for (int s = lane; s < nn; s += 64) {
     unsigned f = L.sflag[s];
@@ -537,21 +569,29 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   for (int s = lane; s < nn; s += 64) origin_in &= L.nb[s] >= 0.0;
   origin_in = __ballot(!origin_in) == 0ull;
   __syncthreads();
-  // K-neighbour indices (slot order = ascending global id)
+  // K-edges in slot order, then K-neighbour indices by ascending atom id
   int nk = 0;
-  unsigned long long extmask = 0ull;
   for (int base = 0; base < nn; base += 64) {
     const int s = base + lane;
-    const unsigned f = s < nn ? L.sflag[s] : 0u;
-    const bool ke = (f & SF_KEDGE) != 0;
+    const bool ke = s < nn && (L.sflag[s] & SF_KEDGE);
     const unsigned long long m = __ballot(ke);
     if (ke) {
       const int kk = nk + prefix_below(m);
-      L.kidx[s] = kk;
-      if (kk < KN_CAP) b.knbr[(size_t)i * KN_CAP + kk] = L.idx[s];
-      if ((f & SF_EXTEDGE) && kk < 64) extmask |= 1ull << kk;
+      if (kk < KN_CAP) L.kslot[kk] = s;
     }
     nk += __popcll(m);
+  }
+  __syncthreads();
+  unsigned long long extmask = 0ull;
+  if (lane < nk && lane < KN_CAP) {
+    const int s = L.kslot[lane];
+    const int id = L.idx[s];
+    int rank = 0;
+    const int lim = min(nk, KN_CAP);
+    for (int t = 0; t < lim; ++t) rank += L.idx[L.kslot[t]] < id;
+    L.kidx[s] = rank;
+    b.knbr[(size_t)i * KN_CAP + rank] = id;
+    if (L.sflag[s] & SF_EXTEDGE) extmask = 1ull << rank;
   }
   {
     unsigned lo = (unsigned)extmask, hi = (unsigned)(extmask >> 32);
@@ -582,10 +622,15 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     if (ka < 0 || kb < 0 || kc < 0 || ka >= KN_CAP || kb >= KN_CAP || kc >= KN_CAP) bad_lane = true;
     else if (at < KT_CAP)
       b.ktet[(size_t)i * KT_CAP + at] = (unsigned)ka | ((unsigned)kb << 8) | ((unsigned)kc << 16);
-    const int ja = L.idx[sa], jb = L.idx[sb], jc = L.idx[sc];
+    int ja = L.idx[sa], jb = L.idx[sb], jc = L.idx[sc];
     if (i < ja && i < jb && i < jc) {
       ++own_tet;
       if (b.export_on) {
+        // ascending ids
+        int t;
+        if (ja > jb) t = ja, ja = jb, jb = t;
+        if (jb > jc) t = jb, jb = jc, jc = t;
+        if (ja > jb) t = ja, ja = jb, jb = t;
         const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_TET], 1ull);
         if ((int64_t)at2 < b.ex_cap_q) {
           int* o = b.ex_tets + 4 * at2;
@@ -678,6 +723,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     if (own_edge) atomicAdd(&b.ctr[C_EDGE], (unsigned long long)own_edge);
     if (own_ext_edge) atomicAdd(&b.ctr[C_EXT_EDGE], (unsigned long long)own_ext_edge);
     if (ties) atomicAdd(&b.ctr[C_NEAR_TIE], (unsigned long long)ties);
+    atomicAdd(&b.ctr[C_CYC_FINAL], (unsigned long long)(clock64() - cyc3));
   }
 }
 
@@ -1028,7 +1074,7 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
 }
 
 // ------------------------------------------------------------------ gather
-__global__ void k_gather(Bufs b, const double* u, double* out) {
+__global__ void k_gather(Bufs b, const double* u, double* out, double scale) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= b.n) return;
   double gx = 0, gy = 0, gz = 0;
@@ -1063,9 +1109,9 @@ __global__ void k_gather(Bufs b, const double* u, double* out) {
     const double* row = b.rows + ((size_t)i * ROW + s) * 3;
     gx += ui * row[0], gy += ui * row[1], gz += ui * row[2];
   }
-  out[3 * m] = gx;
-  out[3 * m + 1] = gy;
-  out[3 * m + 2] = gz;
+  out[3 * m] = scale * gx;
+  out[3 * m + 1] = scale * gy;
+  out[3 * m + 2] = scale * gz;
   if (lost) atomicAdd(&b.ctr[C_LOST_PAIR], (unsigned long long)lost);
 }
 
@@ -1108,8 +1154,8 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
   if (precision == 1) k_terms<float><<<b.n, 64, 0, s>>>(b, with_grad);
   else k_terms<double><<<b.n, 64, 0, s>>>(b, with_grad);
 }
-void launch_gather(const Bufs& b, const double* u, double* out, hipStream_t s) {
-  if (b.n) k_gather<<<blocks(b.n, 256), 256, 0, s>>>(b, u, out);
+void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s) {
+  if (b.n) k_gather<<<blocks(b.n, 256), 256, 0, s>>>(b, u, out, scale);
 }
 
 }  // namespace sasa

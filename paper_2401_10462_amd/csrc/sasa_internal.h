@@ -37,6 +37,10 @@ enum Counter {
   C_PLANE_TESTS,   // algorithmic work counters of the star kernel
   C_NEW_VERTS,
   C_CANDIDATES,
+  C_CYC_GATHER,    // shader cycles per star phase, summed over waves
+  C_CYC_SORT,
+  C_CYC_CLIP,
+  C_CYC_FINAL,
   C_COUNT
 };
 
@@ -91,7 +95,7 @@ void launch_scan(const Bufs& b, hipStream_t s);
 void launch_scatter(const Bufs& b, hipStream_t s);
 void launch_star(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
-void launch_gather(const Bufs& b, const double* u, double* out, hipStream_t s);
+void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int scan_blocks(unsigned hb);
 

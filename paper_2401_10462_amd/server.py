@@ -1,0 +1,207 @@
+"""Continuous-batching SASA + gradient server on one GPU.
+
+Requests (one molecule each: coordinates, radii) are queued as they arrive.  A
+scheduler thread owns ``slots`` library contexts, each with its own HIP stream
+and device buffers.  Whenever a slot is free it admits queued requests in
+arrival order while their summed device footprint (``sasa_footprint``) stays
+within the slot's HBM budget, packs them into one batch (one segment per
+molecule, so no atom of one request ever sees another's), and launches the
+whole path asynchronously on the slot's stream.  Slots overlap on the device;
+a finished slot's results are split back per request and the slot admits the
+next requests right away, so requests that arrive while others run are
+served as soon as a slot and memory free up.
+
+``SasaServer(..., slots=1, max_requests_per_batch=1)`` is the plain form: one
+molecule per launch sequence, first in first out.
+"""
+import collections
+import queue
+import threading
+import time
+from concurrent.futures import Future
+
+import numpy as np
+import torch
+
+from . import _lib
+from .context import SasaContext
+
+
+class Request:
+    __slots__ = ("xyz", "radii", "future", "arrival", "t_admit", "t_done", "n")
+
+    def __init__(self, xyz, radii, arrival):
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        self.radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+        if self.xyz.shape[0] != self.radii.shape[0]:
+            raise ValueError("xyz and radii disagree on the atom count")
+        self.n = self.radii.shape[0]
+        self.future = Future()
+        self.arrival = arrival
+        self.t_admit = None
+        self.t_done = None
+
+
+class _Slot:
+    def __init__(self, device, precision, max_atoms, probe):
+        self.ctx = SasaContext(device=device, precision=precision, max_atoms=max_atoms, async_calls=True)
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.event = torch.cuda.Event()
+        self.reqs = []
+        self.probe = probe
+        self.device = device
+        self.host_out = None
+        self.area = None
+        self.grad = None
+
+    def launch(self, reqs):
+        self.reqs = reqs
+        n = sum(r.n for r in reqs)
+        offs = np.zeros(len(reqs) + 1, np.int64)
+        offs[1:] = np.cumsum([r.n for r in reqs])
+        xyz = torch.from_numpy(np.concatenate([r.xyz for r in reqs])).pin_memory()
+        rad = torch.from_numpy(np.concatenate([r.radii for r in reqs])).pin_memory()
+        with torch.cuda.stream(self.stream):
+            X = xyz.to(self.device, non_blocking=True)
+            R = rad.to(self.device, non_blocking=True)
+            area, grad = self.ctx.compute_batch(offs, X, R, self.probe, grad=True)
+            self.host_out = (torch.empty(n, dtype=torch.float64, pin_memory=True),
+                             torch.empty((n, 3), dtype=torch.float64, pin_memory=True))
+            self.host_out[0].copy_(area, non_blocking=True)
+            self.host_out[1].copy_(grad, non_blocking=True)
+            self.event.record(self.stream)
+        # keep the staging alive until the event completes
+        self._keep = (xyz, rad, X, R, area, grad, offs)
+
+    def done(self):
+        return self.event.query()
+
+    def close(self):
+        self.ctx.close()
+
+    def finish(self):
+        self.event.synchronize()
+        diag = self.ctx.diagnostics()  # raises on capacity / input errors of this batch
+        a, g = self.host_out[0].numpy(), self.host_out[1].numpy()
+        t = time.perf_counter()
+        o = 0
+        for r in self.reqs:
+            r.t_done = t
+            r.future.set_result((a[o:o + r.n].copy(), g[o:o + r.n].copy()))
+            o += r.n
+        reqs, self.reqs, self._keep = self.reqs, [], None
+        return reqs, diag
+
+
+class SasaServer:
+    """Continuous batching over ``slots`` concurrent streams.
+
+    slot_budget_bytes: HBM footprint one slot may use (admission limit); a
+    request larger than the budget is run alone.
+    """
+
+    def __init__(self, device=0, precision="mixed", slots=3, slot_budget_bytes=2 << 30, probe=1.4,
+                 max_requests_per_batch=None, slot_factory=None):
+        self.device = device
+        self.budget = slot_budget_bytes
+        self.max_req = max_requests_per_batch
+        per_atom = _lib.sasa_footprint(1_000_000) / 1_000_000
+        self.max_atoms = int(slot_budget_bytes / per_atom)
+        make = slot_factory or (lambda: _Slot(device, precision, self.max_atoms, probe))
+        self._slots = [make() for _ in range(slots)]
+        self._cuda = slot_factory is None
+        self._q = collections.deque()
+        self._inbox = queue.SimpleQueue()
+        self._stop = threading.Event()
+        self._wake = threading.Event()
+        self._thread = None
+        self.completed = []
+        self.errors = []
+        self.batches = 0
+
+    # ---------------------------------------------------------------- API
+    def submit(self, xyz, radii, arrival=None):
+        r = Request(xyz, radii, time.perf_counter() if arrival is None else arrival)
+        self._inbox.put(r)
+        self._wake.set()
+        return r.future
+
+    def start(self):
+        self._thread = threading.Thread(target=self._loop, name="sasa-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, drain=True):
+        if drain:
+            while not (self._inbox.empty() and not self._q and all(not s.reqs for s in self._slots)):
+                time.sleep(1e-3)
+        self._stop.set()
+        self._wake.set()
+        if self._thread:
+            self._thread.join()
+        for s in self._slots:
+            s.close()
+
+    def __enter__(self):
+        return self.start()
+
+    def __exit__(self, *exc):
+        self.stop(drain=exc[0] is None)
+
+    # ----------------------------------------------------------- scheduler
+    def _admit(self):
+        """Requests for one batch: FIFO while the footprint fits the slot budget."""
+        batch, atoms = [], 0
+        while self._q:
+            r = self._q[0]
+            need = _lib.sasa_footprint(atoms + r.n)
+            if batch and (need > self.budget or (self.max_req and len(batch) >= self.max_req)):
+                break
+            batch.append(self._q.popleft())
+            atoms += r.n
+            if self.max_req and len(batch) >= self.max_req:
+                break
+        return batch
+
+    def _loop(self):
+        if self._cuda:
+            torch.cuda.set_device(self.device)
+        while not self._stop.is_set():
+            while not self._inbox.empty():
+                self._q.append(self._inbox.get())
+            progressed = False
+            for s in self._slots:
+                if s.reqs and s.done():
+                    try:
+                        reqs, _ = s.finish()
+                        self.completed.extend(reqs)
+                    except Exception as e:  # deliver the error to every request of the batch
+                        for r in s.reqs:
+                            r.future.set_exception(e)
+                        self.errors.append(e)
+                        s.reqs = []
+                    progressed = True
+            for s in self._slots:
+                if not s.reqs and self._q:
+                    batch = self._admit()
+                    now = time.perf_counter()
+                    for r in batch:
+                        r.t_admit = now
+                    s.launch(batch)
+                    self.batches += 1
+                    progressed = True
+            if not progressed:
+                if any(s.reqs for s in self._slots):
+                    time.sleep(2e-5)
+                else:
+                    self._wake.wait(timeout=1e-3)
+                    self._wake.clear()
+
+
+def latency_stats(reqs):
+    """p50 / p99 latency (ms) from arrival to result, and atoms/s over the span."""
+    lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs])
+    atoms = sum(r.n for r in reqs)
+    span = max(r.t_done for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "atoms": atoms, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "atoms_per_s": atoms / span, "span_s": span}
