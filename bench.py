@@ -43,7 +43,68 @@ def parse():
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--batch", type=int, default=32, help="molecules in the batched form (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU leg (0: skip)")
+    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md"],
+                   help="globule: the headline line; serving: Poisson stream sweep; md: MD-like frames")
+    p.add_argument("--serve-requests", type=int, default=600, help="requests per arrival rate (serving)")
+    p.add_argument("--rates", default="100,500,2000,5000", help="arrival rates, req/s (serving)")
+    p.add_argument("--md-atoms", type=int, default=20000)
+    p.add_argument("--frames", type=int, default=500)
+    p.add_argument("--calibrate-copy", type=int, default=0,
+                   help="MiB: only run a device copy of this size (HBM counter calibration) and exit")
     return p.parse_args()
+
+
+def pool_molecules(sizes, seed=40_000):
+    """Request molecules: the first n atoms of pooled globule chains, randomly rotated."""
+    from synth.globule import heavy_chain
+    top = max(sizes)
+    levels = sorted(set(int(round(x)) for x in np.geomspace(200, top, 7)))
+    levels[-1] = top
+    pool = [heavy_chain(n, seed + k)[:2] for k, n in enumerate(levels)]
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        k = next(k for k, m in enumerate(levels) if m >= n)
+        x, r = pool[k]
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        out.append((np.ascontiguousarray(x[:n] @ q.T), np.ascontiguousarray(r[:n])))
+    return out
+
+
+def serving(args, precision):
+    """Poisson stream of requests, batched server vs plain (one molecule per launch)."""
+    from paper_2401_10462_amd.server import SasaServer, poisson_run
+    rng = np.random.default_rng(4)
+    nreq = args.serve_requests
+    sizes = np.round(np.exp(rng.uniform(np.log(200), np.log(20000), size=nreq))).astype(int)
+    reqs = pool_molecules(sizes)
+    rates = [float(x) for x in args.rates.split(",")]
+    res = {"requests_per_rate": nreq, "mean_atoms": float(sizes.mean()), "rates": []}
+    for rate in rates:
+        row = {"rate_req_s": rate}
+        for name, kw in (("batched", dict(slots=3, slot_budget_bytes=1 << 30)),
+                         ("plain", dict(slots=1, max_requests_per_batch=1, slot_budget_bytes=1 << 30))):
+            with SasaServer(precision=precision, **kw) as srv:
+                srv.submit(*reqs[0]).result()  # warm-up
+                st = poisson_run(srv, reqs, rate, seed=int(rate))
+                st["batches"] = srv.batches - 1
+            row[name] = st
+        res["rates"].append(row)
+        print(json.dumps({"serving_rate": rate, "batched": row["batched"], "plain": row["plain"]}), file=sys.stderr)
+    return res
+
+
+def md(args, precision):
+    """Config: a globule, cumulative Gaussian moves, SASA + forces every frame, state on the device."""
+    from paper_2401_10462_amd.md_loop import md_loop
+    from synth.globule import heavy_chain
+    xyz, rad, _ = heavy_chain(args.md_atoms, 3)
+    lat, _ = md_loop(xyz, rad, frames=min(args.warmup, 5), precision=precision)
+    lat, kept = md_loop(xyz, rad, frames=args.frames, precision=precision, keep_frames=(0, args.frames - 1))
+    lat = np.array(lat)
+    return {"atoms": len(rad), "frames": args.frames, "frames_per_s": 1e3 / lat.mean(),
+            "atoms_per_s": len(rad) * 1e3 / lat.mean(), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "gamma": 0.005, "sigma": 0.02}
 
 
 def cpu_baseline(xyz, rad, budget):
@@ -73,6 +134,22 @@ def main():
 
     from paper_2401_10462_amd import SasaContext
     from synth.globule import globule
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+        return
+    if args.workload == "serving":
+        print(json.dumps({"workload": "serving", "precision": args.precision, **serving(args, args.precision)}))
+        return
+    if args.workload == "md":
+        print(json.dumps({"workload": "md", "precision": args.precision, **md(args, args.precision)}))
+        return
 
     xyz, rad = globule(args.heavy, args.seed, hydrogens=True)
     n = len(rad)

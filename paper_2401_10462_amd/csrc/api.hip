@@ -94,7 +94,8 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&b.bucket, cap));
     HIP_TRY(c, grow(&b.sorted, cap));
     HIP_TRY(c, grow(&b.spos, cap));
-    HIP_TRY(c, grow(&b.smol, cap));
+    HIP_TRY(c, grow(&b.cell, cap));
+    HIP_TRY(c, grow(&b.scell, cap));
     HIP_TRY(c, grow(&b.vflag, cap));
     HIP_TRY(c, grow(&b.kn_cnt, cap));
     HIP_TRY(c, grow(&b.knbr, cap * KN_CAP));
@@ -313,7 +314,7 @@ void sasa_destroy(void* ctx) {
   hipDeviceSynchronize();
   Bufs& b = c->b;
   void* dev[] = {b.pos,  b.mol,   b.bucket,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
-                 b.smol, b.vflag, b.kn_cnt,   b.knbr,     b.kn_ext, b.kt_cnt,   b.ktet,   b.ktr_cnt,
+                 b.cell, b.scell, b.vflag, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet,   b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
@@ -464,7 +465,7 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
 
 int sasa_footprint(int64_t n, int64_t* bytes) {
   if (n < 0 || !bytes) return fail(nullptr, SASA_E_INVAL, "n < 0 or bytes == NULL");
-  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * 4 + 1 + sizeof(int) * (KN_CAP + 3) +
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int4) * 2 + sizeof(int) * 3 + 1 + sizeof(int) * (KN_CAP + 3) +
                            sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
                            sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
   const int64_t hb = pow2_at_least(2 * std::max<int64_t>(n, 1));

@@ -75,11 +75,12 @@ __global__ void k_prep(Bufs b) {
 __global__ void k_buckets(Bufs b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= b.n) return;
-  const double inv_h = 1.0 / (2.0 * rmax_of(b.ctr));
+  const double inv_h = 1.0 / rmax_of(b.ctr);  // cell side R_max
   const double4 p = b.pos[i];
-  const unsigned k = cell_hash(b.mol[i], cell_coord(p.x, inv_h), cell_coord(p.y, inv_h), cell_coord(p.z, inv_h),
-                               b.hb_mask);
+  const int cx = cell_coord(p.x, inv_h), cy = cell_coord(p.y, inv_h), cz = cell_coord(p.z, inv_h);
+  const unsigned k = cell_hash(b.mol[i], cx, cy, cz, b.hb_mask);
   b.bucket[i] = (int)k;
+  b.cell[i] = make_int4(cx, cy, cz, b.mol[i]);
   atomicAdd(&b.cnt[k], 1);
 }
 
@@ -140,7 +141,7 @@ __global__ void k_scatter(Bufs b) {
   const int slot = b.start[k] + atomicSub(&b.cnt[k], 1) - 1;
   b.sorted[slot] = i;
   b.spos[slot] = b.pos[i];
-  b.smol[slot] = b.mol[i];
+  b.scell[slot] = b.cell[i];
 }
 
 // ------------------------------------------------------------------ star
@@ -182,7 +183,7 @@ struct StarLds {
   unsigned pairs[3 * V_CAP];
   unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
   int kslot[KN_CAP];        // K-edge slots in slot order
-  int bk_s0[27], bk_n[27], bk_pre[28];
+  int bk_s0[128], bk_pre[129];  // first candidate and prefix count of the stencil's cells
 };
 
 enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
@@ -214,76 +215,106 @@ __device__ inline double wave_max(double v) {
 
 __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __shared__ StarLds L;
-  const int i = blockIdx.x;
+  if ((int)blockIdx.x >= b.n) return;
+  const int i = b.sorted[blockIdx.x];  // bucket order: neighbouring blocks share neighbours in cache
   const int lane = threadIdx.x;
-  if (i >= b.n) return;
   const long long cyc0 = clock64();
   const double4 pi = b.pos[i];
   const int mi = b.mol[i];
   const double Ri = pi.w, wi = Ri * Ri;
-  const double inv_h = 1.0 / (2.0 * rmax_of(b.ctr));
+  const double rmax = rmax_of(b.ctr);
+  const double h = rmax, inv_h = 1.0 / rmax;  // cell side R_max
   const int cx = cell_coord(pi.x, inv_h), cy = cell_coord(pi.y, inv_h), cz = cell_coord(pi.z, inv_h);
 
-  // ---- 1. overlapping neighbours from the 27 surrounding cells: all bucket
-  // ranges are read at once, then the candidates are scanned as one flat list
-  int bkv = -1, bs0 = 0, bn = 0;
-  if (lane < 27) {
-    const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-    bkv = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
-    bs0 = b.start[bkv];
-    bn = b.start[bkv + 1] - bs0;
+  // ---- 1. overlapping neighbours: the 5 x 5 x 5 cells around i's cell, minus
+  // those whose box is farther than R_i + R_max from p_i.  Each cell's bucket
+  // range is read at once (two cells per lane); candidates are then scanned as
+  // one flat list and kept only if they belong to the scanned cell (a bucket
+  // shared by several cells is read for each, but every atom is taken once).
+  const double reach = Ri + rmax, reach2 = reach * reach;
+  int c_s0[2] = {0, 0}, c_n[2] = {0, 0};
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int c = lane + 64 * h2;
+    if (c < 125) {
+      const int dx = c % 5 - 2, dy = (c / 5) % 5 - 2, dz = c / 25 - 2;
+      double dd = 0.0;
+      const double lo[3] = {(cx + dx) * h, (cy + dy) * h, (cz + dz) * h};
+      const double pp[3] = {pi.x, pi.y, pi.z};
+      for (int a3 = 0; a3 < 3; ++a3) {
+        const double t = pp[a3] < lo[a3] ? lo[a3] - pp[a3] : (pp[a3] > lo[a3] + h ? pp[a3] - lo[a3] - h : 0.0);
+        dd += t * t;
+      }
+      if (dd < reach2) {
+        const int bk = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
+        c_s0[h2] = b.start[bk];
+        c_n[h2] = b.start[bk + 1] - c_s0[h2];
+      }
+    }
   }
-  // a bucket shared by two of the cells is scanned once (first occurrence)
-  for (int e = 0; e < 26; ++e) {
-    const int other = __shfl(bkv, e, 64);
-    if (lane < 27 && e < lane && other == bkv) bn = 0;
+  // inclusive prefix over cells 0..127 (lane, then lane + 64)
+  int pre0 = c_n[0], pre1 = c_n[1];
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t0 = __shfl_up(pre0, off, 64), t1 = __shfl_up(pre1, off, 64);
+    if (lane >= off) pre0 += t0, pre1 += t1;
   }
-  // inclusive prefix of the bucket sizes over lanes 0..26
-  int pre = bn;
-  for (int off = 1; off < 32; off <<= 1) {
-    const int t = __shfl_up(pre, off, 64);
-    if (lane >= off) pre += t;
-  }
-  if (lane < 27) {
-    L.bk_s0[lane] = bs0;
-    L.bk_n[lane] = bn;
-    L.bk_pre[lane + 1] = pre;
+  const int tot0 = __shfl(pre0, 63, 64);
+  pre1 += tot0;
+  L.bk_s0[lane] = c_s0[0];
+  L.bk_pre[lane + 1] = pre0;
+  if (lane + 64 < 128) {
+    L.bk_s0[lane + 64] = c_s0[1];
+    L.bk_pre[lane + 65] = pre1;
   }
   if (lane == 0) L.bk_pre[0] = 0;
-  const int total = __shfl(pre, 26, 64);
+  const int total = __shfl(pre1, 63, 64);
   __syncthreads();
   int nn = 0;
   bool overflow = false;
   long long plane_tests = 0, new_verts = 0;
-  for (int base = 0; base < total; base += 64) {
-    const int f = base + lane;
-    bool take = false;
-    int j = -1;
-    double key = 0.0;
-    if (f < total) {
-      int c = 0;
-      while (L.bk_pre[c + 1] <= f) ++c;
-      const int k = L.bk_s0[c] + (f - L.bk_pre[c]);
-      j = b.sorted[k];
-      const double4 pj = b.spos[k];
-      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      const double d2 = dx * dx + dy * dy + dz * dz;
-      const double rr = Ri + pj.w;
-      take = (j != i) && (b.smol[k] == mi) && (d2 < rr * rr);
-      // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
-      // neighbour at the same centre has no plane (it empties the cell or
-      // cuts nothing) and goes first
-      key = d2 > 0.0 ? (d2 + wi - pj.w * pj.w) / (2.0 * sqrt(d2)) : -1e300;
-    }
-    const unsigned long long m = __ballot(take);
-    if (take) {
-      const int at = nn + prefix_below(m);
-      if (at < NB_CAP) {
-        L.kidx[at] = j;
-        L.key[at] = key;
+  // two chunks of 64 candidates per round: both rounds' loads are in flight together
+  for (int base = 0; base < total; base += 128) {
+    int j[2] = {-1, -1};
+    bool own[2] = {false, false};
+    double4 pj[2];
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int f = base + 64 * h2 + lane;
+      if (f < total) {
+        int lo = 0, hi = 127;  // cell c with bk_pre[c] <= f < bk_pre[c + 1]
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.bk_pre[mid] <= f) lo = mid;
+          else hi = mid - 1;
+        }
+        const int k = L.bk_s0[lo] + (f - L.bk_pre[lo]);
+        j[h2] = b.sorted[k];
+        pj[h2] = b.spos[k];
+        const int4 ck = b.scell[k];
+        own[h2] = ck.x == cx + lo % 5 - 2 && ck.y == cy + (lo / 5) % 5 - 2 && ck.z == cz + lo / 25 - 2 && ck.w == mi;
       }
     }
-    nn += __popcll(m);
+    for (int h2 = 0; h2 < 2; ++h2) {
+      bool take = false;
+      double key = 0.0;
+      if (j[h2] >= 0 && own[h2]) {
+        const double dx = pj[h2].x - pi.x, dy = pj[h2].y - pi.y, dz = pj[h2].z - pi.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double rr = Ri + pj[h2].w;
+        take = (j[h2] != i) && (d2 < rr * rr);
+        // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
+        // neighbour at the same centre has no plane (it empties the cell or
+        // cuts nothing) and goes first
+        key = d2 > 0.0 ? (d2 + wi - pj[h2].w * pj[h2].w) / (2.0 * sqrt(d2)) : -1e300;
+      }
+      const unsigned long long m = __ballot(take);
+      if (take) {
+        const int at = nn + prefix_below(m);
+        if (at < NB_CAP) {
+          L.kidx[at] = j[h2];
+          L.key[at] = key;
+        }
+      }
+      nn += __popcll(m);
+    }
   }
   if (nn > NB_CAP) {
     overflow = true;
@@ -923,9 +954,9 @@ constexpr double kTripleDepthMin = 0.02;  // -s_t / w_i: triple points close to 
 template <typename T>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   __shared__ TermsLds L;
-  const int i = blockIdx.x;
+  if ((int)blockIdx.x >= b.n) return;
+  const int i = b.sorted[blockIdx.x];  // bucket order, as in k_star
   const int lane = threadIdx.x;
-  if (i >= b.n) return;
   const uint8_t vf = b.vflag[i];
   if (!(vf & VF_EXT)) {
     if (lane == 0) b.area[i] = 0.0;
@@ -1074,45 +1105,61 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
 }
 
 // ------------------------------------------------------------------ gather
-__global__ void k_gather(Bufs b, const double* u, double* out, double scale) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= b.n) return;
+// 16 lanes per receiving atom m (4 atoms per wavefront): lane l takes the
+// K-neighbours l, l + 16, ... of m, finds m among each neighbour i's sorted
+// K-neighbours and adds u_i dA_i/dp_m; a fixed xor tree sums the 16 partials,
+// so the result does not depend on scheduling.
+__device__ inline double sum16(double v) {
+  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* out, double scale) {
+  const int sub = threadIdx.x & 15;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 4);
   double gx = 0, gy = 0, gz = 0;
-  if (b.vflag[m] & VF_EXT) {
-    const double um = u ? u[m] : 1.0;
-    const double* row = b.rows + ((size_t)m * ROW + KN_CAP) * 3;
-    gx += um * row[0], gy += um * row[1], gz += um * row[2];
-  }
-  const int nk = b.kn_cnt[m];
   int lost = 0;
-  for (int k = 0; k < nk; ++k) {
-    const int i = b.knbr[(size_t)m * KN_CAP + k];
-    if (!(b.vflag[i] & VF_EXT)) continue;
-    // position of m among i's K-neighbours (ascending ids)
-    const int* li = b.knbr + (size_t)i * KN_CAP;
-    int lo = 0, hi = b.kn_cnt[i] - 1, s = -1;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int v = li[mid];
-      if (v == m) {
-        s = mid;
-        break;
+  if (m < b.n) {
+    if (sub == 0 && (b.vflag[m] & VF_EXT)) {
+      const double um = u ? u[m] : 1.0;
+      const double* row = b.rows + ((size_t)m * ROW + KN_CAP) * 3;
+      gx = um * row[0], gy = um * row[1], gz = um * row[2];
+    }
+    const int nk = b.kn_cnt[m];
+    for (int k = sub; k < nk; k += 16) {
+      const int i = b.knbr[(size_t)m * KN_CAP + k];
+      if (!(b.vflag[i] & VF_EXT)) continue;
+      const int* li = b.knbr + (size_t)i * KN_CAP;
+      int lo = 0, hi = b.kn_cnt[i] - 1, s = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = li[mid];
+        if (v == m) {
+          s = mid;
+          break;
+        }
+        if (v < m) lo = mid + 1;
+        else hi = mid - 1;
       }
-      if (v < m) lo = mid + 1;
-      else hi = mid - 1;
+      if (s < 0) {
+        ++lost;
+        continue;
+      }
+      const double ui = u ? u[i] : 1.0;
+      const double* row = b.rows + ((size_t)i * ROW + s) * 3;
+      gx += ui * row[0], gy += ui * row[1], gz += ui * row[2];
     }
-    if (s < 0) {
-      ++lost;
-      continue;
-    }
-    const double ui = u ? u[i] : 1.0;
-    const double* row = b.rows + ((size_t)i * ROW + s) * 3;
-    gx += ui * row[0], gy += ui * row[1], gz += ui * row[2];
   }
-  out[3 * m] = scale * gx;
-  out[3 * m + 1] = scale * gy;
-  out[3 * m + 2] = scale * gz;
-  if (lost) atomicAdd(&b.ctr[C_LOST_PAIR], (unsigned long long)lost);
+  gx = sum16(gx);
+  gy = sum16(gy);
+  gz = sum16(gz);
+  for (int off = 8; off > 0; off >>= 1) lost += __shfl_xor(lost, off, 64);
+  if (m < b.n && sub == 0) {
+    out[3 * m] = scale * gx;
+    out[3 * m + 1] = scale * gy;
+    out[3 * m + 2] = scale * gz;
+    if (lost) atomicAdd(&b.ctr[C_LOST_PAIR], (unsigned long long)lost);
+  }
 }
 
 __global__ void k_zero(unsigned* p, size_t words) {
@@ -1155,7 +1202,7 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
   else k_terms<double><<<b.n, 64, 0, s>>>(b, with_grad);
 }
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s) {
-  if (b.n) k_gather<<<blocks(b.n, 256), 256, 0, s>>>(b, u, out, scale);
+  if (b.n) k_gather<<<blocks(b.n, 4), 64, 0, s>>>(b, u, out, scale);
 }
 
 }  // namespace sasa

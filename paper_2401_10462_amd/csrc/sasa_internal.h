@@ -7,8 +7,8 @@
 namespace sasa {
 
 // Per-atom capacities of the star kernel (local data in LDS).
-constexpr int NB_CAP = 192;  // overlapping neighbours of one atom
-constexpr int V_CAP = 128;   // vertices of the clipped power cell (2 per lane)
+constexpr int NB_CAP = 160;  // overlapping neighbours of one atom
+constexpr int V_CAP = 96;    // vertices of the clipped power cell (at most 2 per lane)
 // Per-atom capacities of the kept complex (HBM).
 constexpr int KN_CAP = 64;    // K-edges at an atom (bit mask of exterior edges is one u64)
 constexpr int KT_CAP = 160;   // K-tetrahedra at an atom
@@ -65,7 +65,8 @@ struct Bufs {
   int* scan_tmp = nullptr;   // block sums of the scan
   int* sorted = nullptr;     // atom ids grouped by bucket
   double4* spos = nullptr;   // positions in bucket order (coalesced neighbour loads)
-  int* smol = nullptr;       // molecule ids in bucket order
+  int4* cell = nullptr;      // cell coordinates + molecule id of each atom
+  int4* scell = nullptr;     // the same in bucket order (cell tags of candidates)
   // kept complex
   uint8_t* vflag = nullptr;
   int* kn_cnt = nullptr;

@@ -83,14 +83,12 @@ class _Slot:
         self.event.synchronize()
         diag = self.ctx.diagnostics()  # raises on capacity / input errors of this batch
         a, g = self.host_out[0].numpy(), self.host_out[1].numpy()
-        t = time.perf_counter()
-        o = 0
+        out, o = [], 0
         for r in self.reqs:
-            r.t_done = t
-            r.future.set_result((a[o:o + r.n].copy(), g[o:o + r.n].copy()))
+            out.append((a[o:o + r.n].copy(), g[o:o + r.n].copy()))
             o += r.n
         reqs, self.reqs, self._keep = self.reqs, [], None
-        return reqs, diag
+        return reqs, out
 
 
 class SasaServer:
@@ -173,8 +171,13 @@ class SasaServer:
             for s in self._slots:
                 if s.reqs and s.done():
                     try:
-                        reqs, _ = s.finish()
-                        self.completed.extend(reqs)
+                        reqs, results = s.finish()
+                        t = time.perf_counter()
+                        for r in reqs:
+                            r.t_done = t
+                        self.completed.extend(reqs)  # recorded before any caller is woken
+                        for r, res in zip(reqs, results):
+                            r.future.set_result(res)
                     except Exception as e:  # deliver the error to every request of the batch
                         for r in s.reqs:
                             r.future.set_exception(e)
@@ -205,3 +208,29 @@ def latency_stats(reqs):
     span = max(r.t_done for r in reqs) - min(r.arrival for r in reqs)
     return {"requests": len(reqs), "atoms": atoms, "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "atoms_per_s": atoms / span, "span_s": span}
+
+
+def poisson_run(server, requests, rate, seed=4):
+    """Open-loop load: submit ``requests`` [(xyz, radii), ...] at Poisson arrival times.
+
+    Each request's latency runs from its scheduled arrival to its result, so
+    queueing delay counts even if the submitter falls behind.  Returns the
+    latency / throughput summary (``latency_stats``) of this run.
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(requests))
+    t0 = time.perf_counter() + 0.01
+    arrivals = t0 + np.cumsum(gaps)
+    futs = []
+    for (xyz, rad), ta in zip(requests, arrivals):
+        now = time.perf_counter()
+        if ta > now:
+            time.sleep(ta - now)
+        futs.append(server.submit(xyz, rad, arrival=ta))
+    for f in futs:
+        f.result()
+    ids = {id(f) for f in futs}
+    done = [r for r in server.completed if id(r.future) in ids]
+    out = latency_stats(done)
+    out["rate_req_s"] = rate
+    return out

@@ -240,3 +240,36 @@ def md_frames(xyz, seed, frames, sigma=0.02):
         rng = np.random.Generator(np.random.PCG64([seed, f]))
         cur = cur + rng.normal(scale=sigma, size=cur.shape)
         yield cur
+
+
+def globule_complex(n_total, seed, chains=4):
+    """A complex of ``chains`` globules (one compact chain each, recipe above).
+
+    Large molecules are built this way because the compression step of a single
+    chain does not reach the target density above about 5,000 atoms.  The
+    globules sit on a tetrahedron (or a line for fewer than 4), each moved out
+    along its direction until it is at least 3.0 A from every other chain.
+    """
+    sizes = [n_total // chains + (1 if k < n_total % chains else 0) for k in range(chains)]
+    parts = [heavy_chain(n, seed * 101 + k) for k, n in enumerate(sizes)]
+    dirs = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)[:chains]
+    if chains < 4:
+        dirs = np.array([[k - (chains - 1) / 2, 0, 0] for k in range(chains)], float)
+    dirs /= np.maximum(np.linalg.norm(dirs, axis=1, keepdims=True), 1e-12)
+    placed = []
+    for k, (x, r, e) in enumerate(parts):
+        rad = np.linalg.norm(x, axis=1).max()
+        shift = 0.8 * rad
+        while True:
+            y = x + dirs[k] * shift
+            if not placed:
+                break
+            d, _ = cKDTree(np.vstack([p for p, _ in placed])).query(y)
+            if d.min() >= NONBONDED_MIN:
+                break
+            shift += 0.5
+        placed.append((y, r))
+    xyz = np.vstack([p for p, _ in placed])
+    radii = np.concatenate([r for _, r in placed])
+    xyz -= xyz.mean(axis=0)
+    return np.ascontiguousarray(xyz), radii
