@@ -25,6 +25,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "SASA+gradient atoms/s at 1 GPU (batched vs plain, \u22641e-4 rel err); p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64
 # FP64 operations per unit of star-kernel work, counted from the kernel source:
 #   side test of a cell vertex against a plane: 3 mul + 3 add/sub        =  6
@@ -56,11 +57,11 @@ def parse():
 
 def pool_molecules(sizes, seed=40_000):
     """Request molecules: the first n atoms of pooled globule chains, randomly rotated."""
-    from synth.globule import heavy_chain
+    from synth.globule import globule_complex
     top = max(sizes)
     levels = sorted(set(int(round(x)) for x in np.geomspace(200, top, 7)))
     levels[-1] = top
-    pool = [heavy_chain(n, seed + k)[:2] for k, n in enumerate(levels)]
+    pool = [globule_complex(n, seed + k) for k, n in enumerate(levels)]
     rng = np.random.default_rng(seed)
     out = []
     for n in sizes:
@@ -97,8 +98,8 @@ def serving(args, precision):
 def md(args, precision):
     """Config: a globule, cumulative Gaussian moves, SASA + forces every frame, state on the device."""
     from paper_2401_10462_amd.md_loop import md_loop
-    from synth.globule import heavy_chain
-    xyz, rad, _ = heavy_chain(args.md_atoms, 3)
+    from synth.globule import globule_complex
+    xyz, rad = globule_complex(args.md_atoms, 3)
     lat, _ = md_loop(xyz, rad, frames=min(args.warmup, 5), precision=precision)
     lat, kept = md_loop(xyz, rad, frames=args.frames, precision=precision, keep_frames=(0, args.frames - 1))
     lat = np.array(lat)
@@ -107,21 +108,48 @@ def md(args, precision):
             "p99_ms": float(np.percentile(lat, 99)), "gamma": 0.005, "sigma": 0.02}
 
 
-def cpu_baseline(xyz, rad, budget):
-    """FP64 oracle on the host: whole molecule, repeated up to the time budget."""
+def measured_traffic():
+    """HBM bytes per k_star launch from the committed rocprofv3 counter runs, or
+    None when kernels.hip has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_star_traffic_globule5000H_mixed.json")
+    src = os.path.join(ROOT, "paper_2401_10462_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return rec["bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
+
+
+def cpu_baseline(xyz, rad, budget, area=None, dadx=None):
+    """FP64 oracle on the host: whole molecule, repeated up to the time budget.
+
+    The timed leg also yields the oracle's result for this molecule, so the
+    error of the GPU result just measured is reported beside it (per atom,
+    relative to max(|ref|, 1 A^2) or max(|ref|, 1 A^2/A)).
+    """
     import oracle
     oracle.lib()
     t0 = time.perf_counter()
     runs = 0
+    ref = None
     while True:
-        oracle.run(xyz, rad, 1.4)
+        ref = oracle.run(xyz, rad, 1.4)
         runs += 1
         el = time.perf_counter() - t0
         if el > budget or runs >= 5:
             break
-    return {"value": runs * len(rad) / el, "unit": "atoms/s", "cores": 1, "kind": "oracle",
-            "sample": f"{runs} full run(s) of the {len(rad)}-atom molecule (SASA + dA/dx, FP64, one thread)",
-            "seconds": el, "host_cpus": os.cpu_count()}
+    out = {"value": runs * len(rad) / el, "unit": "atoms/s", "cores": 1, "kind": "oracle",
+           "sample": f"{runs} full run(s) of the {len(rad)}-atom molecule (SASA + dA/dx, FP64, one thread)",
+           "seconds": el, "host_cpus": os.cpu_count()}
+    if area is not None:
+        out["max_rel_err_area"] = float((np.abs(area - ref.area) / np.maximum(ref.area, 1.0)).max())
+        gn = np.linalg.norm(ref.dadx, axis=1)
+        out["max_rel_err_grad"] = float((np.linalg.norm(dadx - ref.dadx, axis=1) / np.maximum(gn, 1.0)).max())
+    return out
 
 
 def main():
@@ -189,7 +217,7 @@ def main():
     achieved = flops / star_s / 1e12
     roofline = {"kernel": "k_star", "dominant_stage": dom, "bound": "alu", "achieved": achieved,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": None, "flop_per_launch": flops, "ms_per_launch": star_s * 1e3,
+                "traffic": measured_traffic() if args.heavy == 2500 and args.seed == 2 else None, "flop_per_launch": flops, "ms_per_launch": star_s * 1e3,
                 "stage_ms_per_step": {k: v / args.steps for k, v in stage.items()}}
 
     # ---- batched form: many molecules (rigid copies) in one launch sequence
@@ -217,11 +245,13 @@ def main():
                    "atoms_per_s": n * args.batch * kb / eb, "ms_per_step": 1e3 * eb / kb,
                    "speedup_vs_plain": (n * args.batch * kb / eb) / value}
 
-    cpu = cpu_baseline(xyz, rad, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(xyz, rad, args.cpu_seconds, area.cpu().numpy(), dadx.cpu().numpy())
 
     lat_ms = np.array(lat) * 1e3
     out = {
-        "metric": "SASA+gradient atoms/s at 1 GPU (plain, one molecule per launch sequence)",
+        "metric": METRIC,
         "value": value,
         "unit": "atoms/s",
         "n_gpus": 1,

@@ -75,7 +75,8 @@ void sasa_destroy(void* ctx);
 
 /*
  * Per-atom SASA of one molecule and the gradient of the molecular SASA.
- *   n       number of atoms (0 is allowed and returns at once)
+ *   n       number of atoms (0 is allowed and returns at once; at most 100,000,000,
+ *           else SASA_E_INVAL)
  *   xyz     n*3 doubles, row-major (x0 y0 z0 x1 ...)
  *   radii   n doubles, van der Waals radii > 0
  *   probe   probe radius >= 0 (1.4 A in the paper)

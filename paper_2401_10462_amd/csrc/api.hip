@@ -26,7 +26,7 @@ struct Ctx {
   int precision = SASA_FP64;
   uint32_t flags = 0;
   int64_t cap_n = 0;
-  unsigned cap_hb = 0;
+  int64_t cap_cells = 0;
   int cap_mol = 0;
   Bufs b;                 // device pointers (capacity-sized)
   double* xyz_d = nullptr;  // staging of host inputs
@@ -54,6 +54,9 @@ struct Ctx {
 
 thread_local std::string g_err;
 
+// Largest batch: keeps every cell and scan index in 32 bits (16 n + 64 cells).
+constexpr int64_t kMaxAtoms = 100000000;
+
 int fail(Ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   g_err = msg;
@@ -79,23 +82,15 @@ hipError_t grow(T** p, size_t count) {
   return count ? hipMalloc((void**)p, count * sizeof(T)) : hipSuccess;
 }
 
-unsigned pow2_at_least(int64_t v) {
-  unsigned p = 1024;
-  while ((int64_t)p < v) p <<= 1;
-  return p;
-}
-
 int ensure(Ctx* c, int64_t n, int nmol) {
   Bufs& b = c->b;
   if (n > c->cap_n) {
     const int64_t cap = std::max<int64_t>(n, c->cap_n + c->cap_n / 2);
     HIP_TRY(c, grow(&b.pos, cap));
     HIP_TRY(c, grow(&b.mol, cap));
-    HIP_TRY(c, grow(&b.bucket, cap));
+    HIP_TRY(c, grow(&b.cellid, cap));
     HIP_TRY(c, grow(&b.sorted, cap));
     HIP_TRY(c, grow(&b.spos, cap));
-    HIP_TRY(c, grow(&b.cell, cap));
-    HIP_TRY(c, grow(&b.scell, cap));
     HIP_TRY(c, grow(&b.vflag, cap));
     HIP_TRY(c, grow(&b.kn_cnt, cap));
     HIP_TRY(c, grow(&b.knbr, cap * KN_CAP));
@@ -112,17 +107,21 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&c->u_d, cap));
     c->cap_n = cap;
   }
-  const unsigned hb = pow2_at_least(2 * std::max<int64_t>(n, 1));
-  if (hb > c->cap_hb) {
-    HIP_TRY(c, grow(&b.cnt, hb));
-    HIP_TRY(c, grow(&b.start, (size_t)hb + 1));
-    HIP_TRY(c, grow(&b.scan_tmp, (size_t)scan_blocks(hb) + 1));
-    c->cap_hb = hb;
+  const int64_t cells = cell_capacity(n);
+  if (cells > c->cap_cells) {
+    const int64_t cap = std::max<int64_t>(cells, c->cap_cells + c->cap_cells / 2);
+    HIP_TRY(c, grow(&b.cnt, cap));
+    HIP_TRY(c, grow(&b.start, (size_t)cap + 1));
+    HIP_TRY(c, grow(&b.scan_tmp, (size_t)scan_blocks((unsigned)cap) + 1));
+    c->cap_cells = cap;
   }
-  b.hb_mask = hb - 1;
+  b.cell_cap = (int)cells;
   if (nmol + 1 > c->cap_mol) {
     const int cap = std::max(nmol + 1, 2 * c->cap_mol);
     HIP_TRY(c, grow(&c->off_d, cap));
+    HIP_TRY(c, grow(&b.mol_box, (size_t)cap * 6));
+    HIP_TRY(c, grow(&b.mol_geo, cap));
+    HIP_TRY(c, grow(&b.mol_dim, cap));
     if (c->off_h) HIP_TRY(c, hipHostFree(c->off_h));
     c->off_h = nullptr;
     HIP_TRY(c, hipHostMalloc((void**)&c->off_h, cap * sizeof(int64_t)));
@@ -187,7 +186,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   for (int k = 0; k < nmol; ++k)
     if (offsets[k + 1] < offsets[k]) return fail(c, SASA_E_INVAL, "offsets must be non-decreasing");
   const int64_t n = offsets[nmol];
-  if (n > (int64_t)1 << 30) return fail(c, SASA_E_INVAL, "too many atoms");
+  if (n > kMaxAtoms) return fail(c, SASA_E_INVAL, "too many atoms (at most 100,000,000 per call)");
   if (n > 0 && (!xyz || !radii)) return fail(c, SASA_E_INVAL, "xyz / radii must not be NULL");
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->pending) {
@@ -224,9 +223,11 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
   launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
-  launch_zero(b.cnt, (size_t)(b.hb_mask + 1) * sizeof(int), s);
+  launch_zero(b.cnt, (size_t)b.cell_cap * sizeof(int), s);
+  launch_zero(b.mol_box, (size_t)b.nmol * 6 * sizeof(unsigned long long), s);
   launch_prep(b, s);
-  launch_buckets(b, s);
+  launch_grid(b, s);
+  launch_count(b, s);
   launch_scan(b, s);
   launch_scatter(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
@@ -313,8 +314,8 @@ void sasa_destroy(void* ctx) {
   hipSetDevice(c->device);
   hipDeviceSynchronize();
   Bufs& b = c->b;
-  void* dev[] = {b.pos,  b.mol,   b.bucket,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
-                 b.cell, b.scell, b.vflag, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet,   b.ktr_cnt,
+  void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
+                 b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
@@ -465,11 +466,14 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
 
 int sasa_footprint(int64_t n, int64_t* bytes) {
   if (n < 0 || !bytes) return fail(nullptr, SASA_E_INVAL, "n < 0 or bytes == NULL");
-  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int4) * 2 + sizeof(int) * 3 + 1 + sizeof(int) * (KN_CAP + 3) +
+  // per atom: positions (2 orders), molecule / cell / sorted ids, flags, the
+  // kept complex, gradient blocks, area and the staging of inputs and outputs;
+  // per molecule (at most one per atom): offsets, box, grid geometry
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * 3 + 1 + sizeof(int) * (KN_CAP + 3) +
                            sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
                            sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
-  const int64_t hb = pow2_at_least(2 * std::max<int64_t>(n, 1));
-  *bytes = n * per_atom + hb * 2 * (int64_t)sizeof(int) + 4096;
+  const int64_t per_mol = sizeof(int64_t) * 2 + sizeof(unsigned long long) * 6 + sizeof(double4) + sizeof(int4);
+  *bytes = n * (per_atom + per_mol) + cell_capacity(n) * 2 * (int64_t)sizeof(int) + 4096;
   return SASA_OK;
 }
 

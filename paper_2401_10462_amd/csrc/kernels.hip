@@ -1,10 +1,12 @@
 // kernels.hip -- HIP kernels (gfx950, wave64) of the exact analytic SASA path.
 //
 // Pipeline for one batch of molecules (each molecule is one segment of atoms):
-//   k_prep      weights R_i = r_i + probe, SoA copy, molecule ids, input checks
-//   k_buckets   spatial hash of every atom's cell (cell side 2 R_max), counts
-//   k_scan*     exclusive scan of the bucket counts
-//   k_scatter   atoms grouped by bucket; positions copied in that order so that
+//   k_prep      weights R_i = r_i + probe, molecule ids, input checks, R_max and
+//               each molecule's bounding box
+//   k_grid      one dense cell grid per molecule (cell side >= R_max)
+//   k_count     cell of every atom, atoms per cell
+//   k_scan*     exclusive scan of the cell counts
+//   k_scatter   atoms grouped by cell; positions copied in that order so that
 //               neighbour loads are coalesced
 //   k_star      one wavefront per atom: its power (Laguerre) cell clipped by the
 //               radical planes of its overlapping neighbours, restricted to its
@@ -29,59 +31,154 @@ __device__ inline int prefix_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-__device__ inline unsigned cell_hash(int mol, int cx, int cy, int cz, unsigned mask) {
-  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
-               (unsigned)mol * 2654435761u;
-  h ^= h >> 13;
-  h *= 0x5bd1e995u;
-  h ^= h >> 15;
-  return h & mask;
-}
-
-__device__ inline int cell_coord(double x, double inv_h) {
-  double c = floor(x * inv_h);
-  c = fmin(fmax(c, -1.0e9), 1.0e9);  // NaN -> -1e9 (fmax returns the non-NaN operand)
-  return (int)c;
-}
-
 __device__ inline double rmax_of(const unsigned long long* ctr) {
   return __longlong_as_double((long long)ctr[C_RMAX_BITS]);
 }
 
-// ------------------------------------------------------------------ prep
-__global__ void k_prep(Bufs b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= b.n) return;
-  const double x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
-  double r = b.radii[i];
-  const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0;
-  if (!ok) {
-    atomicAdd(&b.ctr[C_BAD_INPUT], 1ull);
-    r = 1.0;
-  }
-  const double R = r + b.probe;
-  b.pos[i] = make_double4(ok ? x : 0.0, ok ? y : 0.0, ok ? z : 0.0, R);
-  // molecule id: largest k with offsets[k] <= i
-  int lo = 0, hi = b.nmol - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (b.offsets[mid] <= i) lo = mid;
-    else hi = mid - 1;
-  }
-  b.mol[i] = lo;
-  atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(R));
+// Order-preserving map of doubles to unsigned integers (for atomicMax on
+// coordinates); the box of a molecule keeps max(~ord(x)) for its minimum and
+// max(ord(x)) for its maximum, so a zero-filled box is the empty box.
+__device__ inline unsigned long long ord_bits(double d) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double from_ord(unsigned long long u) {
+  return __longlong_as_double((long long)((u >> 63) ? (u & 0x7fffffffffffffffull) : ~u));
 }
 
-__global__ void k_buckets(Bufs b) {
+__device__ inline double wave_min_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double wave_max_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------ prep
+// Weights R_i = r_i + probe, molecule ids, R_max and each molecule's bounding
+// box (one atomic per molecule present in a wavefront).
+__global__ void k_prep(Bufs b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool live = i < b.n;
+  double x = 0.0, y = 0.0, z = 0.0, R = 0.0;
+  int m = -1;
+  if (live) {
+    x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
+    double r = b.radii[i];
+    const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0;
+    if (!ok) {
+      atomicAdd(&b.ctr[C_BAD_INPUT], 1ull);
+      x = y = z = 0.0;
+      r = 1.0;
+    }
+    R = r + b.probe;
+    b.pos[i] = make_double4(x, y, z, R);
+    // molecule id: largest k with offsets[k] <= i
+    int lo = 0, hi = b.nmol - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (b.offsets[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    b.mol[i] = lo;
+    m = lo;
+  }
+  const double rmax = wave_max_d(R);
+  if (lane == 0 && rmax > 0.0) atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(rmax));
+  unsigned long long pend = __ballot(live);
+  while (pend) {
+    const int leader = (int)__builtin_ctzll(pend);
+    const int mm = __shfl(m, leader, 64);
+    const bool mine = live && m == mm;
+    const unsigned long long grp = __ballot(mine);
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    const double x0 = wave_min_d(mine ? x : inf), y0 = wave_min_d(mine ? y : inf), z0 = wave_min_d(mine ? z : inf);
+    const double x1 = wave_max_d(mine ? x : -inf), y1 = wave_max_d(mine ? y : -inf), z1 = wave_max_d(mine ? z : -inf);
+    if (lane == leader) {
+      unsigned long long* box = b.mol_box + 6 * (size_t)mm;
+      atomicMax(&box[0], ~ord_bits(x0));
+      atomicMax(&box[1], ~ord_bits(y0));
+      atomicMax(&box[2], ~ord_bits(z0));
+      atomicMax(&box[3], ord_bits(x1));
+      atomicMax(&box[4], ord_bits(y1));
+      atomicMax(&box[5], ord_bits(z1));
+    }
+    pend &= ~grp;
+  }
+}
+
+// One dense grid per molecule over its bounding box.  The cell side is R_max
+// (so every overlapping pair lies within two cells along each axis), enlarged
+// for sparse, elongated molecules until the grid has at most 8 n_m + 8 cells;
+// the cells of all molecules are numbered consecutively.
+__global__ __launch_bounds__(1024) void k_grid(Bufs b) {
+  __shared__ int lds[1024];
+  const double rmax = rmax_of(b.ctr);
+  int carry = 0;
+  for (int k0 = 0; k0 < b.nmol; k0 += 1024) {
+    const int k = k0 + (int)threadIdx.x;
+    int cells = 0;
+    double4 geo = make_double4(0.0, 0.0, 0.0, rmax);
+    int nx = 0, ny = 0, nz = 0;
+    if (k < b.nmol) {
+      const int64_t na = b.offsets[k + 1] - b.offsets[k];
+      if (na > 0) {
+        const unsigned long long* box = b.mol_box + 6 * (size_t)k;
+        const double lx = from_ord(~box[0]), ly = from_ord(~box[1]), lz = from_ord(~box[2]);
+        const double ex = from_ord(box[3]) - lx, ey = from_ord(box[4]) - ly, ez = from_ord(box[5]) - lz;
+        const double cap = 8.0 * (double)na + 8.0;
+        double s = rmax;
+        double fx, fy, fz;
+        for (;;) {
+          fx = floor(ex / s) + 1.0, fy = floor(ey / s) + 1.0, fz = floor(ez / s) + 1.0;
+          if (fx * fy * fz <= cap) break;
+          s *= 1.25;
+        }
+        nx = (int)fx, ny = (int)fy, nz = (int)fz;
+        cells = nx * ny * nz;
+        geo = make_double4(lx, ly, lz, s);
+      }
+    }
+    // exclusive scan of the cell counts over this chunk of molecules
+    lds[threadIdx.x] = cells;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int v = (int)threadIdx.x >= off ? lds[threadIdx.x - off] : 0;
+      __syncthreads();
+      lds[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int incl = lds[threadIdx.x], total = lds[1023];
+    __syncthreads();
+    if (k < b.nmol) {
+      b.mol_geo[k] = geo;
+      b.mol_dim[k] = make_int4(nx, ny, nz, carry + incl - cells);
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) b.ctr[C_CELLS] = (unsigned long long)carry;
+}
+
+__device__ inline int cell_index(double v, double lo, double inv_s, int n) {
+  const int c = (int)floor((v - lo) * inv_s);
+  return min(max(c, 0), n - 1);
+}
+
+__global__ void k_count(Bufs b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= b.n) return;
-  const double inv_h = 1.0 / rmax_of(b.ctr);  // cell side R_max
+  const int m = b.mol[i];
+  const double4 g = b.mol_geo[m];
+  const int4 d = b.mol_dim[m];
   const double4 p = b.pos[i];
-  const int cx = cell_coord(p.x, inv_h), cy = cell_coord(p.y, inv_h), cz = cell_coord(p.z, inv_h);
-  const unsigned k = cell_hash(b.mol[i], cx, cy, cz, b.hb_mask);
-  b.bucket[i] = (int)k;
-  b.cell[i] = make_int4(cx, cy, cz, b.mol[i]);
-  atomicAdd(&b.cnt[k], 1);
+  const double inv_s = 1.0 / g.w;
+  const int cx = cell_index(p.x, g.x, inv_s, d.x), cy = cell_index(p.y, g.y, inv_s, d.y),
+            cz = cell_index(p.z, g.z, inv_s, d.z);
+  const int c = d.w + (cz * d.y + cy) * d.x + cx;
+  b.cellid[i] = c;
+  atomicAdd(&b.cnt[c], 1);
 }
 
 // ------------------------------------------------------------------ scan
@@ -117,16 +214,21 @@ __global__ __launch_bounds__(SCAN_T) void k_scan1(const int* cnt, int* start, in
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// exclusive scan of the block sums, in chunks of SCAN_E with a running carry
 __global__ __launch_bounds__(SCAN_T) void k_scan2(int* sums, int nb, int* start, int hb) {
   __shared__ int lds[SCAN_T];
-  const int base = 2 * threadIdx.x;
-  const int a0 = base < nb ? sums[base] : 0;
-  const int a1 = base + 1 < nb ? sums[base + 1] : 0;
-  int total;
-  const int ex = block_scan2(a0, a1, lds, &total);
-  if (base < nb) sums[base] = ex;
-  if (base + 1 < nb) sums[base + 1] = ex + a0;
-  if (threadIdx.x == 0) start[hb] = total;
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += SCAN_E) {
+    const int base = c0 + 2 * threadIdx.x;
+    const int a0 = base < nb ? sums[base] : 0;
+    const int a1 = base + 1 < nb ? sums[base + 1] : 0;
+    int total;
+    const int ex = carry + block_scan2(a0, a1, lds, &total);
+    if (base < nb) sums[base] = ex;
+    if (base + 1 < nb) sums[base + 1] = ex + a0;
+    carry += total;
+  }
+  if (threadIdx.x == 0) start[hb] = carry;
 }
 
 __global__ void k_scan3(int* start, const int* sums, int hb) {
@@ -137,11 +239,10 @@ __global__ void k_scan3(int* start, const int* sums, int hb) {
 __global__ void k_scatter(Bufs b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= b.n) return;
-  const int k = b.bucket[i];
-  const int slot = b.start[k] + atomicSub(&b.cnt[k], 1) - 1;
+  const int c = b.cellid[i];
+  const int slot = b.start[c] + atomicSub(&b.cnt[c], 1) - 1;
   b.sorted[slot] = i;
   b.spos[slot] = b.pos[i];
-  b.scell[slot] = b.cell[i];
 }
 
 // ------------------------------------------------------------------ star
@@ -183,7 +284,6 @@ struct StarLds {
   unsigned pairs[3 * V_CAP];
   unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
   int kslot[KN_CAP];        // K-edge slots in slot order
-  int bk_s0[128], bk_pre[129];  // first candidate and prefix count of the stencil's cells
 };
 
 enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
@@ -216,86 +316,85 @@ __device__ inline double wave_max(double v) {
 __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __shared__ StarLds L;
   if ((int)blockIdx.x >= b.n) return;
-  const int i = b.sorted[blockIdx.x];  // bucket order: neighbouring blocks share neighbours in cache
+  const int i = b.sorted[blockIdx.x];  // cell order: neighbouring blocks share neighbours in cache
   const int lane = threadIdx.x;
   const long long cyc0 = clock64();
   const double4 pi = b.pos[i];
   const int mi = b.mol[i];
   const double Ri = pi.w, wi = Ri * Ri;
+  const int4 gd = b.mol_dim[mi];
+  const double4 gg = b.mol_geo[mi];
   const double rmax = rmax_of(b.ctr);
-  const double h = rmax, inv_h = 1.0 / rmax;  // cell side R_max
-  const int cx = cell_coord(pi.x, inv_h), cy = cell_coord(pi.y, inv_h), cz = cell_coord(pi.z, inv_h);
+  const double h = gg.w;  // cell side of i's molecule (>= R_max)
+  int cx, cy, cz;
+  {
+    const int c = b.cellid[i] - gd.w;
+    cx = c % gd.x;
+    cy = (c / gd.x) % gd.y;
+    cz = c / (gd.x * gd.y);
+  }
 
-  // ---- 1. overlapping neighbours: the 5 x 5 x 5 cells around i's cell, minus
-  // those whose box is farther than R_i + R_max from p_i.  Each cell's bucket
-  // range is read at once (two cells per lane); candidates are then scanned as
-  // one flat list and kept only if they belong to the scanned cell (a bucket
-  // shared by several cells is read for each, but every atom is taken once).
-  const double reach = Ri + rmax, reach2 = reach * reach;
-  int c_s0[2] = {0, 0}, c_n[2] = {0, 0};
-  for (int h2 = 0; h2 < 2; ++h2) {
-    const int c = lane + 64 * h2;
-    if (c < 125) {
-      const int dx = c % 5 - 2, dy = (c / 5) % 5 - 2, dz = c / 25 - 2;
-      double dd = 0.0;
-      const double lo[3] = {(cx + dx) * h, (cy + dy) * h, (cz + dz) * h};
-      const double pp[3] = {pi.x, pi.y, pi.z};
-      for (int a3 = 0; a3 < 3; ++a3) {
-        const double t = pp[a3] < lo[a3] ? lo[a3] - pp[a3] : (pp[a3] > lo[a3] + h ? pp[a3] - lo[a3] - h : 0.0);
-        dd += t * t;
-      }
-      if (dd < reach2) {
-        const int bk = (int)cell_hash(mi, cx + dx, cy + dy, cz + dz, b.hb_mask);
-        c_s0[h2] = b.start[bk];
-        c_n[h2] = b.start[bk + 1] - c_s0[h2];
+  // ---- 1. overlapping neighbours.  Candidates lie within R_i + R_max <= 2h
+  // of p_i: in the rows (cy + dy, cz + dz), |dy|, |dz| <= 2, of x-cells
+  // cx - 2 .. cx + 2, pruned to the chord of that sphere.  Lane r < 25 finds
+  // row r's range of `sorted` (cells along x are contiguous); the rows are
+  // then read as one flat, coalesced candidate list.
+  const double reach = Ri + rmax;
+  const double reach2 = reach * reach * (1.0 + 1e-12) + 1e-12;  // widened: a cell is never lost to rounding
+  int row_a = 0, row_n = 0;
+  if (lane < 25) {
+    const int y = cy + lane % 5 - 2, z = cz + lane / 5 - 2;
+    if (y >= 0 && y < gd.y && z >= 0 && z < gd.z) {
+      const double ylo = gg.y + y * h, zlo = gg.z + z * h;
+      const double ty = pi.y < ylo ? ylo - pi.y : (pi.y > ylo + h ? pi.y - ylo - h : 0.0);
+      const double tz = pi.z < zlo ? zlo - pi.z : (pi.z > zlo + h ? pi.z - zlo - h : 0.0);
+      const double t2 = ty * ty + tz * tz;
+      if (t2 < reach2) {
+        const double half = sqrt(reach2 - t2);
+        const double inv_s = 1.0 / h;
+        const int x0 = max(max(cx - 2, 0), (int)floor((pi.x - half - gg.x) * inv_s));
+        const int x1 = min(min(cx + 2, gd.x - 1), (int)floor((pi.x + half - gg.x) * inv_s));
+        if (x0 <= x1) {
+          const int c0 = gd.w + (z * gd.y + y) * gd.x;
+          row_a = b.start[c0 + x0];
+          row_n = b.start[c0 + x1 + 1] - row_a;
+        }
       }
     }
   }
-  // inclusive prefix over cells 0..127 (lane, then lane + 64)
-  int pre0 = c_n[0], pre1 = c_n[1];
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t0 = __shfl_up(pre0, off, 64), t1 = __shfl_up(pre1, off, 64);
-    if (lane >= off) pre0 += t0, pre1 += t1;
+  int pre = row_n;  // inclusive prefix over the rows
+  for (int off = 1; off < 32; off <<= 1) {
+    const int t = __shfl_up(pre, off, 64);
+    if (lane >= off) pre += t;
   }
-  const int tot0 = __shfl(pre0, 63, 64);
-  pre1 += tot0;
-  L.bk_s0[lane] = c_s0[0];
-  L.bk_pre[lane + 1] = pre0;
-  if (lane + 64 < 128) {
-    L.bk_s0[lane + 64] = c_s0[1];
-    L.bk_pre[lane + 65] = pre1;
-  }
-  if (lane == 0) L.bk_pre[0] = 0;
-  const int total = __shfl(pre1, 63, 64);
-  __syncthreads();
+  const int total = __shfl(pre, 24, 64);
+  const int row_s = pre - row_n;     // first flat index of the row
+  const int row_d = row_a - row_s;   // sorted index = flat index + row_d of its row
   int nn = 0;
   bool overflow = false;
   long long plane_tests = 0, new_verts = 0;
   // two chunks of 64 candidates per round: both rounds' loads are in flight together
   for (int base = 0; base < total; base += 128) {
     int j[2] = {-1, -1};
-    bool own[2] = {false, false};
     double4 pj[2];
     for (int h2 = 0; h2 < 2; ++h2) {
       const int f = base + 64 * h2 + lane;
       if (f < total) {
-        int lo = 0, hi = 127;  // cell c with bk_pre[c] <= f < bk_pre[c + 1]
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (L.bk_pre[mid] <= f) lo = mid;
-          else hi = mid - 1;
+        int d = 0;
+        for (int r = 0; r < 25; ++r) {
+          const int sr = __builtin_amdgcn_readlane(row_s, r);
+          const int dr = __builtin_amdgcn_readlane(row_d, r);
+          if (sr <= f) d = dr;
         }
-        const int k = L.bk_s0[lo] + (f - L.bk_pre[lo]);
+        const int k = f + d;
         j[h2] = b.sorted[k];
         pj[h2] = b.spos[k];
-        const int4 ck = b.scell[k];
-        own[h2] = ck.x == cx + lo % 5 - 2 && ck.y == cy + (lo / 5) % 5 - 2 && ck.z == cz + lo / 25 - 2 && ck.w == mi;
       }
     }
     for (int h2 = 0; h2 < 2; ++h2) {
       bool take = false;
       double key = 0.0;
-      if (j[h2] >= 0 && own[h2]) {
+      if (j[h2] >= 0) {
         const double dx = pj[h2].x - pi.x, dy = pj[h2].y - pi.y, dz = pj[h2].z - pi.z;
         const double d2 = dx * dx + dy * dy + dz * dz;
         const double rr = Ri + pj[h2].w;
@@ -955,7 +1054,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   __shared__ TermsLds L;
   if ((int)blockIdx.x >= b.n) return;
-  const int i = b.sorted[blockIdx.x];  // bucket order, as in k_star
+  const int i = b.sorted[blockIdx.x];  // cell order, as in k_star
   const int lane = threadIdx.x;
   const uint8_t vf = b.vflag[i];
   if (!(vf & VF_EXT)) {
@@ -1180,11 +1279,14 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 void launch_prep(const Bufs& b, hipStream_t s) {
   if (b.n) k_prep<<<blocks(b.n, 256), 256, 0, s>>>(b);
 }
-void launch_buckets(const Bufs& b, hipStream_t s) {
-  if (b.n) k_buckets<<<blocks(b.n, 256), 256, 0, s>>>(b);
+void launch_grid(const Bufs& b, hipStream_t s) {
+  if (b.n) k_grid<<<1, 1024, 0, s>>>(b);
+}
+void launch_count(const Bufs& b, hipStream_t s) {
+  if (b.n) k_count<<<blocks(b.n, 256), 256, 0, s>>>(b);
 }
 void launch_scan(const Bufs& b, hipStream_t s) {
-  const int hb = (int)b.hb_mask + 1;
+  const int hb = b.cell_cap;
   const int nb = scan_blocks((unsigned)hb);
   k_scan1<<<nb, SCAN_T, 0, s>>>(b.cnt, b.start, b.scan_tmp, hb);
   k_scan2<<<1, SCAN_T, 0, s>>>(b.scan_tmp, nb, b.start, hb);

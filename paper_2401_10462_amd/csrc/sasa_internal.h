@@ -31,6 +31,7 @@ enum Counter {
   C_BAD_INPUT,     // NaN / Inf / radius <= 0
   C_LOST_PAIR,     // K-edge seen from one side only (gather)
   C_RMAX_BITS,     // bits of max R (positive doubles order like integers)
+  C_CELLS,         // grid cells used by all molecules
   C_EX_EDGE,       // export cursors
   C_EX_TRI,
   C_EX_TET,
@@ -50,23 +51,25 @@ constexpr uint8_t VF_IN = 1, VF_EXT = 2;
 struct Bufs {
   int n = 0;
   int nmol = 0;
-  unsigned hb_mask = 0;  // hash buckets - 1 (power of two)
+  int cell_cap = 0;      // grid cells available to all molecules together
   // inputs staged or borrowed
   const double* xyz = nullptr;
   const double* radii = nullptr;
   double probe = 0;
   const int64_t* offsets = nullptr;  // nmol + 1 (device)
-  // cell list
+  // cell list: one dense grid per molecule, cells numbered x fastest, so the
+  // atoms of a run of cells along x are one contiguous range of `sorted`
   double4* pos = nullptr;    // x, y, z, R (original order)
   int* mol = nullptr;        // molecule id (original order)
-  int* bucket = nullptr;     // hash bucket of each atom
-  int* cnt = nullptr;        // bucket counts (hb)
-  int* start = nullptr;      // exclusive scan of cnt (hb + 1)
+  int* cellid = nullptr;     // grid cell of each atom (original order)
+  unsigned long long* mol_box = nullptr;  // per molecule: ordered bits of min x, y, z and -max x, y, z
+  double4* mol_geo = nullptr;  // per molecule: grid origin x, y, z and cell side
+  int4* mol_dim = nullptr;     // per molecule: cells along x, y, z and the first cell's index
+  int* cnt = nullptr;        // atoms per cell (cell_cap)
+  int* start = nullptr;      // exclusive scan of cnt (cell_cap + 1)
   int* scan_tmp = nullptr;   // block sums of the scan
-  int* sorted = nullptr;     // atom ids grouped by bucket
-  double4* spos = nullptr;   // positions in bucket order (coalesced neighbour loads)
-  int4* cell = nullptr;      // cell coordinates + molecule id of each atom
-  int4* scell = nullptr;     // the same in bucket order (cell tags of candidates)
+  int* sorted = nullptr;     // atom ids grouped by cell
+  double4* spos = nullptr;   // positions in cell order (coalesced neighbour loads)
   // kept complex
   uint8_t* vflag = nullptr;
   int* kn_cnt = nullptr;
@@ -91,7 +94,8 @@ struct Bufs {
 
 // Launchers (kernels.hip).
 void launch_prep(const Bufs& b, hipStream_t s);
-void launch_buckets(const Bufs& b, hipStream_t s);
+void launch_grid(const Bufs& b, hipStream_t s);
+void launch_count(const Bufs& b, hipStream_t s);
 void launch_scan(const Bufs& b, hipStream_t s);
 void launch_scatter(const Bufs& b, hipStream_t s);
 void launch_star(const Bufs& b, hipStream_t s);
@@ -99,5 +103,8 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int scan_blocks(unsigned hb);
+// Grid cells a batch of n atoms may use: a molecule of m > 0 atoms gets at most
+// 8 m + 8 cells (empty molecules none), so all molecules together at most 16 n.
+inline int64_t cell_capacity(int64_t n) { return 16 * n + 64; }
 
 }  // namespace sasa

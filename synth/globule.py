@@ -242,32 +242,34 @@ def md_frames(xyz, seed, frames, sigma=0.02):
         yield cur
 
 
-def globule_complex(n_total, seed, chains=4):
-    """A complex of ``chains`` globules (one compact chain each, recipe above).
+def globule_complex(n_total, seed, chain_atoms=2500):
+    """A complex of compact globules (one chain each, recipe above).
 
     Large molecules are built this way because the compression step of a single
-    chain does not reach the target density above about 5,000 atoms.  The
-    globules sit on a tetrahedron (or a line for fewer than 4), each moved out
-    along its direction until it is at least 3.0 A from every other chain.
+    chain stops reaching the target density with all exclusions above a few
+    thousand atoms.  ceil(n_total / chain_atoms) chains are placed along
+    Fibonacci-sphere directions, each moved out until it is at least 3.0 A from
+    every chain placed before it.
     """
+    chains = max(1, -(-n_total // chain_atoms))
     sizes = [n_total // chains + (1 if k < n_total % chains else 0) for k in range(chains)]
     parts = [heavy_chain(n, seed * 101 + k) for k, n in enumerate(sizes)]
-    dirs = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)[:chains]
-    if chains < 4:
-        dirs = np.array([[k - (chains - 1) / 2, 0, 0] for k in range(chains)], float)
-    dirs /= np.maximum(np.linalg.norm(dirs, axis=1, keepdims=True), 1e-12)
+    k = np.arange(chains) + 0.5
+    phi = np.arccos(1 - 2 * k / chains)
+    theta = np.pi * (1 + 5 ** 0.5) * k
+    dirs = np.column_stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)])
     placed = []
-    for k, (x, r, e) in enumerate(parts):
+    for c, (x, r, e) in enumerate(parts):
         rad = np.linalg.norm(x, axis=1).max()
-        shift = 0.8 * rad
+        shift = 0.0 if chains == 1 else rad
         while True:
-            y = x + dirs[k] * shift
+            y = x + dirs[c] * shift
             if not placed:
                 break
             d, _ = cKDTree(np.vstack([p for p, _ in placed])).query(y)
             if d.min() >= NONBONDED_MIN:
                 break
-            shift += 0.5
+            shift += 1.0
         placed.append((y, r))
     xyz = np.vstack([p for p, _ in placed])
     radii = np.concatenate([r for _, r in placed])

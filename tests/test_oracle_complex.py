@@ -124,16 +124,22 @@ def test_classification_identities():
 
 
 def test_simplex_counts_per_atom():
-    # paper: > 11200 tets, 22600 triangles, 13000 edges for 1700 atoms
-    # (6.6 / 13.3 / 7.6 per atom).  A smaller globule has a larger surface
-    # share, so the counts per atom are lower; this is a loose sanity band.
+    # the paper's counts for a 1700-atom molecule (tests/golden/paper_values.json:
+    # > 11200 tets, 22600 triangles, 13000 edges, i.e. 6.6 / 13.3 / 7.6 per
+    # atom).  A smaller globule has a larger surface share, so the counts per
+    # atom are lower; this is a loose sanity band.
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")) as f:
+        g = json.load(f)["simplex_counts"]
+    ref = np.array([g["tetrahedra_more_than"], g["triangles_more_than"], g["edges_more_than"]]) / g["atoms"]
     xyz, rad, _ = heavy_chain(2000, 2)
     r = oracle.run(xyz, rad, 1.4)
     n = len(rad)
     per = np.array([r.counts["tetrahedra"], r.counts["triangles"], r.counts["edges"]]) / n
-    assert 0.45 * 6.6 < per[0] < 1.3 * 6.6
-    assert 0.45 * 13.3 < per[1] < 1.3 * 13.3
-    assert 0.6 * 7.6 < per[2] < 1.3 * 7.6
+    assert 0.45 * ref[0] < per[0] < 1.3 * ref[0]
+    assert 0.45 * ref[1] < per[1] < 1.3 * ref[1]
+    assert 0.6 * ref[2] < per[2] < 1.3 * ref[2]
     # Euler characteristic of the dual complex of a connected molecule-like union
     chi = r.counts["vertices"] - r.counts["edges"] + r.counts["triangles"] - r.counts["tetrahedra"]
     assert abs(chi - 1) <= 50  # one component; tunnels and cavities shift it a little
