@@ -272,8 +272,7 @@ def main():
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,
         "diagnostics": {k: diag[k] for k in ("max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
-                                             "overflow", "plane_tests", "new_vertices", "candidates",
-                                             "cycles_gather", "cycles_sort", "cycles_clip", "cycles_final")},
+                                             "overflow", "plane_tests", "new_vertices", "candidates")},
         "sasa_total": float(area.sum().item()),
     }
     print(json.dumps(out))

@@ -149,19 +149,14 @@ typedef struct {
   int64_t overflow;           /* atoms beyond the kernels' neighbour / vertex capacity */
   double ms_total;            /* wall time of the last synchronous call */
   /* stage times of the last call (SASA_FLAG_TIMING; HIP events on the call's stream) */
-  double ms_cells;            /* weights, spatial hash, scan, scatter */
-  double ms_star;             /* per-atom power-cell clipping and the star in K */
+  double ms_cells;            /* weights, per-molecule cell grid, scan, scatter */
+  double ms_star;             /* per-atom power-cell clipping, the star in K, its counters */
   double ms_terms;            /* Eq. 1 area terms (and gradient blocks) */
   double ms_gather;           /* segmented gradient sums */
   /* algorithmic work of the last call's star kernel */
   int64_t plane_tests;        /* (vertex, plane) side tests while clipping */
   int64_t new_vertices;       /* cell vertices created (three-plane solves) */
   int64_t candidates;         /* neighbour-candidate distance tests */
-  /* shader clock cycles of the star kernel's phases, summed over all wavefronts */
-  int64_t cycles_gather;      /* neighbour search in the 27 cells */
-  int64_t cycles_sort;        /* neighbour ordering and plane set-up */
-  int64_t cycles_clip;        /* power-cell clipping */
-  int64_t cycles_final;       /* star extraction, classification, stores */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

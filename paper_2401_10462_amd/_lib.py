@@ -49,8 +49,7 @@ class sasa_diag(ctypes.Structure):
         "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
         "capacity_retries", "input_errors", "overflow")] + [
         (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_terms", "ms_gather")] + [
-        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "cycles_gather",
-                                            "cycles_sort", "cycles_clip", "cycles_final")]
+        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates")]
 
 
 _lib = None

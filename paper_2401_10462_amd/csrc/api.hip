@@ -92,6 +92,7 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&b.sorted, cap));
     HIP_TRY(c, grow(&b.spos, cap));
     HIP_TRY(c, grow(&b.vflag, cap));
+    HIP_TRY(c, grow(&b.stat, cap * STAT_STRIDE));
     HIP_TRY(c, grow(&b.kn_cnt, cap));
     HIP_TRY(c, grow(&b.knbr, cap * KN_CAP));
     HIP_TRY(c, grow(&b.kn_ext, cap));
@@ -152,10 +153,6 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.plane_tests = (int64_t)h[C_PLANE_TESTS];
   c->diag.new_vertices = (int64_t)h[C_NEW_VERTS];
   c->diag.candidates = (int64_t)h[C_CANDIDATES];
-  c->diag.cycles_gather = (int64_t)h[C_CYC_GATHER];
-  c->diag.cycles_sort = (int64_t)h[C_CYC_SORT];
-  c->diag.cycles_clip = (int64_t)h[C_CYC_CLIP];
-  c->diag.cycles_final = (int64_t)h[C_CYC_FINAL];
   if (c->timed) {
     float ms[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
@@ -232,6 +229,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   launch_scatter(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   launch_star(b, s);
+  launch_stats(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
   launch_terms(b, c->precision, dA_dx != nullptr, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
@@ -311,19 +309,19 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
 void sasa_destroy(void* ctx) {
   auto* c = (Ctx*)ctx;
   if (!c) return;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
   Bufs& b = c->b;
   void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
-                 b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
+                 b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
-    if (p) hipFree(p);
-  if (c->off_h) hipHostFree(c->off_h);
+    if (p) (void)hipFree(p);
+  if (c->off_h) (void)hipHostFree(c->off_h);
   for (auto& ev : c->ev)
-    if (ev) hipEventDestroy(ev);
-  if (c->ctr_h) hipHostFree(c->ctr_h);
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->ctr_h) (void)hipHostFree(c->ctr_h);
   delete c;
 }
 
@@ -442,6 +440,7 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
   HIP_TRY(c, hipMemcpyAsync(b.ctr + C_RMAX_BITS, &rmax_bits, sizeof(rmax_bits), hipMemcpyHostToDevice, s));
   launch_star(b, s);
+  launch_stats(b, s);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(s));
   c->timed = false;
@@ -466,10 +465,11 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
 
 int sasa_footprint(int64_t n, int64_t* bytes) {
   if (n < 0 || !bytes) return fail(nullptr, SASA_E_INVAL, "n < 0 or bytes == NULL");
-  // per atom: positions (2 orders), molecule / cell / sorted ids, flags, the
+  // per atom: positions (2 orders), molecule / cell / sorted ids, the star's
+  // statistics record, flags, the
   // kept complex, gradient blocks, area and the staging of inputs and outputs;
   // per molecule (at most one per atom): offsets, box, grid geometry
-  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * 3 + 1 + sizeof(int) * (KN_CAP + 3) +
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * (3 + STAT_STRIDE) + 1 + sizeof(int) * (KN_CAP + 3) +
                            sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
                            sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
   const int64_t per_mol = sizeof(int64_t) * 2 + sizeof(unsigned long long) * 6 + sizeof(double4) + sizeof(int4);

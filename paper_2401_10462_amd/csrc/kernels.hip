@@ -56,9 +56,22 @@ __device__ inline double wave_max_d(double v) {
 }
 
 // ------------------------------------------------------------------ prep
+constexpr int PREP_T = 1024;
+
+// molecule of atom a: largest k with offsets[k] <= a
+__device__ inline int mol_of(const Bufs& b, int a) {
+  int lo = 0, hi = b.nmol - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.offsets[mid] <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Weights R_i = r_i + probe, molecule ids, R_max and each molecule's bounding
-// box (one atomic per molecule present in a wavefront).
-__global__ void k_prep(Bufs b) {
+// box, kept by atomicMax on the shared counters and boxes.
+__global__ __launch_bounds__(PREP_T) void k_prep(Bufs b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool live = i < b.n;
@@ -75,15 +88,35 @@ __global__ void k_prep(Bufs b) {
     }
     R = r + b.probe;
     b.pos[i] = make_double4(x, y, z, R);
-    // molecule id: largest k with offsets[k] <= i
-    int lo = 0, hi = b.nmol - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (b.offsets[mid] <= i) lo = mid;
-      else hi = mid - 1;
+    m = mol_of(b, i);
+    b.mol[i] = m;
+  }
+  // a block inside one molecule (the common case) merges its wavefronts in
+  // LDS and issues one set of atomics; otherwise each wavefront issues one set
+  // per molecule it holds
+  __shared__ double part[PREP_T / 64][7];
+  const int first = blockIdx.x * PREP_T, last = min(b.n - 1, first + PREP_T - 1);
+  const bool one_mol = b.nmol == 1 || mol_of(b, first) == mol_of(b, last);
+  const double inf = __longlong_as_double(0x7ff0000000000000ll);
+  if (one_mol) {
+    const double v[7] = {wave_min_d(live ? x : inf), wave_min_d(live ? y : inf), wave_min_d(live ? z : inf),
+                         wave_max_d(live ? x : -inf), wave_max_d(live ? y : -inf), wave_max_d(live ? z : -inf),
+                         wave_max_d(R)};
+    if (lane == 0)
+      for (int q = 0; q < 7; ++q) part[threadIdx.x >> 6][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+      const int q = threadIdx.x;
+      double r = part[0][q];
+      for (int w = 1; w < PREP_T / 64; ++w) r = q < 3 ? fmin(r, part[w][q]) : fmax(r, part[w][q]);
+      if (q == 6) {
+        if (r > 0.0) atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(r));
+      } else {
+        unsigned long long* box = b.mol_box + 6 * (size_t)mol_of(b, first);
+        atomicMax(&box[q], q < 3 ? ~ord_bits(r) : ord_bits(r));
+      }
     }
-    b.mol[i] = lo;
-    m = lo;
+    return;
   }
   const double rmax = wave_max_d(R);
   if (lane == 0 && rmax > 0.0) atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(rmax));
@@ -93,7 +126,6 @@ __global__ void k_prep(Bufs b) {
     const int mm = __shfl(m, leader, 64);
     const bool mine = live && m == mm;
     const unsigned long long grp = __ballot(mine);
-    const double inf = __longlong_as_double(0x7ff0000000000000ll);
     const double x0 = wave_min_d(mine ? x : inf), y0 = wave_min_d(mine ? y : inf), z0 = wave_min_d(mine ? z : inf);
     const double x1 = wave_max_d(mine ? x : -inf), y1 = wave_max_d(mine ? y : -inf), z1 = wave_max_d(mine ? z : -inf);
     if (lane == leader) {
@@ -318,7 +350,6 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   if ((int)blockIdx.x >= b.n) return;
   const int i = b.sorted[blockIdx.x];  // cell order: neighbouring blocks share neighbours in cache
   const int lane = threadIdx.x;
-  const long long cyc0 = clock64();
   const double4 pi = b.pos[i];
   const int mi = b.mol[i];
   const double Ri = pi.w, wi = Ri * Ri;
@@ -420,7 +451,6 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     nn = NB_CAP;
   }
   __syncthreads();
-  const long long cyc1 = clock64();
   // ---- slots in clipping order: nearest plane first, ties by atom id
   for (int s = lane; s < nn; s += 64) {
     const double me = L.key[s];
@@ -445,7 +475,6 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     L.sflag[s] = 0u;
     L.kidx[s] = -1;
   }
-  const long long cyc2 = clock64();
 
   // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
   // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
@@ -560,20 +589,18 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     rho2 = wave_max(r2);
     __syncthreads();  // the next cut overwrites pairs / vertices only after everyone has read
   }
-  const long long cyc3 = clock64();
+  int* st = b.stat + (size_t)i * STAT_STRIDE;
   if (lane == 0) {
-    atomicAdd(&b.ctr[C_CYC_GATHER], (unsigned long long)(cyc1 - cyc0));
-    atomicAdd(&b.ctr[C_CYC_SORT], (unsigned long long)(cyc2 - cyc1));
-    atomicAdd(&b.ctr[C_CYC_CLIP], (unsigned long long)(cyc3 - cyc2));
-    atomicMax(&b.ctr[C_MAX_NB], (unsigned long long)nn);
-    atomicMax(&b.ctr[C_MAX_V], (unsigned long long)vmax);
-    atomicAdd(&b.ctr[C_CANDIDATES], (unsigned long long)total);
-    atomicAdd(&b.ctr[C_PLANE_TESTS], (unsigned long long)plane_tests);
-    atomicAdd(&b.ctr[C_NEW_VERTS], (unsigned long long)new_verts);
+    st[S_NN] = nn;
+    st[S_VMAX] = vmax;
+    st[S_CAND] = total;
+    st[S_TESTS] = (int)plane_tests;
+    st[S_NEWV] = (int)new_verts;
   }
   if (overflow) {
     if (lane == 0) {
-      atomicAdd(&b.ctr[C_OVERFLOW], 1ull);
+      for (int q = S_TIES; q < S_COUNT; ++q) st[q] = 0;
+      st[S_BAD] = 1;
       b.vflag[i] = 0;
       b.kn_cnt[i] = 0;
       b.kt_cnt[i] = 0;
@@ -833,7 +860,6 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   }
   if (lane == 0) {
     if (bad) {
-      atomicAdd(&b.ctr[C_OVERFLOW], 1ull);
       b.vflag[i] = 0;
       b.kn_cnt[i] = 0;
       b.kt_cnt[i] = 0;
@@ -845,15 +871,72 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       b.kt_cnt[i] = ntet;
       b.ktr_cnt[i] = next_tri;
     }
-    if (inK) atomicAdd(&b.ctr[C_VERT], 1ull);
-    if (ext) atomicAdd(&b.ctr[C_EXT_VERT], 1ull);
-    if (own_tet) atomicAdd(&b.ctr[C_TET], (unsigned long long)own_tet);
-    if (own_tri) atomicAdd(&b.ctr[C_TRI], (unsigned long long)own_tri);
-    if (own_ext_tri) atomicAdd(&b.ctr[C_EXT_TRI], (unsigned long long)own_ext_tri);
-    if (own_edge) atomicAdd(&b.ctr[C_EDGE], (unsigned long long)own_edge);
-    if (own_ext_edge) atomicAdd(&b.ctr[C_EXT_EDGE], (unsigned long long)own_ext_edge);
-    if (ties) atomicAdd(&b.ctr[C_NEAR_TIE], (unsigned long long)ties);
-    atomicAdd(&b.ctr[C_CYC_FINAL], (unsigned long long)(clock64() - cyc3));
+    st[S_TIES] = ties;
+    st[S_BAD] = bad ? 1 : 0;
+    st[S_VERT] = inK ? 1 : 0;
+    st[S_EXTV] = ext ? 1 : 0;
+    st[S_TET] = own_tet;
+    st[S_TRI] = own_tri;
+    st[S_EXTTRI] = own_ext_tri;
+    st[S_EDGE] = own_edge;
+    st[S_EXTEDGE] = own_ext_edge;
+  }
+}
+
+// ------------------------------------------------------------------ stats
+// Sums (maxima for the sizes) of the star kernel's per-atom records into the
+// counters: each thread folds four atoms, a block folds 4,096, and one thread
+// per block issues the atomics.
+constexpr int STATS_T = 1024, STATS_PER = 4;
+
+__device__ inline int stat_counter(int q) {
+  switch (q) {
+    case S_NN: return C_MAX_NB;
+    case S_VMAX: return C_MAX_V;
+    case S_CAND: return C_CANDIDATES;
+    case S_TESTS: return C_PLANE_TESTS;
+    case S_NEWV: return C_NEW_VERTS;
+    case S_TIES: return C_NEAR_TIE;
+    case S_BAD: return C_OVERFLOW;
+    case S_VERT: return C_VERT;
+    case S_EXTV: return C_EXT_VERT;
+    case S_TET: return C_TET;
+    case S_TRI: return C_TRI;
+    case S_EXTTRI: return C_EXT_TRI;
+    case S_EDGE: return C_EDGE;
+    default: return C_EXT_EDGE;
+  }
+}
+
+__global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
+  __shared__ long long part[STATS_T / 64][S_COUNT];
+  long long acc[S_COUNT];
+  for (int q = 0; q < S_COUNT; ++q) acc[q] = 0;
+  const int base = blockIdx.x * STATS_T * STATS_PER + threadIdx.x;
+  for (int j = 0; j < STATS_PER; ++j) {
+    const int a = base + j * STATS_T;
+    if (a >= b.n) break;
+    const int* st = b.stat + (size_t)a * STAT_STRIDE;
+    for (int q = 0; q < S_COUNT; ++q) {
+      const long long v = st[q];
+      acc[q] = (q == S_NN || q == S_VMAX) ? max(acc[q], v) : acc[q] + v;
+    }
+  }
+  for (int q = 0; q < S_COUNT; ++q)
+    for (int off = 32; off > 0; off >>= 1) {
+      const long long o = __shfl_xor(acc[q], off, 64);
+      acc[q] = (q == S_NN || q == S_VMAX) ? max(acc[q], o) : acc[q] + o;
+    }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < S_COUNT; ++q) part[wv][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < S_COUNT) {
+    const int q = threadIdx.x;
+    long long v = part[0][q];
+    for (int w = 1; w < STATS_T / 64; ++w) v = (q == S_NN || q == S_VMAX) ? max(v, part[w][q]) : v + part[w][q];
+    if (q == S_NN || q == S_VMAX) atomicMax(&b.ctr[stat_counter(q)], (unsigned long long)v);
+    else if (v) atomicAdd(&b.ctr[stat_counter(q)], (unsigned long long)v);
   }
 }
 
@@ -949,10 +1032,13 @@ struct TermsLds {
   unsigned tet[KT_CAP];
   unsigned tri[KTR_CAP];
   double S[KN_CAP];                 // cap areas of exterior edges
-  double phi[KT_CAP][3];            // dihedral fractions along (i,a), (i,b), (i,c)
-  double tg[KT_CAP][3][3];          // tet contributions to a, b, c
-  double rg[KTR_CAP][2][3];         // triangle contributions to a, b
-  double red[64];
+  union {
+    struct {
+      double phi[64][3];    // dihedral fractions along (i,a), (i,b), (i,c) of one chunk of tetrahedra
+      double tg[64][3][3];  // their contributions to a, b, c
+    } t;
+    double rg[64][2][3];    // contributions of one chunk of triangles to a, b
+  } c;
 };
 
 template <typename T>
@@ -1088,79 +1174,103 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
     L.S[k] = Sk;
   }
   __syncthreads();
-  // tetrahedra: solid angle at i, dihedral angles along the three edges at i
-  double omega_sum = 0.0;
-  for (int t = lane; t < nt; t += 64) {
-    const unsigned w = L.tet[t];
-    const int ks[3] = {(int)(w & 255u), (int)((w >> 8) & 255u), (int)((w >> 16) & 255u)};
-    if (ks[0] >= nk || ks[1] >= nk || ks[2] >= nk) {  // never produced by k_star; keeps LDS reads in range
-      L.phi[t][0] = L.phi[t][1] = L.phi[t][2] = 0.0;
-      for (int c = 0; c < 3; ++c) L.tg[t][c][0] = L.tg[t][c][1] = L.tg[t][c][2] = 0.0;
-      continue;
+  // tetrahedra, in chunks of 64 (one per lane): solid angle at i, dihedral
+  // angles along the three edges at i and their gradient contributions; after
+  // each chunk, lane k adds the entries that touch K-neighbour k, in order
+  double omega_sum = 0.0, phi_sum = 0.0;
+  double gx = 0.0, gy = 0.0, gz = 0.0;  // gradient block of K-neighbour k
+  for (int c0 = 0; c0 < nt; c0 += 64) {
+    const int t = c0 + lane;
+    if (t < nt) {
+      const unsigned w = L.tet[t];
+      const int ks[3] = {(int)(w & 255u), (int)((w >> 8) & 255u), (int)((w >> 16) & 255u)};
+      if (ks[0] >= nk || ks[1] >= nk || ks[2] >= nk) {  // never produced by k_star; keeps LDS reads in range
+        L.c.t.phi[lane][0] = L.c.t.phi[lane][1] = L.c.t.phi[lane][2] = 0.0;
+        for (int c = 0; c < 3; ++c) L.c.t.tg[lane][c][0] = L.c.t.tg[lane][c][1] = L.c.t.tg[lane][c][2] = 0.0;
+      } else {
+        bool dbl = sizeof(T) == sizeof(double);
+        if (!dbl)
+          dbl = tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
+                            L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin;
+        double ph[3];
+        const double om = dbl ? tet_item<double>(L, ks, extm, Si, grad, ph, L.c.t.tg[lane])
+                              : tet_item<T>(L, ks, extm, Si, grad, ph, L.c.t.tg[lane]);
+        omega_sum += om;
+        L.c.t.phi[lane][0] = ph[0], L.c.t.phi[lane][1] = ph[1], L.c.t.phi[lane][2] = ph[2];
+      }
     }
-    bool dbl = sizeof(T) == sizeof(double);
-    if (!dbl)
-      dbl = tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]], L.px[ks[2]],
-                        L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin;
-    double ph[3];
-    const double om = dbl ? tet_item<double>(L, ks, extm, Si, grad, ph, L.tg[t])
-                          : tet_item<T>(L, ks, extm, Si, grad, ph, L.tg[t]);
-    omega_sum += om;
-    L.phi[t][0] = ph[0], L.phi[t][1] = ph[1], L.phi[t][2] = ph[2];
+    __syncthreads();
+    if (k < nk) {
+      const int lim = min(64, nt - c0);
+      for (int q = 0; q < lim; ++q) {
+        const unsigned w = L.tet[c0 + q];
+        const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u), c = (int)((w >> 16) & 255u);
+        const int pos = a == k ? 0 : bb == k ? 1 : c == k ? 2 : -1;
+        if (pos < 0) continue;
+        phi_sum += L.c.t.phi[q][pos];
+        if (grad) gx += L.c.t.tg[q][pos][0], gy += L.c.t.tg[q][pos][1], gz += L.c.t.tg[q][pos][2];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // edges: outer dihedral coefficient Phi = 1 - sum of the K-tet dihedral fractions
   double area_part = 0.0;
-  double ex = 0, ey = 0, ez = 0;  // edge contribution to atom k
   if (kext) {
-    double phi_sum = 0.0;
-    for (int t = 0; t < nt; ++t) {
-      const unsigned w = L.tet[t];
-      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u), c = (int)((w >> 16) & 255u);
-      if (a == k) phi_sum += L.phi[t][0];
-      else if (bb == k) phi_sum += L.phi[t][1];
-      else if (c == k) phi_sum += L.phi[t][2];
-    }
     const double Phi = 1.0 - phi_sum;
     area_part -= Phi * Sk;
-    ex = -Phi * (double)gS.x;
-    ey = -Phi * (double)gS.y;
-    ez = -Phi * (double)gS.z;
+    gx -= Phi * (double)gS.x;
+    gy -= Phi * (double)gS.y;
+    gz -= Phi * (double)gS.z;
   }
-  // exterior triangles: Eq. 6 through the triple point
-  for (int r = lane; r < nr; r += 64) {
-    const unsigned w = L.tri[r];
-    const int ka = (int)(w & 255u), kb = (int)((w >> 8) & 255u);
-    if (ka >= nk || kb >= nk) {  // never produced by k_star; keeps LDS reads in range
-      for (int c = 0; c < 3; ++c) L.rg[r][0][c] = L.rg[r][1][c] = 0.0;
-      continue;
+  // exterior triangles: Eq. 6 through the triple point, in chunks of 64
+  for (int c0 = 0; c0 < nr; c0 += 64) {
+    const int r = c0 + lane;
+    if (r < nr) {
+      const unsigned w = L.tri[r];
+      const int ka = (int)(w & 255u), kb = (int)((w >> 8) & 255u);
+      double St = 0.0;
+      double G[2][3] = {{0, 0, 0}, {0, 0, 0}};
+      double ct = 0.0;
+      if (ka < nk && kb < nk) {  // always true for k_star's output; keeps LDS reads in range
+        ct = 1.0 - 0.5 * (double)(w >> 16);
+        // triple point in double: y in the plane of the centres, x = y + sqrt(-s) n
+        const double ax = L.px[ka], ay = L.py[ka], az = L.pz[ka];
+        const double bx = L.px[kb], by = L.py[kb], bz = L.pz[kb];
+        const double wa = L.pR[ka] * L.pR[ka], wb = L.pR[kb] * L.pR[kb];
+        const double aa = ax * ax + ay * ay + az * az, bb2 = bx * bx + by * by + bz * bz,
+                     ab = ax * bx + ay * by + az * bz;
+        const double ra = aa - wa + wi, rb = bb2 - wb + wi;
+        const double det = 2.0 * (aa * bb2 - ab * ab);
+        const double al = (ra * bb2 - rb * ab) / det, be = (aa * rb - ab * ra) / det;
+        const double yx = al * ax + be * bx, yy = al * ay + be * by, yz = al * az + be * bz;
+        const double s = yx * yx + yy * yy + yz * yz - wi;
+        if (s < 0.0) {
+          const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+          const double f = sqrt(-s / (nx * nx + ny * ny + nz * nz));
+          const double X0 = yx + f * nx, X1 = yy + f * ny, X2 = yz + f * nz;
+          bool dbl = sizeof(T) == sizeof(double);
+          if (!dbl)
+            dbl = (-s < kTripleDepthMin * wi) || tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin;
+          St = dbl ? tri_item<double>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
+                   : tri_item<T>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
+        }
+      }
+      area_part += ct * St;
+      if (grad)
+        for (int c = 0; c < 3; ++c) L.c.rg[lane][0][c] = ct * G[0][c], L.c.rg[lane][1][c] = ct * G[1][c];
     }
-    const double ct = 1.0 - 0.5 * (double)(w >> 16);
-    // triple point in double: y in the plane of the centres, x = y + sqrt(-s) n
-    const double ax = L.px[ka], ay = L.py[ka], az = L.pz[ka];
-    const double bx = L.px[kb], by = L.py[kb], bz = L.pz[kb];
-    const double wa = L.pR[ka] * L.pR[ka], wb = L.pR[kb] * L.pR[kb];
-    const double aa = ax * ax + ay * ay + az * az, bb2 = bx * bx + by * by + bz * bz, ab = ax * bx + ay * by + az * bz;
-    const double ra = aa - wa + wi, rb = bb2 - wb + wi;
-    const double det = 2.0 * (aa * bb2 - ab * ab);
-    const double al = (ra * bb2 - rb * ab) / det, be = (aa * rb - ab * ra) / det;
-    const double yx = al * ax + be * bx, yy = al * ay + be * by, yz = al * az + be * bz;
-    const double s = yx * yx + yy * yy + yz * yz - wi;
-    double St = 0.0;
-    double G[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    if (s < 0.0) {
-      const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
-      const double f = sqrt(-s / (nx * nx + ny * ny + nz * nz));
-      const double X0 = yx + f * nx, X1 = yy + f * ny, X2 = yz + f * nz;
-      bool dbl = sizeof(T) == sizeof(double);
-      if (!dbl)
-        dbl = (-s < kTripleDepthMin * wi) || tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin;
-      St = dbl ? tri_item<double>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
-               : tri_item<T>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
+    if (!grad) continue;
+    __syncthreads();
+    if (k < nk) {
+      const int lim = min(64, nr - c0);
+      for (int q = 0; q < lim; ++q) {
+        const unsigned w = L.tri[c0 + q];
+        const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u);
+        const int pos = a == k ? 0 : bb == k ? 1 : -1;
+        if (pos >= 0) gx += L.c.rg[q][pos][0], gy += L.c.rg[q][pos][1], gz += L.c.rg[q][pos][2];
+      }
     }
-    area_part += ct * St;
-    if (grad)
-      for (int c = 0; c < 3; ++c) L.rg[r][0][c] = ct * G[0][c], L.rg[r][1][c] = ct * G[1][c];
+    __syncthreads();
   }
   // area: Omega_i 4 pi w_i - sum Phi S + sum c S_t  (deterministic butterfly sums)
   double os = omega_sum, ap = area_part;
@@ -1170,22 +1280,8 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   }
   if (lane == 0) b.area[i] = (1.0 - os) * Si + ap;
   if (!grad) return;
-  __syncthreads();
-  // gradient block for K-neighbour k: edge + tetrahedra + triangles containing k
-  double gx = ex, gy = ey, gz = ez;
+  // gradient block of K-neighbour k: edge + tetrahedra + triangles containing k
   if (k < nk) {
-    for (int t = 0; t < nt; ++t) {
-      const unsigned w = L.tet[t];
-      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u), c = (int)((w >> 16) & 255u);
-      const int pos = a == k ? 0 : bb == k ? 1 : c == k ? 2 : -1;
-      if (pos >= 0) gx += L.tg[t][pos][0], gy += L.tg[t][pos][1], gz += L.tg[t][pos][2];
-    }
-    for (int r = 0; r < nr; ++r) {
-      const unsigned w = L.tri[r];
-      const int a = (int)(w & 255u), bb = (int)((w >> 8) & 255u);
-      const int pos = a == k ? 0 : bb == k ? 1 : -1;
-      if (pos >= 0) gx += L.rg[r][pos][0], gy += L.rg[r][pos][1], gz += L.rg[r][pos][2];
-    }
     double* row = b.rows + ((size_t)i * ROW + k) * 3;
     row[0] = gx, row[1] = gy, row[2] = gz;
   } else {
@@ -1277,7 +1373,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (words) k_zero<<<blocks(words, 256), 256, 0, s>>>((unsigned*)p, words);
 }
 void launch_prep(const Bufs& b, hipStream_t s) {
-  if (b.n) k_prep<<<blocks(b.n, 256), 256, 0, s>>>(b);
+  if (b.n) k_prep<<<blocks(b.n, PREP_T), PREP_T, 0, s>>>(b);
 }
 void launch_grid(const Bufs& b, hipStream_t s) {
   if (b.n) k_grid<<<1, 1024, 0, s>>>(b);
@@ -1297,6 +1393,9 @@ void launch_scatter(const Bufs& b, hipStream_t s) {
 }
 void launch_star(const Bufs& b, hipStream_t s) {
   if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
+}
+void launch_stats(const Bufs& b, hipStream_t s) {
+  if (b.n) k_stats<<<blocks(b.n, STATS_T * STATS_PER), STATS_T, 0, s>>>(b);
 }
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
   if (!b.n) return;

@@ -38,12 +38,30 @@ enum Counter {
   C_PLANE_TESTS,   // algorithmic work counters of the star kernel
   C_NEW_VERTS,
   C_CANDIDATES,
-  C_CYC_GATHER,    // shader cycles per star phase, summed over waves
-  C_CYC_SORT,
-  C_CYC_CLIP,
-  C_CYC_FINAL,
   C_COUNT
 };
+
+// Per-atom record of the star kernel (plain stores, one per atom), summed into
+// the counters by k_stats: a wavefront never issues a device-scope atomic on
+// the shared counters, which would serialise every wavefront on one L2 line.
+enum Stat {
+  S_NN = 0,   // overlapping neighbours (max)
+  S_VMAX,     // largest polytope while clipping (max)
+  S_CAND,     // neighbour candidates read
+  S_TESTS,    // (vertex, plane) side tests
+  S_NEWV,     // vertices created
+  S_TIES,     // near-degenerate decisions
+  S_BAD,      // capacity exceeded or broken star
+  S_VERT,     // atom is a vertex of K
+  S_EXTV,     // ... an exterior one
+  S_TET,      // owned simplices (lowest index)
+  S_TRI,
+  S_EXTTRI,
+  S_EDGE,
+  S_EXTEDGE,
+  S_COUNT
+};
+constexpr int STAT_STRIDE = 16;  // ints per atom record
 
 // Vertex flags.
 constexpr uint8_t VF_IN = 1, VF_EXT = 2;
@@ -79,6 +97,7 @@ struct Bufs {
   unsigned* ktet = nullptr;            // n * KT_CAP, 3 x 8-bit K-neighbour slots
   int* ktr_cnt = nullptr;
   unsigned* ktri = nullptr;            // n * KTR_CAP, 2 x 8-bit slots + n_tet << 16
+  int* stat = nullptr;       // n * STAT_STRIDE per-atom records of the star kernel
   // results
   double* area = nullptr;
   double* rows = nullptr;    // n * ROW * 3
@@ -99,6 +118,7 @@ void launch_count(const Bufs& b, hipStream_t s);
 void launch_scan(const Bufs& b, hipStream_t s);
 void launch_scatter(const Bufs& b, hipStream_t s);
 void launch_star(const Bufs& b, hipStream_t s);
+void launch_stats(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -242,18 +242,31 @@ def md_frames(xyz, seed, frames, sigma=0.02):
         yield cur
 
 
-def globule_complex(n_total, seed, chain_atoms=2500):
+def _chain(args):
+    return heavy_chain(*args)
+
+
+def globule_complex(n_total, seed, chain_atoms=2500, workers=8):
     """A complex of compact globules (one chain each, recipe above).
 
     Large molecules are built this way because the compression step of a single
     chain stops reaching the target density with all exclusions above a few
     thousand atoms.  ceil(n_total / chain_atoms) chains are placed along
     Fibonacci-sphere directions, each moved out until it is at least 3.0 A from
-    every chain placed before it.
+    every chain placed before it.  The chains are drawn in up to ``workers``
+    fresh (spawned) processes; each has its own seed, so the result does not
+    depend on the worker count.
     """
     chains = max(1, -(-n_total // chain_atoms))
     sizes = [n_total // chains + (1 if k < n_total % chains else 0) for k in range(chains)]
-    parts = [heavy_chain(n, seed * 101 + k) for k, n in enumerate(sizes)]
+    jobs = [(n, seed * 101 + k) for k, n in enumerate(sizes)]
+    if chains > 1 and workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, chains), mp_context=mp.get_context("spawn")) as ex:
+            parts = list(ex.map(_chain, jobs))
+    else:
+        parts = [_chain(j) for j in jobs]
     k = np.arange(chains) + 0.5
     phi = np.arccos(1 - 2 * k / chains)
     theta = np.pi * (1 + 5 ** 0.5) * k
