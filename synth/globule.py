@@ -70,7 +70,9 @@ def _grow(n, rng, radius):
     """Self-avoiding walk of n atoms inside a sphere, with backtracking.
 
     Dead ends are left by backtracking; the depth grows with the number of
-    consecutive failures so that a jammed region is always escaped.
+    consecutive failures, and a walk that makes no new progress for 20,000
+    attempts retreats 32, 64, ... 1024 atoms, so that a jammed region is always
+    escaped.
     """
     pos = np.zeros((n, 3))
     grid = _Grid(NONBONDED_MIN)
@@ -78,7 +80,20 @@ def _grow(n, rng, radius):
     grid.add(0, pos[0])
     i = 1
     stuck = 0
+    best, since_best, escape = 1, 0, 0
     while i < n:
+        if i > best:
+            best, since_best = i, 0
+        since_best += 1
+        if since_best > 20000:
+            # a pocket the short backtracks keep regrowing into: retreat further
+            # each time (never taken while the chain keeps making progress)
+            escape += 1
+            since_best = 0
+            for _ in range(min(i - 1, 16 << min(escape, 6))):
+                i -= 1
+                grid.remove(i, pos[i])
+            best = i
         k = 32
         steps = rng.uniform(BOND_MIN, BOND_MAX, size=k)[:, None] * _unit(rng, k)
         cand = pos[i - 1] + steps
@@ -246,6 +261,18 @@ def _chain(args):
     return heavy_chain(*args)
 
 
+def heavy_chains(jobs, workers=8):
+    """heavy_chain(n, seed) for every (n, seed) in ``jobs``, drawn in up to
+    ``workers`` spawned processes (the results do not depend on the count)."""
+    jobs = list(jobs)
+    if len(jobs) > 1 and workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
+            return list(ex.map(_chain, jobs))
+    return [_chain(j) for j in jobs]
+
+
 def globule_complex(n_total, seed, chain_atoms=2500, workers=8):
     """A complex of compact globules (one chain each, recipe above).
 
@@ -259,14 +286,7 @@ def globule_complex(n_total, seed, chain_atoms=2500, workers=8):
     """
     chains = max(1, -(-n_total // chain_atoms))
     sizes = [n_total // chains + (1 if k < n_total % chains else 0) for k in range(chains)]
-    jobs = [(n, seed * 101 + k) for k, n in enumerate(sizes)]
-    if chains > 1 and workers > 1:
-        import multiprocessing as mp
-        from concurrent.futures import ProcessPoolExecutor
-        with ProcessPoolExecutor(max_workers=min(workers, chains), mp_context=mp.get_context("spawn")) as ex:
-            parts = list(ex.map(_chain, jobs))
-    else:
-        parts = [_chain(j) for j in jobs]
+    parts = heavy_chains([(n, seed * 101 + k) for k, n in enumerate(sizes)], workers)
     k = np.arange(chains) + 0.5
     phi = np.arccos(1 - 2 * k / chains)
     theta = np.pi * (1 + 5 ** 0.5) * k
