@@ -272,7 +272,8 @@ def main():
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,
         "diagnostics": {k: diag[k] for k in ("max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
-                                             "overflow", "plane_tests", "new_vertices", "candidates")},
+                                             "overflow", "plane_tests", "new_vertices", "candidates",
+                                             "planes_used", "max_planes_used", "atoms_over_64_planes")},
         "sasa_total": float(area.sum().item()),
     }
     print(json.dumps(out))

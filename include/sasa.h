@@ -157,6 +157,9 @@ typedef struct {
   int64_t plane_tests;        /* (vertex, plane) side tests while clipping */
   int64_t new_vertices;       /* cell vertices created (three-plane solves) */
   int64_t candidates;         /* neighbour-candidate distance tests */
+  int64_t planes_used;        /* radical planes visited by the clipping loops (sum over atoms) */
+  int64_t max_planes_used;    /* ... largest for one atom */
+  int64_t atoms_over_64_planes; /* atoms whose clipping visited more than 64 planes */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

@@ -49,7 +49,8 @@ class sasa_diag(ctypes.Structure):
         "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
         "capacity_retries", "input_errors", "overflow")] + [
         (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_terms", "ms_gather")] + [
-        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates")]
+        (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "planes_used",
+                                            "max_planes_used", "atoms_over_64_planes")]
 
 
 _lib = None

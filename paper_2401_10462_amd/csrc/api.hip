@@ -91,6 +91,7 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&b.cellid, cap));
     HIP_TRY(c, grow(&b.sorted, cap));
     HIP_TRY(c, grow(&b.spos, cap));
+    HIP_TRY(c, grow(&b.smc, cap));
     HIP_TRY(c, grow(&b.vflag, cap));
     HIP_TRY(c, grow(&b.stat, cap * STAT_STRIDE));
     HIP_TRY(c, grow(&b.kn_cnt, cap));
@@ -140,19 +141,22 @@ bool host_inputs_ok(int64_t n, const double* xyz, const double* radii) {
 }
 
 int read_counters(Ctx* c, hipStream_t s) {
-  HIP_TRY(c, hipMemcpyAsync(c->ctr_h, c->b.ctr, C_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(c->ctr_h, c->b.ctr, CTR_BYTES, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   c->pending = false;
   const unsigned long long* h = c->ctr_h;
-  c->diag.max_neighbours = (int64_t)h[C_MAX_NB];
-  c->diag.max_cell_vertices = (int64_t)h[C_MAX_V];
-  c->diag.near_ties = (int64_t)h[C_NEAR_TIE];
-  c->diag.lost_pairs = (int64_t)h[C_LOST_PAIR];
-  c->diag.input_errors = (int64_t)h[C_BAD_INPUT];
-  c->diag.overflow = (int64_t)h[C_OVERFLOW];
-  c->diag.plane_tests = (int64_t)h[C_PLANE_TESTS];
-  c->diag.new_vertices = (int64_t)h[C_NEW_VERTS];
-  c->diag.candidates = (int64_t)h[C_CANDIDATES];
+  c->diag.max_neighbours = (int64_t)h[ctr_slot(C_MAX_NB)];
+  c->diag.max_cell_vertices = (int64_t)h[ctr_slot(C_MAX_V)];
+  c->diag.near_ties = (int64_t)h[ctr_slot(C_NEAR_TIE)];
+  c->diag.lost_pairs = (int64_t)h[ctr_slot(C_LOST_PAIR)];
+  c->diag.input_errors = (int64_t)h[ctr_slot(C_BAD_INPUT)];
+  c->diag.overflow = (int64_t)h[ctr_slot(C_OVERFLOW)];
+  c->diag.plane_tests = (int64_t)h[ctr_slot(C_PLANE_TESTS)];
+  c->diag.new_vertices = (int64_t)h[ctr_slot(C_NEW_VERTS)];
+  c->diag.candidates = (int64_t)h[ctr_slot(C_CANDIDATES)];
+  c->diag.planes_used = (int64_t)h[ctr_slot(C_PLANES_USED)];
+  c->diag.max_planes_used = (int64_t)h[ctr_slot(C_MAX_PLANES)];
+  c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
   if (c->timed) {
     float ms[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
@@ -162,11 +166,11 @@ int read_counters(Ctx* c, hipStream_t s) {
     c->diag.ms_gather = ms[3];
     c->timed = false;
   }
-  if (h[C_BAD_INPUT]) {
+  if (h[ctr_slot(C_BAD_INPUT)]) {
     c->kept = false;
     return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
   }
-  if (h[C_OVERFLOW]) {
+  if (h[ctr_slot(C_OVERFLOW)]) {
     c->kept = false;
     return fail(c, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
   }
@@ -219,14 +223,19 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
   const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
-  launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
-  launch_zero(b.cnt, (size_t)b.cell_cap * sizeof(int), s);
-  launch_zero(b.mol_box, (size_t)b.nmol * 6 * sizeof(unsigned long long), s);
-  launch_prep(b, s);
-  launch_grid(b, s);
-  launch_count(b, s);
-  launch_scan(b, s);
-  launch_scatter(b, s);
+  if (nmol <= 1 && n <= ONE_BLOCK_MAX_ATOMS) {
+    launch_cells_one(b, s);  // also clears the counters
+    if (!n) launch_zero(b.ctr, CTR_BYTES, s);
+  } else {
+    launch_zero(b.ctr, CTR_BYTES, s);
+    launch_zero(b.cnt, (size_t)b.cell_cap * sizeof(int), s);
+    launch_zero(b.mol_box, (size_t)b.nmol * 6 * sizeof(unsigned long long), s);
+    launch_prep(b, s);
+    launch_grid(b, s);
+    launch_count(b, s);
+    launch_scan(b, s);
+    launch_scatter(b, s);
+  }
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   launch_star(b, s);
   launch_stats(b, s);
@@ -282,13 +291,13 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
     return fail(nullptr, SASA_E_DEVICE, "no such HIP device");
   }
   hipError_t e = hipSetDevice(c->device);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->b.ctr, C_COUNT * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->ctr_h, C_COUNT * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->b.ctr, CTR_BYTES);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->ctr_h, CTR_BYTES);
   if (e != hipSuccess) {
     sasa_destroy(c);
     return fail(nullptr, SASA_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
   }
-  std::memset(c->ctr_h, 0, C_COUNT * sizeof(unsigned long long));
+  std::memset(c->ctr_h, 0, CTR_BYTES);
   if (c->flags & SASA_FLAG_TIMING)
     for (auto& ev : c->ev)
       if (hipEventCreate(&ev) != hipSuccess) {
@@ -312,7 +321,7 @@ void sasa_destroy(void* ctx) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   Bufs& b = c->b;
-  void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos,
+  void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos, b.smc,
                  b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
@@ -392,13 +401,13 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]) {
     if (rc) return rc;
   }
   const unsigned long long* h = c->ctr_h;
-  counts[0] = (int64_t)h[C_VERT];
-  counts[1] = (int64_t)h[C_EDGE];
-  counts[2] = (int64_t)h[C_TRI];
-  counts[3] = (int64_t)h[C_TET];
-  counts[4] = (int64_t)h[C_EXT_VERT];
-  counts[5] = (int64_t)h[C_EXT_EDGE];
-  counts[6] = (int64_t)h[C_EXT_TRI];
+  counts[0] = (int64_t)h[ctr_slot(C_VERT)];
+  counts[1] = (int64_t)h[ctr_slot(C_EDGE)];
+  counts[2] = (int64_t)h[ctr_slot(C_TRI)];
+  counts[3] = (int64_t)h[ctr_slot(C_TET)];
+  counts[4] = (int64_t)h[ctr_slot(C_EXT_VERT)];
+  counts[5] = (int64_t)h[ctr_slot(C_EXT_EDGE)];
+  counts[6] = (int64_t)h[ctr_slot(C_EXT_TRI)];
   counts[7] = c->n;
   return SASA_OK;
 }
@@ -436,9 +445,9 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   b.ex_cap_q = c->ex_cap_q;
   hipStream_t s = nullptr;
   // keep R_max (needed for the cell size), clear everything else
-  unsigned long long rmax_bits = c->ctr_h[C_RMAX_BITS];
-  launch_zero(b.ctr, C_COUNT * sizeof(unsigned long long), s);
-  HIP_TRY(c, hipMemcpyAsync(b.ctr + C_RMAX_BITS, &rmax_bits, sizeof(rmax_bits), hipMemcpyHostToDevice, s));
+  unsigned long long rmax_bits = c->ctr_h[ctr_slot(C_RMAX_BITS)];
+  launch_zero(b.ctr, CTR_BYTES, s);
+  HIP_TRY(c, hipMemcpyAsync(b.ctr + ctr_slot(C_RMAX_BITS), &rmax_bits, sizeof(rmax_bits), hipMemcpyHostToDevice, s));
   launch_star(b, s);
   launch_stats(b, s);
   HIP_TRY(c, hipGetLastError());
@@ -469,7 +478,7 @@ int sasa_footprint(int64_t n, int64_t* bytes) {
   // statistics record, flags, the
   // kept complex, gradient blocks, area and the staging of inputs and outputs;
   // per molecule (at most one per atom): offsets, box, grid geometry
-  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int) * (3 + STAT_STRIDE) + 1 + sizeof(int) * (KN_CAP + 3) +
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int2) + sizeof(int) * (3 + STAT_STRIDE) + 1 + sizeof(int) * (KN_CAP + 3) +
                            sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
                            sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
   const int64_t per_mol = sizeof(int64_t) * 2 + sizeof(unsigned long long) * 6 + sizeof(double4) + sizeof(int4);

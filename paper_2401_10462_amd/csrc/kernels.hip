@@ -32,7 +32,7 @@ __device__ inline int prefix_below(unsigned long long m) {
 }
 
 __device__ inline double rmax_of(const unsigned long long* ctr) {
-  return __longlong_as_double((long long)ctr[C_RMAX_BITS]);
+  return __longlong_as_double((long long)ctr[ctr_slot(C_RMAX_BITS)]);
 }
 
 // Order-preserving map of doubles to unsigned integers (for atomicMax on
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(PREP_T) void k_prep(Bufs b) {
     double r = b.radii[i];
     const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0;
     if (!ok) {
-      atomicAdd(&b.ctr[C_BAD_INPUT], 1ull);
+      atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], 1ull);
       x = y = z = 0.0;
       r = 1.0;
     }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(PREP_T) void k_prep(Bufs b) {
       double r = part[0][q];
       for (int w = 1; w < PREP_T / 64; ++w) r = q < 3 ? fmin(r, part[w][q]) : fmax(r, part[w][q]);
       if (q == 6) {
-        if (r > 0.0) atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(r));
+        if (r > 0.0) atomicMax(&b.ctr[ctr_slot(C_RMAX_BITS)], (unsigned long long)__double_as_longlong(r));
       } else {
         unsigned long long* box = b.mol_box + 6 * (size_t)mol_of(b, first);
         atomicMax(&box[q], q < 3 ? ~ord_bits(r) : ord_bits(r));
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(PREP_T) void k_prep(Bufs b) {
     return;
   }
   const double rmax = wave_max_d(R);
-  if (lane == 0 && rmax > 0.0) atomicMax(&b.ctr[C_RMAX_BITS], (unsigned long long)__double_as_longlong(rmax));
+  if (lane == 0 && rmax > 0.0) atomicMax(&b.ctr[ctr_slot(C_RMAX_BITS)], (unsigned long long)__double_as_longlong(rmax));
   unsigned long long pend = __ballot(live);
   while (pend) {
     const int leader = (int)__builtin_ctzll(pend);
@@ -141,6 +141,24 @@ __global__ __launch_bounds__(PREP_T) void k_prep(Bufs b) {
   }
 }
 
+// Grid over the box [lo, hi] of a molecule of na atoms: cell side R_max,
+// enlarged by factors of 1.25 until the grid has at most 8 na + 8 cells.
+__device__ inline int grid_dims(double lx, double ly, double lz, double hx, double hy, double hz, int64_t na,
+                                double rmax, double4& geo, int& nx, int& ny, int& nz) {
+  const double ex = hx - lx, ey = hy - ly, ez = hz - lz;
+  const double cap = 8.0 * (double)na + 8.0;
+  double s = rmax;
+  double fx, fy, fz;
+  for (;;) {
+    fx = floor(ex / s) + 1.0, fy = floor(ey / s) + 1.0, fz = floor(ez / s) + 1.0;
+    if (fx * fy * fz <= cap) break;
+    s *= 1.25;
+  }
+  nx = (int)fx, ny = (int)fy, nz = (int)fz;
+  geo = make_double4(lx, ly, lz, s);
+  return nx * ny * nz;
+}
+
 // One dense grid per molecule over its bounding box.  The cell side is R_max
 // (so every overlapping pair lies within two cells along each axis), enlarged
 // for sparse, elongated molecules until the grid has at most 8 n_m + 8 cells;
@@ -159,18 +177,8 @@ __global__ __launch_bounds__(1024) void k_grid(Bufs b) {
       if (na > 0) {
         const unsigned long long* box = b.mol_box + 6 * (size_t)k;
         const double lx = from_ord(~box[0]), ly = from_ord(~box[1]), lz = from_ord(~box[2]);
-        const double ex = from_ord(box[3]) - lx, ey = from_ord(box[4]) - ly, ez = from_ord(box[5]) - lz;
-        const double cap = 8.0 * (double)na + 8.0;
-        double s = rmax;
-        double fx, fy, fz;
-        for (;;) {
-          fx = floor(ex / s) + 1.0, fy = floor(ey / s) + 1.0, fz = floor(ez / s) + 1.0;
-          if (fx * fy * fz <= cap) break;
-          s *= 1.25;
-        }
-        nx = (int)fx, ny = (int)fy, nz = (int)fz;
-        cells = nx * ny * nz;
-        geo = make_double4(lx, ly, lz, s);
+        cells = grid_dims(lx, ly, lz, from_ord(box[3]), from_ord(box[4]), from_ord(box[5]), na, rmax, geo, nx, ny,
+                          nz);
       }
     }
     // exclusive scan of the cell counts over this chunk of molecules
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(1024) void k_grid(Bufs b) {
     }
     carry += total;
   }
-  if (threadIdx.x == 0) b.ctr[C_CELLS] = (unsigned long long)carry;
+  if (threadIdx.x == 0) b.ctr[ctr_slot(C_CELLS)] = (unsigned long long)carry;
 }
 
 __device__ inline int cell_index(double v, double lo, double inv_s, int n) {
@@ -275,6 +283,108 @@ __global__ void k_scatter(Bufs b) {
   const int slot = b.start[c] + atomicSub(&b.cnt[c], 1) - 1;
   b.sorted[slot] = i;
   b.spos[slot] = b.pos[i];
+  b.smc[slot] = make_int2(b.mol[i], c);
+}
+
+// ------------------------------------------------------------------ one molecule
+// The whole cell-list stage of a call with one molecule in one block: clears
+// the counters, weights + box, grid, per-cell counts (in LDS when the grid
+// fits), their scan and the scatter into cell order.  It replaces the ten
+// launches of the batched path for the common single-molecule call.
+constexpr int ONE_T = 1024;
+constexpr int ONE_LDS_CELLS = 8192;
+
+__global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
+  __shared__ int lcnt[ONE_LDS_CELLS];
+  __shared__ double red[ONE_T / 64][7];
+  __shared__ int scan_lds[ONE_T];
+  __shared__ int s_cells;
+  const int t = threadIdx.x, lane = t & 63;
+  for (int k = t; k < C_COUNT * CTR_STRIDE; k += ONE_T) b.ctr[k] = 0ull;
+  // weights, box and R_max
+  const double inf = __longlong_as_double(0x7ff0000000000000ll);
+  double v[7] = {inf, inf, inf, -inf, -inf, -inf, 0.0};
+  int bad = 0;
+  for (int i = t; i < b.n; i += ONE_T) {
+    double x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
+    double r = b.radii[i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0)) {
+      ++bad;
+      x = y = z = 0.0;
+      r = 1.0;
+    }
+    const double R = r + b.probe;
+    b.pos[i] = make_double4(x, y, z, R);
+    b.mol[i] = 0;
+    v[0] = fmin(v[0], x), v[1] = fmin(v[1], y), v[2] = fmin(v[2], z);
+    v[3] = fmax(v[3], x), v[4] = fmax(v[4], y), v[5] = fmax(v[5], z);
+    v[6] = fmax(v[6], R);
+  }
+  for (int q = 0; q < 7; ++q) v[q] = q < 3 ? wave_min_d(v[q]) : wave_max_d(v[q]);
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if (lane == 0)
+    for (int q = 0; q < 7; ++q) red[t >> 6][q] = v[q];
+  __syncthreads();  // also orders the counter clearing before the stores below
+  if (lane == 0 && bad) atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], (unsigned long long)bad);
+  if (t == 0) {
+    for (int w = 1; w < ONE_T / 64; ++w)
+      for (int q = 0; q < 7; ++q) v[q] = q < 3 ? fmin(v[q], red[w][q]) : fmax(v[q], red[w][q]);
+    const double rmax = v[6];
+    b.ctr[ctr_slot(C_RMAX_BITS)] = (unsigned long long)__double_as_longlong(rmax);
+    double4 geo;
+    int nx, ny, nz;
+    const int cells = grid_dims(v[0], v[1], v[2], v[3], v[4], v[5], b.n, rmax, geo, nx, ny, nz);
+    b.mol_geo[0] = geo;
+    b.mol_dim[0] = make_int4(nx, ny, nz, 0);
+    b.ctr[ctr_slot(C_CELLS)] = (unsigned long long)cells;
+    s_cells = cells;
+  }
+  __syncthreads();
+  const int cells = s_cells;
+  const bool in_lds = cells <= ONE_LDS_CELLS;
+  int* cnt = in_lds ? lcnt : b.cnt;
+  for (int c = t; c < cells; c += ONE_T) cnt[c] = 0;
+  __syncthreads();
+  const double4 g = b.mol_geo[0];
+  const int4 d = b.mol_dim[0];
+  const double inv_s = 1.0 / g.w;
+  for (int i = t; i < b.n; i += ONE_T) {
+    const double4 p = b.pos[i];
+    const int c = (cell_index(p.z, g.z, inv_s, d.z) * d.y + cell_index(p.y, g.y, inv_s, d.y)) * d.x +
+                  cell_index(p.x, g.x, inv_s, d.x);
+    b.cellid[i] = c;
+    atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  // exclusive scan: thread t owns the contiguous cells [t*per, (t+1)*per)
+  const int per = (cells + ONE_T - 1) / ONE_T;
+  const int c0 = min(t * per, cells), c1 = min(c0 + per, cells);
+  int sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  scan_lds[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < ONE_T; off <<= 1) {
+    const int x = t >= off ? scan_lds[t - off] : 0;
+    __syncthreads();
+    scan_lds[t] += x;
+    __syncthreads();
+  }
+  int run = scan_lds[t] - sum;
+  for (int c = c0; c < c1; ++c) {
+    const int k = cnt[c];
+    b.start[c] = run;
+    cnt[c] = run;  // becomes the fill cursor of the cell
+    run += k;
+  }
+  if (t == ONE_T - 1) b.start[cells] = scan_lds[ONE_T - 1];
+  __syncthreads();
+  for (int i = t; i < b.n; i += ONE_T) {
+    const int c = b.cellid[i];
+    const int slot = atomicAdd(&cnt[c], 1);
+    b.sorted[slot] = i;
+    b.spos[slot] = b.pos[i];
+    b.smc[slot] = make_int2(0, c);
+  }
 }
 
 // ------------------------------------------------------------------ star
@@ -305,17 +415,35 @@ __device__ inline bool has2(unsigned p, unsigned a, unsigned b) {
   return (x == a || y == a || z == a) && (x == b || y == b || z == b);
 }
 
+constexpr int EH_BITS = 8, EH_SIZE = 1 << EH_BITS;  // > 2 x the 1.5 V_CAP edges of a cell
+static_assert(V_CAP <= 128, "vertex slots are 7 bits in the edge table");
+
 struct StarLds {
   int idx[NB_CAP];  // neighbour global ids, slot order = clipping order (nearest plane first)
   double nx[NB_CAP], ny[NB_CAP], nz[NB_CAP], nb[NB_CAP];  // plane n = 2a, offset b
-  double key[NB_CAP];      // signed distance of each plane from p_i
   unsigned sflag[NB_CAP];  // per-slot flags (facet present, K-triangles, K-edge ...)
-  int kidx[NB_CAP];        // slot -> K-neighbour index or -1; candidate ids while gathering
-  double vx[V_CAP], vy[V_CAP], vz[V_CAP];
-  unsigned vp[V_CAP];
-  unsigned pairs[3 * V_CAP];
-  unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
-  int kslot[KN_CAP];        // K-edge slots in slot order
+  int kidx[NB_CAP];        // slot -> K-neighbour index or -1
+  union {
+    struct {  // candidates in arrival order (neighbour search and ranking only)
+      double key[NB_CAP];  // signed distance of the radical plane from p_i
+      int id[NB_CAP];
+    } app;
+    struct {  // the cell across a cut, then the star's lists
+      double vx[V_CAP], vy[V_CAP], vz[V_CAP];
+      unsigned vp[V_CAP];
+      union {
+        unsigned pairs[3 * V_CAP];  // edges of the removed vertices of one cut
+        struct {                    // cell edges by plane pair: code << 7 | first end, second end
+          unsigned key[EH_SIZE];
+          unsigned char second[EH_SIZE];
+        } eh;
+        struct {
+          unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
+          int kslot[KN_CAP];        // K-edge slots in slot order
+        } st;
+      } w;
+    } cl;
+  } u;
 };
 
 enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
@@ -340,6 +468,18 @@ __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, 
   z = (A.b * bcz + B.b * caz + C.b * abz) * inv;
 }
 
+// value of lane l (wave-uniform l)
+__device__ inline double rdl(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// clipping order of candidate (k, i) before (kk, ii): nearest plane first, ties by atom id
+__device__ inline int before(double k, int i, double kk, int ii) { return (k < kk) || (k == kk && i < ii); }
+
 __device__ inline double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
@@ -348,10 +488,13 @@ __device__ inline double wave_max(double v) {
 __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __shared__ StarLds L;
   if ((int)blockIdx.x >= b.n) return;
-  const int i = b.sorted[blockIdx.x];  // cell order: neighbouring blocks share neighbours in cache
+  // atoms in cell order (neighbouring blocks share neighbours in cache); the
+  // atom's id, position, molecule and cell come from the cell-ordered copies
+  const int i = b.sorted[blockIdx.x];
   const int lane = threadIdx.x;
-  const double4 pi = b.pos[i];
-  const int mi = b.mol[i];
+  const double4 pi = b.spos[blockIdx.x];
+  const int2 mc = b.smc[blockIdx.x];
+  const int mi = mc.x;
   const double Ri = pi.w, wi = Ri * Ri;
   const int4 gd = b.mol_dim[mi];
   const double4 gg = b.mol_geo[mi];
@@ -359,7 +502,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   const double h = gg.w;  // cell side of i's molecule (>= R_max)
   int cx, cy, cz;
   {
-    const int c = b.cellid[i] - gd.w;
+    const int c = mc.y - gd.w;
     cx = c % gd.x;
     cy = (c / gd.x) % gd.y;
     cz = c / (gd.x * gd.y);
@@ -404,14 +547,17 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   int nn = 0;
   bool overflow = false;
   long long plane_tests = 0, new_verts = 0;
-  // two chunks of 64 candidates per round: both rounds' loads are in flight together
-  for (int base = 0; base < total; base += 128) {
-    int j[2] = {-1, -1};
-    double4 pj[2];
-    for (int h2 = 0; h2 < 2; ++h2) {
+  // four chunks of 64 candidates per round: all their loads are in flight together
+  for (int base = 0; base < total; base += 256) {
+    int j[4];
+    double4 pj[4];
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
       const int f = base + 64 * h2 + lane;
+      j[h2] = -1;
       if (f < total) {
         int d = 0;
+#pragma unroll
         for (int r = 0; r < 25; ++r) {
           const int sr = __builtin_amdgcn_readlane(row_s, r);
           const int dr = __builtin_amdgcn_readlane(row_d, r);
@@ -422,25 +568,25 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
         pj[h2] = b.spos[k];
       }
     }
-    for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
       bool take = false;
-      double key = 0.0;
+      double dx = 0.0, dy = 0.0, dz = 0.0, d2 = 0.0;
       if (j[h2] >= 0) {
-        const double dx = pj[h2].x - pi.x, dy = pj[h2].y - pi.y, dz = pj[h2].z - pi.z;
-        const double d2 = dx * dx + dy * dy + dz * dz;
+        dx = pj[h2].x - pi.x, dy = pj[h2].y - pi.y, dz = pj[h2].z - pi.z;
+        d2 = dx * dx + dy * dy + dz * dz;
         const double rr = Ri + pj[h2].w;
         take = (j[h2] != i) && (d2 < rr * rr);
-        // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
-        // neighbour at the same centre has no plane (it empties the cell or
-        // cuts nothing) and goes first
-        key = d2 > 0.0 ? (d2 + wi - pj[h2].w * pj[h2].w) / (2.0 * sqrt(d2)) : -1e300;
       }
       const unsigned long long m = __ballot(take);
       if (take) {
         const int at = nn + prefix_below(m);
         if (at < NB_CAP) {
-          L.kidx[at] = j[h2];
-          L.key[at] = key;
+          // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
+          // neighbour at the same centre has no plane (it empties the cell or
+          // cuts nothing) and goes first
+          L.u.app.id[at] = j[h2];
+          L.u.app.key[at] = d2 > 0.0 ? (d2 + wi - pj[h2].w * pj[h2].w) / (2.0 * sqrt(d2)) : -1e300;
         }
       }
       nn += __popcll(m);
@@ -451,31 +597,59 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     nn = NB_CAP;
   }
   __syncthreads();
-  // ---- slots in clipping order: nearest plane first, ties by atom id
-  for (int s = lane; s < nn; s += 64) {
-    const double me = L.key[s];
-    const int id = L.kidx[s];
-    int rank = 0;
-    for (int t = 0; t < nn; ++t) {
-      const double o = L.key[t];
-      rank += (o < me) || (o == me && L.kidx[t] < id);
+  // ---- slots in clipping order: nearest plane first, ties by atom id.  Lane
+  // s holds candidates s, s + 64, s + 128 in registers, ranks each against all
+  // others (read with readlane) and writes its plane at its rank; the
+  // candidates' positions are fetched while the ranks are counted.
+  const int nsets = (nn + 63) >> 6;
+  double ck0 = 0.0, ck1 = 0.0, ck2 = 0.0;
+  int ci0 = -1, ci1 = -1, ci2 = -1;
+  if (lane < nn) ck0 = L.u.app.key[lane], ci0 = L.u.app.id[lane];
+  if (lane + 64 < nn) ck1 = L.u.app.key[lane + 64], ci1 = L.u.app.id[lane + 64];
+  if (lane + 128 < nn) ck2 = L.u.app.key[lane + 128], ci2 = L.u.app.id[lane + 128];
+  double4 cp0 = make_double4(0.0, 0.0, 0.0, 0.0), cp1 = cp0, cp2 = cp0;
+  if (ci0 >= 0) cp0 = b.pos[ci0];
+  if (ci1 >= 0) cp1 = b.pos[ci1];
+  if (ci2 >= 0) cp2 = b.pos[ci2];
+  int rk0 = 0, rk1 = 0, rk2 = 0;
+  for (int hb = 0; hb < nsets; ++hb) {
+    const double kk = hb == 0 ? ck0 : (hb == 1 ? ck1 : ck2);
+    const int ii = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
+    const int lim = min(64, nn - 64 * hb);
+    if (nsets == 1) {
+      for (int t = 0; t < lim; ++t) rk0 += before(rdl(kk, t), rdl(ii, t), ck0, ci0);
+    } else if (nsets == 2) {
+      for (int t = 0; t < lim; ++t) {
+        const double kt = rdl(kk, t);
+        const int it = rdl(ii, t);
+        rk0 += before(kt, it, ck0, ci0);
+        rk1 += before(kt, it, ck1, ci1);
+      }
+    } else {
+      for (int t = 0; t < lim; ++t) {
+        const double kt = rdl(kk, t);
+        const int it = rdl(ii, t);
+        rk0 += before(kt, it, ck0, ci0);
+        rk1 += before(kt, it, ck1, ci1);
+        rk2 += before(kt, it, ck2, ci2);
+      }
     }
-    L.idx[rank] = id;
   }
-  __syncthreads();
-  for (int s = lane; s < nn; s += 64) {
-    const double4 pj = b.pos[L.idx[s]];
+  for (int hb = 0; hb < 3; ++hb) {
+    const int id = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
+    if (id < 0) continue;
+    const int r = hb == 0 ? rk0 : (hb == 1 ? rk1 : rk2);
+    const double4 pj = hb == 0 ? cp0 : (hb == 1 ? cp1 : cp2);
     const double ax = pj.x - pi.x, ay = pj.y - pi.y, az = pj.z - pi.z;
     const double a2 = ax * ax + ay * ay + az * az;
-    L.nx[s] = 2.0 * ax;
-    L.ny[s] = 2.0 * ay;
-    L.nz[s] = 2.0 * az;
-    L.nb[s] = a2 - pj.w * pj.w + wi;
-    L.key[s] = a2 > 0.0 ? L.nb[s] / (2.0 * sqrt(a2)) : -1e300;
-    L.sflag[s] = 0u;
-    L.kidx[s] = -1;
+    L.idx[r] = id;
+    L.nx[r] = 2.0 * ax;
+    L.ny[r] = 2.0 * ay;
+    L.nz[r] = 2.0 * az;
+    L.nb[r] = a2 - pj.w * pj.w + wi;
+    L.sflag[r] = 0u;
+    L.kidx[r] = -1;
   }
-
   // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
   // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
   // registers; LDS holds the cell only across a cut.
@@ -489,16 +663,37 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     z0 = (lane & 4) ? -half : half;
     p0 = ((lane & 1) ? 1u : 0u) | (((lane & 2) ? 3u : 2u) << 10) | (((lane & 4) ? 5u : 4u) << 20);
   }
-  double rho2 = 3.0 * half * half;  // largest |v|^2 of the current cell
+  double rho2 = 3.0 * half * half;  // bound on |v|^2 over the cell (exact when rho_exact)
+  bool rho_exact = true;
   bool empty = false;
   int vmax = 8;
+  int kstop = nn;  // planes visited
   __syncthreads();
   for (int k = 0; k < nn && !overflow; ++k) {
     const double qx = L.nx[k], qy = L.ny[k], qz = L.nz[k], qb = L.nb[k];
-    const double key = L.key[k];
-    // security radius: no later plane (farther from p_i) can reach the cell;
-    // the margin covers the last-bit differences between the sort key and this one
-    if (key >= 0.0 && key * key >= rho2 * (1.0 + 1e-9) + 1e-12) break;
+    // security radius: the plane's signed distance from p_i is b / |n| (its
+    // ranking key); once it reaches the largest |v| of the cell, no plane from
+    // here on can cut it.  Tested without a root or division as b >= 0 and
+    // b^2 >= rho^2 |n|^2, with a margin for the last-bit differences between
+    // this form and the ranking key.  A neighbour at the same centre (n = 0)
+    // has no plane and never ends the loop.  rho^2 is kept as an upper bound
+    // (a cut never moves a vertex away from p_i) and made exact only when the
+    // bound would end the loop.
+    const double qn2 = qx * qx + qy * qy + qz * qz;
+    const bool far = qn2 > 0.0 && qb >= 0.0;
+    if (far && qb * qb >= (rho2 * (1.0 + 1e-9) + 1e-12) * qn2) {
+      if (!rho_exact) {
+        double r2 = 0.0;
+        if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
+        if (lane + 64 < nv) r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
+        rho2 = wave_max(r2);
+        rho_exact = true;
+      }
+      if (qb * qb >= (rho2 * (1.0 + 1e-9) + 1e-12) * qn2) {
+        kstop = k;
+        break;
+      }
+    }
     const bool r0 = lane < nv && qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
     const bool r1 = lane + 64 < nv && qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
     plane_tests += nv;
@@ -508,21 +703,22 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     if (nrem == 0) continue;
     if (nrem == nv) {
       empty = true;
+      kstop = k + 1;
       break;
     }
     const unsigned pid = 6u + (unsigned)k;
     // removed vertices list their three edges (plane pairs)
     if (r0) {
       const int rk = prefix_below(m0);
-      L.pairs[3 * rk + 0] = pid1(p0) | (pid2(p0) << 10);
-      L.pairs[3 * rk + 1] = pid0(p0) | (pid2(p0) << 10);
-      L.pairs[3 * rk + 2] = pid0(p0) | (pid1(p0) << 10);
+      L.u.cl.w.pairs[3 * rk + 0] = pid1(p0) | (pid2(p0) << 10);
+      L.u.cl.w.pairs[3 * rk + 1] = pid0(p0) | (pid2(p0) << 10);
+      L.u.cl.w.pairs[3 * rk + 2] = pid0(p0) | (pid1(p0) << 10);
     }
     if (r1) {
       const int rk = nr0 + prefix_below(m1);
-      L.pairs[3 * rk + 0] = pid1(p1) | (pid2(p1) << 10);
-      L.pairs[3 * rk + 1] = pid0(p1) | (pid2(p1) << 10);
-      L.pairs[3 * rk + 2] = pid0(p1) | (pid1(p1) << 10);
+      L.u.cl.w.pairs[3 * rk + 0] = pid1(p1) | (pid2(p1) << 10);
+      L.u.cl.w.pairs[3 * rk + 1] = pid0(p1) | (pid2(p1) << 10);
+      L.u.cl.w.pairs[3 * rk + 2] = pid0(p1) | (pid1(p1) << 10);
     }
     __syncthreads();
     const int nkeep = nv - nrem;
@@ -531,24 +727,31 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     const unsigned long long k0 = __ballot(lane < nv && !r0), k1 = __ballot(lane + 64 < nv && !r1);
     if (lane < nv && !r0) {
       const int d = prefix_below(k0);
-      L.vx[d] = x0, L.vy[d] = y0, L.vz[d] = z0, L.vp[d] = p0;
+      L.u.cl.vx[d] = x0, L.u.cl.vy[d] = y0, L.u.cl.vz[d] = z0, L.u.cl.vp[d] = p0;
     }
     if (lane + 64 < nv && !r1) {
       const int d = __popcll(k0) + prefix_below(k1);
-      L.vx[d] = x1, L.vy[d] = y1, L.vz[d] = z1, L.vp[d] = p1;
+      L.u.cl.vx[d] = x1, L.u.cl.vy[d] = y1, L.u.cl.vz[d] = z1, L.u.cl.vp[d] = p1;
     }
     // an edge with exactly one removed end crosses the plane: new vertex on it,
     // solved from its three planes in ascending id order (canonical)
+    // (up to 64 edges, lane e holds edge e and counts its copies with
+    // readlane; more edges take the LDS loop)
     const int ne = 3 * nrem;
     int ncross = 0;
     for (int base = 0; base < ne; base += 64) {
       const int e = base + lane;
       bool cross = false;
       unsigned pr = 0;
-      if (e < ne) {
-        pr = L.pairs[e];
+      if (ne <= 64) {
+        pr = e < ne ? L.u.cl.w.pairs[e] : 0xffffffffu;
         int c = 0;
-        for (int t = 0; t < ne; ++t) c += (L.pairs[t] == pr);
+        for (int t = 0; t < ne; ++t) c += (unsigned)__builtin_amdgcn_readlane((int)pr, t) == pr;
+        cross = e < ne && c == 1;
+      } else if (e < ne) {
+        pr = L.u.cl.w.pairs[e];
+        int c = 0;
+        for (int t = 0; t < ne; ++t) c += (L.u.cl.w.pairs[t] == pr);
         cross = (c == 1);
       }
       const unsigned long long cm = __ballot(cross);
@@ -559,10 +762,10 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
           double x, y, z;
           solve3(plane_of(L, pid0(tri3), half), plane_of(L, pid1(tri3), half), plane_of(L, pid2(tri3), half), x,
                  y, z);
-          L.vx[slot] = x;
-          L.vy[slot] = y;
-          L.vz[slot] = z;
-          L.vp[slot] = tri3;
+          L.u.cl.vx[slot] = x;
+          L.u.cl.vy[slot] = y;
+          L.u.cl.vz[slot] = z;
+          L.u.cl.vp[slot] = tri3;
         }
       }
       ncross += __popcll(cm);
@@ -577,16 +780,10 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     __syncthreads();
     x0 = y0 = z0 = x1 = y1 = z1 = 0.0;
     p0 = p1 = 0u;
-    double r2 = 0.0;
-    if (lane < nv) {
-      x0 = L.vx[lane], y0 = L.vy[lane], z0 = L.vz[lane], p0 = L.vp[lane];
-      r2 = x0 * x0 + y0 * y0 + z0 * z0;
-    }
-    if (lane + 64 < nv) {
-      x1 = L.vx[lane + 64], y1 = L.vy[lane + 64], z1 = L.vz[lane + 64], p1 = L.vp[lane + 64];
-      r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
-    }
-    rho2 = wave_max(r2);
+    if (lane < nv) x0 = L.u.cl.vx[lane], y0 = L.u.cl.vy[lane], z0 = L.u.cl.vz[lane], p0 = L.u.cl.vp[lane];
+    if (lane + 64 < nv)
+      x1 = L.u.cl.vx[lane + 64], y1 = L.u.cl.vy[lane + 64], z1 = L.u.cl.vz[lane + 64], p1 = L.u.cl.vp[lane + 64];
+    rho_exact = false;
     __syncthreads();  // the next cut overwrites pairs / vertices only after everyone has read
   }
   int* st = b.stat + (size_t)i * STAT_STRIDE;
@@ -596,6 +793,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     st[S_CAND] = total;
     st[S_TESTS] = (int)plane_tests;
     st[S_NEWV] = (int)new_verts;
+    st[S_KSTOP] = kstop;
   }
   if (overflow) {
     if (lane == 0) {
@@ -637,21 +835,49 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     }
   }
   __syncthreads();
-  // cell edges: partner of each of my vertices along each of its three plane
-  // pairs; an edge is handled by its lower vertex.  Triangles are appended in
-  // a fixed (vertex, pair) order so that the star is deterministic.
+  // cell edges: the two end vertices of an edge (a plane pair) meet in a small
+  // LDS hash table keyed by the pair: the first to arrive claims an entry
+  // (atomic compare-and-swap), the second finds it and leaves its slot there.
+  // An edge is handled by its lower vertex; triangles are appended in a fixed
+  // (vertex, pair) order so that the star is deterministic.
+  unsigned* ht = L.u.cl.w.eh.key;
+  unsigned char* ht2 = L.u.cl.w.eh.second;
+  for (int q = lane; q < EH_SIZE; q += 64) ht[q] = 0xffffffffu, ht2[q] = 0xffu;
+  __syncthreads();
   int partner[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
-  for (int t = 0; t < nv; ++t) {
-    const unsigned pt = L.vp[t];
-    for (int h = 0; h < 2; ++h) {
-      const int v = lane + 64 * h;
-      if (v >= nv || t == v) continue;
-      const unsigned p = h ? p1 : p0;
-      if (has2(pt, pid1(p), pid2(p))) partner[h][0] = t;
-      if (has2(pt, pid0(p), pid2(p))) partner[h][1] = t;
-      if (has2(pt, pid0(p), pid1(p))) partner[h][2] = t;
+  int claimed[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+  for (int h = 0; h < 2; ++h) {
+    const int v = lane + 64 * h;
+    if (v >= nv) continue;
+    const unsigned p = h ? p1 : p0;
+    for (int c = 0; c < 3; ++c) {
+      const unsigned code = c == 0 ? (pid1(p) | (pid2(p) << 10)) : c == 1 ? (pid0(p) | (pid2(p) << 10))
+                                                                          : (pid0(p) | (pid1(p) << 10));
+      const unsigned mine = (code << 7) | (unsigned)v;
+      unsigned hsh = (code * 2654435761u) >> (32 - EH_BITS);
+      for (int probe = 0; probe < EH_SIZE; ++probe) {
+        const unsigned old = atomicCAS(&ht[hsh], 0xffffffffu, mine);
+        if (old == 0xffffffffu) {
+          claimed[h][c] = (int)hsh;
+          break;
+        }
+        if ((old >> 7) == code) {
+          partner[h][c] = (int)(old & 127u);
+          ht2[hsh] = (unsigned char)v;
+          break;
+        }
+        hsh = (hsh + 1) & (EH_SIZE - 1);
+      }
     }
   }
+  __syncthreads();
+  for (int h = 0; h < 2; ++h)
+    for (int c = 0; c < 3; ++c)
+      if (claimed[h][c] >= 0) {
+        const unsigned u = ht2[claimed[h][c]];
+        partner[h][c] = u == 0xffu ? -1 : (int)u;
+      }
+  __syncthreads();  // the table's LDS is reused by the triangle list
   int ntri = 0;
   for (int h = 0; h < 2; ++h) {
     const int v = lane + 64 * h;
@@ -665,8 +891,8 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       bool hit = false;
       unsigned word = 0;
       if (v < nv && u > v && pa >= 6 && pb >= 6) {
-        const double ux = L.vx[u], uy = L.vy[u], uz = L.vz[u];
-        const unsigned pu = L.vp[u];
+        const double ux = L.u.cl.vx[u], uy = L.u.cl.vy[u], uz = L.u.cl.vz[u];
+        const unsigned pu = L.u.cl.vp[u];
         const double u2 = ux * ux + uy * uy + uz * uz;
         const bool uin = (u2 - wi <= 0.0) && pid0(pu) >= 6;
         // closest point of the segment to p_i
@@ -689,7 +915,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       const unsigned long long hm = __ballot(hit);
       if (hit) {
         const int at = ntri + prefix_below(hm);
-        if (at < 2 * V_CAP) L.tri[at] = word;
+        if (at < 2 * V_CAP) L.u.cl.w.st.tri[at] = word;
       }
       ntri += __popcll(hm);
     }
@@ -734,18 +960,18 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     const unsigned long long m = __ballot(ke);
     if (ke) {
       const int kk = nk + prefix_below(m);
-      if (kk < KN_CAP) L.kslot[kk] = s;
+      if (kk < KN_CAP) L.u.cl.w.st.kslot[kk] = s;
     }
     nk += __popcll(m);
   }
   __syncthreads();
   unsigned long long extmask = 0ull;
   if (lane < nk && lane < KN_CAP) {
-    const int s = L.kslot[lane];
+    const int s = L.u.cl.w.st.kslot[lane];
     const int id = L.idx[s];
     int rank = 0;
     const int lim = min(nk, KN_CAP);
-    for (int t = 0; t < lim; ++t) rank += L.idx[L.kslot[t]] < id;
+    for (int t = 0; t < lim; ++t) rank += L.idx[L.u.cl.w.st.kslot[t]] < id;
     L.kidx[s] = rank;
     b.knbr[(size_t)i * KN_CAP + rank] = id;
     if (L.sflag[s] & SF_EXTEDGE) extmask = 1ull << rank;
@@ -788,7 +1014,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
         if (ja > jb) t = ja, ja = jb, jb = t;
         if (jb > jc) t = jb, jb = jc, jc = t;
         if (ja > jb) t = ja, ja = jb, jb = t;
-        const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_TET], 1ull);
+        const unsigned long long at2 = atomicAdd(&b.ctr[ctr_slot(C_EX_TET)], 1ull);
         if ((int64_t)at2 < b.ex_cap_q) {
           int* o = b.ex_tets + 4 * at2;
           o[0] = i, o[1] = ja, o[2] = jb, o[3] = jc;
@@ -803,7 +1029,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     bool keep = false;
     unsigned word = 0;
     if (r < ntri) {
-      const unsigned t = L.tri[r];
+      const unsigned t = L.u.cl.w.st.tri[r];
       const int sa = (int)(t & 1023u), sb = (int)((t >> 10) & 1023u);
       const unsigned nt = t >> 20;
       const int ka = L.kidx[sa], kb = L.kidx[sb];
@@ -815,7 +1041,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
         ++own_tri;
         own_ext_tri += keep;
         if (b.export_on) {
-          const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_TRI], 1ull);
+          const unsigned long long at2 = atomicAdd(&b.ctr[ctr_slot(C_EX_TRI)], 1ull);
           if ((int64_t)at2 < b.ex_cap_t) {
             int* o = b.ex_tris + 3 * at2;
             o[0] = i, o[1] = min(ja, jb), o[2] = max(ja, jb);
@@ -841,7 +1067,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       ++own_edge;
       own_ext_edge += (f & SF_EXTEDGE) != 0;
       if (b.export_on) {
-        const unsigned long long at2 = atomicAdd(&b.ctr[C_EX_EDGE], 1ull);
+        const unsigned long long at2 = atomicAdd(&b.ctr[ctr_slot(C_EX_EDGE)], 1ull);
         if ((int64_t)at2 < b.ex_cap_e) {
           b.ex_edges[2 * at2] = i;
           b.ex_edges[2 * at2 + 1] = L.idx[s];
@@ -885,9 +1111,9 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
 
 // ------------------------------------------------------------------ stats
 // Sums (maxima for the sizes) of the star kernel's per-atom records into the
-// counters: each thread folds four atoms, a block folds 4,096, and one thread
-// per block issues the atomics.
-constexpr int STATS_T = 1024, STATS_PER = 4;
+// counters: one atom per thread (a record is four int4 loads), a block folds
+// its 1,024 records and one thread per counter issues the block's atomic.
+constexpr int STATS_T = 1024;
 
 __device__ inline int stat_counter(int q) {
   switch (q) {
@@ -904,39 +1130,45 @@ __device__ inline int stat_counter(int q) {
     case S_TRI: return C_TRI;
     case S_EXTTRI: return C_EXT_TRI;
     case S_EDGE: return C_EDGE;
+    case S_KSTOP: return C_PLANES_USED;
     default: return C_EXT_EDGE;
   }
 }
 
 __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
-  __shared__ long long part[STATS_T / 64][S_COUNT];
-  long long acc[S_COUNT];
-  for (int q = 0; q < S_COUNT; ++q) acc[q] = 0;
-  const int base = blockIdx.x * STATS_T * STATS_PER + threadIdx.x;
-  for (int j = 0; j < STATS_PER; ++j) {
-    const int a = base + j * STATS_T;
-    if (a >= b.n) break;
-    const int* st = b.stat + (size_t)a * STAT_STRIDE;
-    for (int q = 0; q < S_COUNT; ++q) {
-      const long long v = st[q];
-      acc[q] = (q == S_NN || q == S_VMAX) ? max(acc[q], v) : acc[q] + v;
+  static_assert(STAT_STRIDE == 16 && S_COUNT < 16, "a record is four int4 with one spare slot");
+  constexpr int S_KMAX = 15;  // spare slot: the largest S_KSTOP of the block
+  constexpr int S_KGT = 16;   // extra slot: atoms that visited more than 64 planes
+  __shared__ int part[STATS_T / 64][17];
+  const int a = blockIdx.x * STATS_T + threadIdx.x;
+  int v[17];
+  if (a < b.n) {
+    const int4* r = (const int4*)(b.stat + (size_t)a * STAT_STRIDE);
+    for (int c = 0; c < 4; ++c) {
+      const int4 t = r[c];
+      v[4 * c] = t.x, v[4 * c + 1] = t.y, v[4 * c + 2] = t.z, v[4 * c + 3] = t.w;
     }
+  } else {
+    for (int q = 0; q < 16; ++q) v[q] = 0;
   }
-  for (int q = 0; q < S_COUNT; ++q)
+  v[S_KMAX] = v[S_KSTOP];
+  v[S_KGT] = v[S_KSTOP] > 64 ? 1 : 0;
+  auto is_max = [](int q) { return q == S_NN || q == S_VMAX || q == S_KMAX; };
+  for (int q = 0; q < 17; ++q)
     for (int off = 32; off > 0; off >>= 1) {
-      const long long o = __shfl_xor(acc[q], off, 64);
-      acc[q] = (q == S_NN || q == S_VMAX) ? max(acc[q], o) : acc[q] + o;
+      const int o = __shfl_xor(v[q], off, 64);
+      v[q] = is_max(q) ? max(v[q], o) : v[q] + o;
     }
-  const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < S_COUNT; ++q) part[wv][q] = acc[q];
+    for (int q = 0; q < 17; ++q) part[threadIdx.x >> 6][q] = v[q];
   __syncthreads();
-  if (threadIdx.x < S_COUNT) {
+  if (threadIdx.x < 17 && (threadIdx.x < S_COUNT || threadIdx.x >= S_KMAX)) {
     const int q = threadIdx.x;
-    long long v = part[0][q];
-    for (int w = 1; w < STATS_T / 64; ++w) v = (q == S_NN || q == S_VMAX) ? max(v, part[w][q]) : v + part[w][q];
-    if (q == S_NN || q == S_VMAX) atomicMax(&b.ctr[stat_counter(q)], (unsigned long long)v);
-    else if (v) atomicAdd(&b.ctr[stat_counter(q)], (unsigned long long)v);
+    long long t = part[0][q];
+    for (int w = 1; w < STATS_T / 64; ++w) t = is_max(q) ? max(t, (long long)part[w][q]) : t + part[w][q];
+    const int ctr = q == S_KMAX ? C_MAX_PLANES : q == S_KGT ? C_PLANES_GT64 : stat_counter(q);
+    if (is_max(q)) atomicMax(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
+    else if (t) atomicAdd(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
   }
 }
 
@@ -1353,7 +1585,7 @@ __global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* 
     out[3 * m] = scale * gx;
     out[3 * m + 1] = scale * gy;
     out[3 * m + 2] = scale * gz;
-    if (lost) atomicAdd(&b.ctr[C_LOST_PAIR], (unsigned long long)lost);
+    if (lost) atomicAdd(&b.ctr[ctr_slot(C_LOST_PAIR)], (unsigned long long)lost);
   }
 }
 
@@ -1391,11 +1623,14 @@ void launch_scan(const Bufs& b, hipStream_t s) {
 void launch_scatter(const Bufs& b, hipStream_t s) {
   if (b.n) k_scatter<<<blocks(b.n, 256), 256, 0, s>>>(b);
 }
+void launch_cells_one(const Bufs& b, hipStream_t s) {
+  if (b.n) k_cells_one<<<1, ONE_T, 0, s>>>(b);
+}
 void launch_star(const Bufs& b, hipStream_t s) {
   if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
 }
 void launch_stats(const Bufs& b, hipStream_t s) {
-  if (b.n) k_stats<<<blocks(b.n, STATS_T * STATS_PER), STATS_T, 0, s>>>(b);
+  if (b.n) k_stats<<<blocks(b.n, STATS_T), STATS_T, 0, s>>>(b);
 }
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
   if (!b.n) return;

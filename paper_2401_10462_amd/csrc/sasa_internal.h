@@ -38,8 +38,16 @@ enum Counter {
   C_PLANE_TESTS,   // algorithmic work counters of the star kernel
   C_NEW_VERTS,
   C_CANDIDATES,
+  C_PLANES_USED,   // planes the clipping loop visited (sum and max over atoms)
+  C_MAX_PLANES,
+  C_PLANES_GT64,   // atoms whose clipping visited more than 64 planes
   C_COUNT
 };
+// Counters sit 128 bytes apart, so that atomics on different counters never
+// queue on one L2 line; counter k is ctr[ctr_slot(k)].
+constexpr int CTR_STRIDE = 16;
+constexpr int ctr_slot(int k) { return k * CTR_STRIDE; }
+constexpr size_t CTR_BYTES = (size_t)C_COUNT * CTR_STRIDE * sizeof(unsigned long long);
 
 // Per-atom record of the star kernel (plain stores, one per atom), summed into
 // the counters by k_stats: a wavefront never issues a device-scope atomic on
@@ -59,6 +67,7 @@ enum Stat {
   S_EXTTRI,
   S_EDGE,
   S_EXTEDGE,
+  S_KSTOP,    // planes the clipping loop visited
   S_COUNT
 };
 constexpr int STAT_STRIDE = 16;  // ints per atom record
@@ -88,6 +97,7 @@ struct Bufs {
   int* scan_tmp = nullptr;   // block sums of the scan
   int* sorted = nullptr;     // atom ids grouped by cell
   double4* spos = nullptr;   // positions in cell order (coalesced neighbour loads)
+  int2* smc = nullptr;       // molecule id and cell in cell order
   // kept complex
   uint8_t* vflag = nullptr;
   int* kn_cnt = nullptr;
@@ -117,7 +127,10 @@ void launch_grid(const Bufs& b, hipStream_t s);
 void launch_count(const Bufs& b, hipStream_t s);
 void launch_scan(const Bufs& b, hipStream_t s);
 void launch_scatter(const Bufs& b, hipStream_t s);
+void launch_cells_one(const Bufs& b, hipStream_t s);
 void launch_star(const Bufs& b, hipStream_t s);
+// Largest single molecule whose cell list is built by one block.
+constexpr int64_t ONE_BLOCK_MAX_ATOMS = 65536;
 void launch_stats(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
