@@ -204,9 +204,13 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   b.nmol = std::max(nmol, 1);
   b.probe = probe;
   b.export_on = 0;
-  std::memcpy(c->off_h, offsets, (size_t)(nmol + 1) * sizeof(int64_t));
-  if (nmol == 0) c->off_h[1] = 0;
-  HIP_TRY(c, hipMemcpyAsync(c->off_d, c->off_h, (size_t)(b.nmol + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  // the single-block cell list of a one-molecule call never reads the offsets
+  const bool one_block = nmol <= 1 && n <= ONE_BLOCK_MAX_ATOMS;
+  if (!one_block) {
+    std::memcpy(c->off_h, offsets, (size_t)(nmol + 1) * sizeof(int64_t));
+    if (nmol == 0) c->off_h[1] = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->off_d, c->off_h, (size_t)(b.nmol + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  }
   b.offsets = c->off_d;
   if (mem == SASA_MEM_HOST) {
     if (n) {
@@ -223,7 +227,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
   const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
-  if (nmol <= 1 && n <= ONE_BLOCK_MAX_ATOMS) {
+  if (one_block) {
     launch_cells_one(b, s);  // also clears the counters
     if (!n) launch_zero(b.ctr, CTR_BYTES, s);
   } else {

@@ -294,7 +294,11 @@ __global__ void k_scatter(Bufs b) {
 constexpr int ONE_T = 1024;
 constexpr int ONE_LDS_CELLS = 8192;
 
+// PER > 0: every atom of the call stays in the registers of one thread
+// (n <= PER * ONE_T); PER == 0: the atoms are re-read from memory per phase.
+template <int PER>
 __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
+  constexpr int R = PER > 0 ? PER : 1;
   __shared__ int lcnt[ONE_LDS_CELLS];
   __shared__ double red[ONE_T / 64][7];
   __shared__ int scan_lds[ONE_T];
@@ -304,21 +308,35 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   // weights, box and R_max
   const double inf = __longlong_as_double(0x7ff0000000000000ll);
   double v[7] = {inf, inf, inf, -inf, -inf, -inf, 0.0};
+  double rx[R], ry[R], rz[R], rr[R];
+  int rc[R];
   int bad = 0;
-  for (int i = t; i < b.n; i += ONE_T) {
-    double x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
+  auto load = [&](int i, double& x, double& y, double& z, double& Rw) {
+    x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
     double r = b.radii[i];
     if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0)) {
       ++bad;
       x = y = z = 0.0;
       r = 1.0;
     }
-    const double R = r + b.probe;
-    b.pos[i] = make_double4(x, y, z, R);
+    Rw = r + b.probe;
+    b.pos[i] = make_double4(x, y, z, Rw);
     b.mol[i] = 0;
     v[0] = fmin(v[0], x), v[1] = fmin(v[1], y), v[2] = fmin(v[2], z);
     v[3] = fmax(v[3], x), v[4] = fmax(v[4], y), v[5] = fmax(v[5], z);
-    v[6] = fmax(v[6], R);
+    v[6] = fmax(v[6], Rw);
+  };
+  if (PER > 0) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t + k * ONE_T;
+      if (i < b.n) load(i, rx[k], ry[k], rz[k], rr[k]);
+    }
+  } else {
+    for (int i = t; i < b.n; i += ONE_T) {
+      double x, y, z, Rw;
+      load(i, x, y, z, Rw);
+    }
   }
   for (int q = 0; q < 7; ++q) v[q] = q < 3 ? wave_min_d(v[q]) : wave_max_d(v[q]);
   for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
@@ -338,22 +356,39 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     b.mol_dim[0] = make_int4(nx, ny, nz, 0);
     b.ctr[ctr_slot(C_CELLS)] = (unsigned long long)cells;
     s_cells = cells;
+    red[0][0] = geo.x, red[0][1] = geo.y, red[0][2] = geo.z, red[0][3] = geo.w;
+    red[0][4] = __longlong_as_double(((long long)nx << 32) | (unsigned)ny);
+    red[0][5] = __longlong_as_double((long long)nz);
   }
   __syncthreads();
   const int cells = s_cells;
   const bool in_lds = cells <= ONE_LDS_CELLS;
   int* cnt = in_lds ? lcnt : b.cnt;
   for (int c = t; c < cells; c += ONE_T) cnt[c] = 0;
+  const double gx = red[0][0], gy = red[0][1], gz = red[0][2], inv_s = 1.0 / red[0][3];
+  const long long d01 = __double_as_longlong(red[0][4]);
+  const int dx = (int)(d01 >> 32), dy = (int)(d01 & 0xffffffffll), dz = (int)__double_as_longlong(red[0][5]);
   __syncthreads();
-  const double4 g = b.mol_geo[0];
-  const int4 d = b.mol_dim[0];
-  const double inv_s = 1.0 / g.w;
-  for (int i = t; i < b.n; i += ONE_T) {
-    const double4 p = b.pos[i];
-    const int c = (cell_index(p.z, g.z, inv_s, d.z) * d.y + cell_index(p.y, g.y, inv_s, d.y)) * d.x +
-                  cell_index(p.x, g.x, inv_s, d.x);
-    b.cellid[i] = c;
-    atomicAdd(&cnt[c], 1);
+  auto cell_of = [&](double x, double y, double z) {
+    return (cell_index(z, gz, inv_s, dz) * dy + cell_index(y, gy, inv_s, dy)) * dx + cell_index(x, gx, inv_s, dx);
+  };
+  if (PER > 0) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t + k * ONE_T;
+      if (i < b.n) {
+        rc[k] = cell_of(rx[k], ry[k], rz[k]);
+        b.cellid[i] = rc[k];
+        atomicAdd(&cnt[rc[k]], 1);
+      }
+    }
+  } else {
+    for (int i = t; i < b.n; i += ONE_T) {
+      const double4 p = b.pos[i];
+      const int c = cell_of(p.x, p.y, p.z);
+      b.cellid[i] = c;
+      atomicAdd(&cnt[c], 1);
+    }
   }
   __syncthreads();
   // exclusive scan: thread t owns the contiguous cells [t*per, (t+1)*per)
@@ -378,12 +413,25 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   }
   if (t == ONE_T - 1) b.start[cells] = scan_lds[ONE_T - 1];
   __syncthreads();
-  for (int i = t; i < b.n; i += ONE_T) {
-    const int c = b.cellid[i];
-    const int slot = atomicAdd(&cnt[c], 1);
-    b.sorted[slot] = i;
-    b.spos[slot] = b.pos[i];
-    b.smc[slot] = make_int2(0, c);
+  if (PER > 0) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t + k * ONE_T;
+      if (i < b.n) {
+        const int slot = atomicAdd(&cnt[rc[k]], 1);
+        b.sorted[slot] = i;
+        b.spos[slot] = make_double4(rx[k], ry[k], rz[k], rr[k]);
+        b.smc[slot] = make_int2(0, rc[k]);
+      }
+    }
+  } else {
+    for (int i = t; i < b.n; i += ONE_T) {
+      const int c = b.cellid[i];
+      const int slot = atomicAdd(&cnt[c], 1);
+      b.sorted[slot] = i;
+      b.spos[slot] = b.pos[i];
+      b.smc[slot] = make_int2(0, c);
+    }
   }
 }
 
@@ -1113,7 +1161,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
 // Sums (maxima for the sizes) of the star kernel's per-atom records into the
 // counters: one atom per thread (a record is four int4 loads), a block folds
 // its 1,024 records and one thread per counter issues the block's atomic.
-constexpr int STATS_T = 1024;
+constexpr int STATS_T = 256;
 
 __device__ inline int stat_counter(int q) {
   switch (q) {
@@ -1624,7 +1672,9 @@ void launch_scatter(const Bufs& b, hipStream_t s) {
   if (b.n) k_scatter<<<blocks(b.n, 256), 256, 0, s>>>(b);
 }
 void launch_cells_one(const Bufs& b, hipStream_t s) {
-  if (b.n) k_cells_one<<<1, ONE_T, 0, s>>>(b);
+  if (!b.n) return;
+  if (b.n <= 8 * ONE_T) k_cells_one<8><<<1, ONE_T, 0, s>>>(b);
+  else k_cells_one<0><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
   if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
