@@ -94,6 +94,7 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&b.smc, cap));
     HIP_TRY(c, grow(&b.vflag, cap));
     HIP_TRY(c, grow(&b.stat, cap * STAT_STRIDE));
+    HIP_TRY(c, grow(&b.wide, cap));
     HIP_TRY(c, grow(&b.kn_cnt, cap));
     HIP_TRY(c, grow(&b.knbr, cap * KN_CAP));
     HIP_TRY(c, grow(&b.kn_ext, cap));
@@ -326,7 +327,7 @@ void sasa_destroy(void* ctx) {
   (void)hipDeviceSynchronize();
   Bufs& b = c->b;
   void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos, b.smc,
-                 b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
+                 b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.wide, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
@@ -482,7 +483,7 @@ int sasa_footprint(int64_t n, int64_t* bytes) {
   // statistics record, flags, the
   // kept complex, gradient blocks, area and the staging of inputs and outputs;
   // per molecule (at most one per atom): offsets, box, grid geometry
-  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int2) + sizeof(int) * (3 + STAT_STRIDE) + 1 + sizeof(int) * (KN_CAP + 3) +
+  const int64_t per_atom = sizeof(double4) * 2 + sizeof(int2) + sizeof(int) * (4 + STAT_STRIDE) + 1 + sizeof(int) * (KN_CAP + 3) +
                            sizeof(unsigned long long) + sizeof(unsigned) * (KT_CAP + KTR_CAP) +
                            sizeof(double) * (ROW * 3 + 1 + 3 + 3 + 1 + 1);
   const int64_t per_mol = sizeof(int64_t) * 2 + sizeof(unsigned long long) * 6 + sizeof(double4) + sizeof(int4);

@@ -463,47 +463,76 @@ __device__ inline bool has2(unsigned p, unsigned a, unsigned b) {
   return (x == a || y == a || z == a) && (x == b || y == b || z == b);
 }
 
-constexpr int EH_BITS = 8, EH_SIZE = 1 << EH_BITS;  // > 2 x the 1.5 V_CAP edges of a cell
-static_assert(V_CAP <= 128, "vertex slots are 7 bits in the edge table");
+constexpr int EH_BITS = 8, EH_SIZE = 1 << EH_BITS;  // > 2 x the 1.5 VC edges of a cell
 
+// LDS of one star: NBC overlapping neighbours, VC cell vertices, the planes of
+// the NPL nearest neighbours (farther ones are recomputed when needed).
+template <int NBC, int VC, int NPL>
 struct StarLds {
-  int idx[NB_CAP];  // neighbour global ids, slot order = clipping order (nearest plane first)
-  double nx[NB_CAP], ny[NB_CAP], nz[NB_CAP], nb[NB_CAP];  // plane n = 2a, offset b
-  unsigned sflag[NB_CAP];  // per-slot flags (facet present, K-triangles, K-edge ...)
-  int kidx[NB_CAP];        // slot -> K-neighbour index or -1
+  static_assert(VC <= 128 && NBC % 4 == 0 && NPL <= NBC, "vertex slots are 7 bits in the edge table");
+  static constexpr int kPlanes = NPL;
+  int idx[NBC];  // neighbour global ids, slot order = clipping order (nearest plane first)
+  double nx[NPL], ny[NPL], nz[NPL], nb[NPL];  // plane n = 2a, offset b
+  union {
+    unsigned char b[NBC];  // per-slot flags (facet present, K-triangles, K-edge ...)
+    unsigned w[NBC / 4];   // the same four to a word (atomic OR)
+  } sf;
+  signed char kidx[NBC];  // slot -> K-neighbour index or -1
   union {
     struct {  // candidates in arrival order (neighbour search and ranking only)
-      double key[NB_CAP];  // signed distance of the radical plane from p_i
-      int id[NB_CAP];
+      double key[NBC];  // signed distance of the radical plane from p_i
+      int id[NBC];
     } app;
     struct {  // the cell across a cut, then the star's lists
-      double vx[V_CAP], vy[V_CAP], vz[V_CAP];
-      unsigned vp[V_CAP];
+      double vx[VC], vy[VC], vz[VC];
+      unsigned vp[VC];
       union {
-        unsigned pairs[3 * V_CAP];  // edges of the removed vertices of one cut
-        struct {                    // cell edges by plane pair: code << 7 | first end, second end
+        unsigned pairs[3 * VC];  // edges of the removed vertices of one cut
+        struct {                 // cell edges by plane pair: code << 7 | first end, second end
           unsigned key[EH_SIZE];
           unsigned char second[EH_SIZE];
         } eh;
         struct {
-          unsigned tri[2 * V_CAP];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
-          int kslot[KN_CAP];        // K-edge slots in slot order
+          unsigned tri[2 * VC];  // triangle candidates: slot a | slot b << 10 | n_tet << 20
+          int kslot[KN_CAP];     // K-edge slots in slot order
         } st;
       } w;
     } cl;
   } u;
 };
 
+template <class LT>
+__device__ inline void sf_or(LT& L, int s, unsigned f) {
+  atomicOr(&L.sf.w[s >> 2], f << ((s & 3) * 8));
+}
+
 enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, SF_EXTEDGE = 16 };
 
-__device__ inline Pl plane_of(const StarLds& L, unsigned pid, double half) {
+// Radical plane of neighbour j (position pj, weight R_j^2) seen from p_i:
+// n = 2 (p_j - p_i), b = |p_j - p_i|^2 - w_j + w_i, in a fixed order of
+// correctly rounded operations so that every evaluation gives the same bits.
+__device__ inline Pl radical_plane(const double4& pi, double wi, const double4& pj) {
+  const double ax = __dsub_rn(pj.x, pi.x), ay = __dsub_rn(pj.y, pi.y), az = __dsub_rn(pj.z, pi.z);
+  const double a2 = __dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(az, az));
+  return {2.0 * ax, 2.0 * ay, 2.0 * az, __dadd_rn(__dsub_rn(a2, __dmul_rn(pj.w, pj.w)), wi)};
+}
+
+// Plane of neighbour slot q: from LDS, or recomputed for slots past the
+// stored ones.
+template <class LT>
+__device__ inline Pl slot_plane(const LT& L, const Bufs& b, const double4& pi, double wi, int q) {
+  if (q < LT::kPlanes) return {L.nx[q], L.ny[q], L.nz[q], L.nb[q]};
+  return radical_plane(pi, wi, b.pos[L.idx[q]]);
+}
+
+template <class LT>
+__device__ inline Pl plane_of(const LT& L, const Bufs& b, const double4& pi, double wi, unsigned pid, double half) {
   if (pid < 6) {
     const double s = (pid & 1) ? -1.0 : 1.0;
     const unsigned ax = pid >> 1;
     return {ax == 0 ? s : 0.0, ax == 1 ? s : 0.0, ax == 2 ? s : 0.0, half};
   }
-  const unsigned q = pid - 6;
-  return {L.nx[q], L.ny[q], L.nz[q], L.nb[q]};
+  return slot_plane(L, b, pi, wi, (int)pid - 6);
 }
 
 __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, double& y, double& z) {
@@ -533,15 +562,18 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void k_star(Bufs b) {
-  __shared__ StarLds L;
-  if ((int)blockIdx.x >= b.n) return;
+// The star of the atom at cell-ordered position sidx.  Returns false when the
+// atom needs more than NBC neighbours or VC cell vertices and `last` is not
+// set (it is then left to a pass with larger capacities; nothing is written);
+// with `last` such an atom is reported as a capacity overflow.
+template <int NBC, int VC, int NPL>
+__device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, bool last) {
   // atoms in cell order (neighbouring blocks share neighbours in cache); the
   // atom's id, position, molecule and cell come from the cell-ordered copies
-  const int i = b.sorted[blockIdx.x];
+  const int i = b.sorted[sidx];
   const int lane = threadIdx.x;
-  const double4 pi = b.spos[blockIdx.x];
-  const int2 mc = b.smc[blockIdx.x];
+  const double4 pi = b.spos[sidx];
+  const int2 mc = b.smc[sidx];
   const int mi = mc.x;
   const double Ri = pi.w, wi = Ri * Ri;
   const int4 gd = b.mol_dim[mi];
@@ -629,7 +661,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       const unsigned long long m = __ballot(take);
       if (take) {
         const int at = nn + prefix_below(m);
-        if (at < NB_CAP) {
+        if (at < NBC) {
           // distance of the radical plane from p_i: (d^2 + w_i - w_j) / (2 d); a
           // neighbour at the same centre has no plane (it empties the cell or
           // cuts nothing) and goes first
@@ -640,9 +672,9 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       nn += __popcll(m);
     }
   }
-  if (nn > NB_CAP) {
+  if (nn > NBC) {
     overflow = true;
-    nn = NB_CAP;
+    nn = NBC;
   }
   __syncthreads();
   // ---- slots in clipping order: nearest plane first, ties by atom id.  Lane
@@ -687,15 +719,12 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     const int id = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
     if (id < 0) continue;
     const int r = hb == 0 ? rk0 : (hb == 1 ? rk1 : rk2);
-    const double4 pj = hb == 0 ? cp0 : (hb == 1 ? cp1 : cp2);
-    const double ax = pj.x - pi.x, ay = pj.y - pi.y, az = pj.z - pi.z;
-    const double a2 = ax * ax + ay * ay + az * az;
     L.idx[r] = id;
-    L.nx[r] = 2.0 * ax;
-    L.ny[r] = 2.0 * ay;
-    L.nz[r] = 2.0 * az;
-    L.nb[r] = a2 - pj.w * pj.w + wi;
-    L.sflag[r] = 0u;
+    if (r < NPL) {
+      const Pl q = radical_plane(pi, wi, hb == 0 ? cp0 : (hb == 1 ? cp1 : cp2));
+      L.nx[r] = q.x, L.ny[r] = q.y, L.nz[r] = q.z, L.nb[r] = q.b;
+    }
+    L.sf.b[r] = 0;
     L.kidx[r] = -1;
   }
   // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
@@ -718,7 +747,8 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   int kstop = nn;  // planes visited
   __syncthreads();
   for (int k = 0; k < nn && !overflow; ++k) {
-    const double qx = L.nx[k], qy = L.ny[k], qz = L.nz[k], qb = L.nb[k];
+    const Pl qk = slot_plane(L, b, pi, wi, k);
+    const double qx = qk.x, qy = qk.y, qz = qk.z, qb = qk.b;
     // security radius: the plane's signed distance from p_i is b / |n| (its
     // ranking key); once it reaches the largest |v| of the cell, no plane from
     // here on can cut it.  Tested without a root or division as b >= 0 and
@@ -733,7 +763,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       if (!rho_exact) {
         double r2 = 0.0;
         if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
-        if (lane + 64 < nv) r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
+        if ((VC > 64 && lane + 64 < nv)) r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
         rho2 = wave_max(r2);
         rho_exact = true;
       }
@@ -743,7 +773,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       }
     }
     const bool r0 = lane < nv && qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
-    const bool r1 = lane + 64 < nv && qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
+    const bool r1 = (VC > 64 && lane + 64 < nv) && qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
     plane_tests += nv;
     const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
     const int nr0 = __popcll(m0);
@@ -772,12 +802,12 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     const int nkeep = nv - nrem;
     // kept vertices move to their compacted slots (old LDS contents are dead:
     // every lane holds its vertices in registers)
-    const unsigned long long k0 = __ballot(lane < nv && !r0), k1 = __ballot(lane + 64 < nv && !r1);
+    const unsigned long long k0 = __ballot(lane < nv && !r0), k1 = __ballot((VC > 64 && lane + 64 < nv) && !r1);
     if (lane < nv && !r0) {
       const int d = prefix_below(k0);
       L.u.cl.vx[d] = x0, L.u.cl.vy[d] = y0, L.u.cl.vz[d] = z0, L.u.cl.vp[d] = p0;
     }
-    if (lane + 64 < nv && !r1) {
+    if ((VC > 64 && lane + 64 < nv) && !r1) {
       const int d = __popcll(k0) + prefix_below(k1);
       L.u.cl.vx[d] = x1, L.u.cl.vy[d] = y1, L.u.cl.vz[d] = z1, L.u.cl.vp[d] = p1;
     }
@@ -805,11 +835,11 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       const unsigned long long cm = __ballot(cross);
       if (cross) {
         const int slot = nkeep + ncross + prefix_below(cm);
-        if (slot < V_CAP) {
+        if (slot < VC) {
           const unsigned tri3 = pack3(pr & 1023u, pr >> 10, pid);
           double x, y, z;
-          solve3(plane_of(L, pid0(tri3), half), plane_of(L, pid1(tri3), half), plane_of(L, pid2(tri3), half), x,
-                 y, z);
+          solve3(plane_of(L, b, pi, wi, pid0(tri3), half), plane_of(L, b, pi, wi, pid1(tri3), half),
+                 plane_of(L, b, pi, wi, pid2(tri3), half), x, y, z);
           L.u.cl.vx[slot] = x;
           L.u.cl.vy[slot] = y;
           L.u.cl.vz[slot] = z;
@@ -820,7 +850,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     }
     new_verts += ncross;
     nv = nkeep + ncross;
-    if (nv > V_CAP) {
+    if (nv > VC) {
       overflow = true;
       break;
     }
@@ -829,7 +859,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     x0 = y0 = z0 = x1 = y1 = z1 = 0.0;
     p0 = p1 = 0u;
     if (lane < nv) x0 = L.u.cl.vx[lane], y0 = L.u.cl.vy[lane], z0 = L.u.cl.vz[lane], p0 = L.u.cl.vp[lane];
-    if (lane + 64 < nv)
+    if ((VC > 64 && lane + 64 < nv))
       x1 = L.u.cl.vx[lane + 64], y1 = L.u.cl.vy[lane + 64], z1 = L.u.cl.vz[lane + 64], p1 = L.u.cl.vp[lane + 64];
     rho_exact = false;
     __syncthreads();  // the next cut overwrites pairs / vertices only after everyone has read
@@ -844,6 +874,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     st[S_KSTOP] = kstop;
   }
   if (overflow) {
+    if (!last) return false;
     if (lane == 0) {
       for (int q = S_TIES; q < S_COUNT; ++q) st[q] = 0;
       st[S_BAD] = 1;
@@ -852,11 +883,11 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       b.kt_cnt[i] = 0;
       b.ktr_cnt[i] = 0;
     }
-    return;
+    return true;
   }
   if (empty) nv = 0;
   if (lane >= nv) x0 = y0 = z0 = 0.0, p0 = 0u;
-  if (lane + 64 >= nv) x1 = y1 = z1 = 0.0, p1 = 0u;
+  if ((VC <= 64 || lane + 64 >= nv)) x1 = y1 = z1 = 0.0, p1 = 0u;
 
   // ---- 3. the star: K-tetrahedra (cell vertices in B_i), K-triangles (cell
   // edges meeting B_i), K-edges (facets meeting B_i)
@@ -867,7 +898,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     in0 = m <= 0.0 && pid0(p0) >= 6;
     ties += fabs(m) < kNearTie;
   }
-  if (lane + 64 < nv) {
+  if ((VC > 64 && lane + 64 < nv)) {
     const double m = x1 * x1 + y1 * y1 + z1 * z1 - wi;
     in1 = m <= 0.0 && pid0(p1) >= 6;
     ties += fabs(m) < kNearTie;
@@ -879,7 +910,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       const unsigned p = h ? p1 : p0;
       const unsigned ids[3] = {pid0(p), pid1(p), pid2(p)};
       for (int c = 0; c < 3; ++c)
-        if (ids[c] >= 6) atomicOr(&L.sflag[ids[c] - 6], (unsigned)SF_FACET);
+        if (ids[c] >= 6) sf_or(L, (int)ids[c] - 6, (unsigned)SF_FACET);
     }
   }
   __syncthreads();
@@ -956,26 +987,27 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
           const unsigned nt = (unsigned)vin + (unsigned)uin;
           word = (pa - 6) | ((pb - 6) << 10) | (nt << 20);
           const unsigned f = SF_KTRI | (nt <= 1 ? SF_EXTTRI : 0u);
-          atomicOr(&L.sflag[pa - 6], f);
-          atomicOr(&L.sflag[pb - 6], f);
+          sf_or(L, (int)pa - 6, f);
+          sf_or(L, (int)pb - 6, f);
         }
       }
       const unsigned long long hm = __ballot(hit);
       if (hit) {
         const int at = ntri + prefix_below(hm);
-        if (at < 2 * V_CAP) L.u.cl.w.st.tri[at] = word;
+        if (at < 2 * VC) L.u.cl.w.st.tri[at] = word;
       }
       ntri += __popcll(hm);
     }
   }
-  ntri = min(ntri, 2 * V_CAP);
+  ntri = min(ntri, 2 * VC);
   __syncthreads();
   // facets without a K-triangle: K-edge iff the disk centre lies in the cell
   for (int s = lane; s < nn; s += 64) {
-    unsigned f = L.sflag[s];
+    unsigned f = L.sf.b[s];
     bool kedge = (f & SF_KTRI) != 0;
     if (!kedge && (f & SF_FACET)) {
-      const double nx = L.nx[s], ny = L.ny[s], nz = L.nz[s], nb = L.nb[s];
+      const Pl qs = slot_plane(L, b, pi, wi, s);
+      const double nx = qs.x, ny = qs.y, nz = qs.z, nb = qs.b;
       const double sc = nb / (nx * nx + ny * ny + nz * nz);
       const double yx = sc * nx, yy = sc * ny, yz = sc * nz;
       const double se = yx * yx + yy * yy + yz * yz - wi;
@@ -983,7 +1015,8 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       bool inside = se <= 0.0;
       for (int t = 0; t < nn && inside; ++t) {
         if (t == s) continue;
-        const double g = L.nb[t] - (L.nx[t] * yx + L.ny[t] * yy + L.nz[t] * yz);
+        const Pl qt = slot_plane(L, b, pi, wi, t);
+        const double g = qt.b - (qt.x * yx + qt.y * yy + qt.z * yz);
         ties += fabs(g) < kNearTie;
         inside = g >= 0.0;
       }
@@ -993,18 +1026,18 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
       f |= SF_KEDGE;
       if (!(f & SF_KTRI) || (f & SF_EXTTRI)) f |= SF_EXTEDGE;
     }
-    L.sflag[s] = f;
+    L.sf.b[s] = (unsigned char)f;
   }
   // origin in the cell (used when there is no K-edge)
   bool origin_in = true;
-  for (int s = lane; s < nn; s += 64) origin_in &= L.nb[s] >= 0.0;
+  for (int s = lane; s < nn; s += 64) origin_in &= slot_plane(L, b, pi, wi, s).b >= 0.0;
   origin_in = __ballot(!origin_in) == 0ull;
   __syncthreads();
   // K-edges in slot order, then K-neighbour indices by ascending atom id
   int nk = 0;
   for (int base = 0; base < nn; base += 64) {
     const int s = base + lane;
-    const bool ke = s < nn && (L.sflag[s] & SF_KEDGE);
+    const bool ke = s < nn && (L.sf.b[s] & SF_KEDGE);
     const unsigned long long m = __ballot(ke);
     if (ke) {
       const int kk = nk + prefix_below(m);
@@ -1020,9 +1053,9 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     int rank = 0;
     const int lim = min(nk, KN_CAP);
     for (int t = 0; t < lim; ++t) rank += L.idx[L.u.cl.w.st.kslot[t]] < id;
-    L.kidx[s] = rank;
+    L.kidx[s] = (signed char)rank;
     b.knbr[(size_t)i * KN_CAP + rank] = id;
-    if (L.sflag[s] & SF_EXTEDGE) extmask = 1ull << rank;
+    if (L.sf.b[s] & SF_EXTEDGE) extmask = 1ull << rank;
   }
   {
     unsigned lo = (unsigned)extmask, hi = (unsigned)(extmask >> 32);
@@ -1110,7 +1143,7 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
   // owned edges
   int own_edge = 0, own_ext_edge = 0;
   for (int s = lane; s < nn; s += 64) {
-    const unsigned f = L.sflag[s];
+    const unsigned f = L.sf.b[s];
     if ((f & SF_KEDGE) && i < L.idx[s]) {
       ++own_edge;
       own_ext_edge += (f & SF_EXTEDGE) != 0;
@@ -1154,6 +1187,34 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
     st[S_EXTTRI] = own_ext_tri;
     st[S_EDGE] = own_edge;
     st[S_EXTEDGE] = own_ext_edge;
+  }
+  return true;
+}
+
+// Fast pass over all atoms with LDS sized for 20 wavefronts per CU (planes of
+// the 128 nearest neighbours in LDS, cells of up to 64 vertices); the rare
+// atoms whose cell grows past 64 vertices are queued for the wide pass.
+constexpr int V_FAST = 64, NPL_FAST = 128;
+
+__global__ __launch_bounds__(64) void k_star(Bufs b) {
+  __shared__ StarLds<NB_CAP, V_FAST, NPL_FAST> L;
+  if ((int)blockIdx.x >= b.n) return;
+  if (!star_atom(b, L, blockIdx.x, false) && threadIdx.x == 0) {
+    const unsigned long long q = atomicAdd(&b.ctr[ctr_slot(C_WIDE)], 1ull);
+    b.wide[q] = (int)blockIdx.x;
+  }
+}
+
+// Wide pass: the queued atoms, with the full capacities, a fixed grid looping
+// over the queue (it returns at once when the queue is empty).
+constexpr int WIDE_BLOCKS = 64;
+
+__global__ __launch_bounds__(64) void k_star_wide(Bufs b) {
+  __shared__ StarLds<NB_CAP, V_CAP, NB_CAP> L;
+  const int cnt = (int)b.ctr[ctr_slot(C_WIDE)];
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+    __syncthreads();
+    star_atom(b, L, b.wide[q], true);
   }
 }
 
@@ -1677,7 +1738,9 @@ void launch_cells_one(const Bufs& b, hipStream_t s) {
   else k_cells_one<0><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
-  if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
+  if (!b.n) return;
+  k_star<<<b.n, 64, 0, s>>>(b);
+  k_star_wide<<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
 }
 void launch_stats(const Bufs& b, hipStream_t s) {
   if (b.n) k_stats<<<blocks(b.n, STATS_T), STATS_T, 0, s>>>(b);

@@ -8,7 +8,7 @@ namespace sasa {
 
 // Per-atom capacities of the star kernel (local data in LDS).
 constexpr int NB_CAP = 160;  // overlapping neighbours of one atom
-constexpr int V_CAP = 96;    // vertices of the clipped power cell (at most 2 per lane)
+constexpr int V_CAP = 128;   // vertices of the clipped power cell (two slots per lane)
 // Per-atom capacities of the kept complex (HBM).
 constexpr int KN_CAP = 64;    // K-edges at an atom (bit mask of exterior edges is one u64)
 constexpr int KT_CAP = 160;   // K-tetrahedra at an atom
@@ -41,6 +41,7 @@ enum Counter {
   C_PLANES_USED,   // planes the clipping loop visited (sum and max over atoms)
   C_MAX_PLANES,
   C_PLANES_GT64,   // atoms whose clipping visited more than 64 planes
+  C_WIDE,          // atoms queued for the star kernel's wide pass
   C_COUNT
 };
 // Counters sit 128 bytes apart, so that atomics on different counters never
@@ -108,6 +109,7 @@ struct Bufs {
   int* ktr_cnt = nullptr;
   unsigned* ktri = nullptr;            // n * KTR_CAP, 2 x 8-bit slots + n_tet << 16
   int* stat = nullptr;       // n * STAT_STRIDE per-atom records of the star kernel
+  int* wide = nullptr;       // cell-ordered positions queued for the star's wide pass (n)
   // results
   double* area = nullptr;
   double* rows = nullptr;    // n * ROW * 3
