@@ -154,3 +154,38 @@ def test_edge_cases(ctxs):
         fresh.backward(np.zeros(3))
     assert e.value.code == _lib.SASA_E_STATE
     fresh.close()
+
+
+def _shell(n_shell, R_center=4.0, r_shell=1.5, dist=5.0, seed=0):
+    """A large atom whose power cell has about 2 n_shell vertices: n_shell atoms
+    on a Fibonacci shell around it (small jitter keeps general position)."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(n_shell) + 0.5
+    phi = np.arccos(1 - 2 * k / n_shell)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    d = np.column_stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)])
+    xyz = np.vstack([[0.0, 0.0, 0.0], dist * d + rng.normal(scale=0.05, size=d.shape)])
+    rad = np.concatenate([[R_center], np.full(n_shell, r_shell)])
+    return xyz, rad
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_cell_takes_the_wide_pass(ctxs, prec):
+    # 48 shell atoms: the central cell has more than 64 vertices, beyond the
+    # fast pass's capacity, and is computed by the wide pass
+    xyz, rad = _shell(48)
+    ref = oracle.run(xyz, rad, 1.4)
+    ctx = ctxs[prec]
+    area, dadx = ctx.compute(xyz, rad, 1.4)
+    d = ctx.diagnostics()
+    assert d["max_cell_vertices"] > 64 and d["overflow"] == 0
+    _check_complex(ctx, ref)
+    _check_values(area, dadx, ref, TOL[prec])
+
+
+def test_cell_beyond_every_capacity_is_an_error(ctxs):
+    from paper_2401_10462_amd import _lib
+    xyz, rad = _shell(90, R_center=5.0, dist=6.0)
+    with pytest.raises(_lib.SasaError) as e:
+        ctxs["fp64"].compute(xyz, rad, 1.4)
+    assert e.value.code == _lib.SASA_E_CAPACITY
