@@ -209,6 +209,16 @@ def main():
     value = n * args.steps / elapsed
     diag = ctx.diagnostics()
 
+    # ---- the same molecule from host buffers (PCIe transfers inside each call)
+    for _ in range(2):
+        ctx.compute(xyz, rad, 1.4)
+    th = time.perf_counter()
+    kh = max(5, args.steps // 3)
+    for _ in range(kh):
+        ctx.compute(xyz, rad, 1.4)
+    eh = time.perf_counter() - th
+    host = {"atoms_per_s": n * kh / eh, "ms_per_call": 1e3 * eh / kh, "calls": kh}
+
     # ---- dominant kernel roofline (VALU-bound FP64 clipping)
     dom = max(stage, key=stage.get)
     star_s = stage["star"] / 1e3 / args.steps
@@ -268,6 +278,7 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "batched": batched,
+        "host_pointers": host,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,
