@@ -150,7 +150,8 @@ typedef struct {
   double ms_total;            /* wall time of the last synchronous call */
   /* stage times of the last call (SASA_FLAG_TIMING; HIP events on the call's stream) */
   double ms_cells;            /* weights, per-molecule cell grid, scan, scatter */
-  double ms_star;             /* per-atom power-cell clipping, the star in K, its counters */
+  double ms_star;             /* per-atom power-cell clipping and the star in K (fast pass) */
+  double ms_star_wide;        /* the star's pass for cells too large for the fast pass, and its counters */
   double ms_terms;            /* Eq. 1 area terms (and gradient blocks) */
   double ms_gather;           /* segmented gradient sums */
   /* algorithmic work of the last call's star kernel */

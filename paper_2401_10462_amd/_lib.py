@@ -48,7 +48,8 @@ class sasa_diag(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_atoms", "n_mol", "max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
         "capacity_retries", "input_errors", "overflow")] + [
-        (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_terms", "ms_gather")] + [
+        (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_star_wide", "ms_terms",
+                                             "ms_gather")] + [
         (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "planes_used",
                                             "max_planes_used", "atoms_over_64_planes")]
 

@@ -46,7 +46,7 @@ struct Ctx {
   double probe = 0;
   bool pending = false;  // an async call whose counters were not read yet
   hipStream_t last_stream = nullptr;  // stream of the last call (pending counters are read there)
-  hipEvent_t ev[5] = {};  // stage boundaries (SASA_FLAG_TIMING)
+  hipEvent_t ev[6] = {};  // stage boundaries (SASA_FLAG_TIMING)
   bool timed = false;     // events of the last call were recorded
   sasa_diag diag{};
   std::string err;
@@ -159,12 +159,13 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.max_planes_used = (int64_t)h[ctr_slot(C_MAX_PLANES)];
   c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
   if (c->timed) {
-    float ms[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    float ms[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 5; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
     c->diag.ms_cells = ms[0];
     c->diag.ms_star = ms[1];
-    c->diag.ms_terms = ms[2];
-    c->diag.ms_gather = ms[3];
+    c->diag.ms_star_wide = ms[2];
+    c->diag.ms_terms = ms[3];
+    c->diag.ms_gather = ms[4];
     c->timed = false;
   }
   if (h[ctr_slot(C_BAD_INPUT)]) {
@@ -243,12 +244,14 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   }
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   launch_star(b, s);
-  launch_stats(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
-  launch_terms(b, c->precision, dA_dx != nullptr, s);
+  launch_star_wide(b, s);
+  launch_stats(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
-  if (dA_dx) launch_gather(b, nullptr, out, scale, s);
+  launch_terms(b, c->precision, dA_dx != nullptr, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[4], s));
+  if (dA_dx) launch_gather(b, nullptr, out, scale, s);
+  if (timing) HIP_TRY(c, hipEventRecord(c->ev[5], s));
   c->timed = timing;
   HIP_TRY(c, hipGetLastError());
   if (mem == SASA_MEM_HOST && n) {
@@ -454,6 +457,7 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   launch_zero(b.ctr, CTR_BYTES, s);
   HIP_TRY(c, hipMemcpyAsync(b.ctr + ctr_slot(C_RMAX_BITS), &rmax_bits, sizeof(rmax_bits), hipMemcpyHostToDevice, s));
   launch_star(b, s);
+  launch_star_wide(b, s);
   launch_stats(b, s);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(s));

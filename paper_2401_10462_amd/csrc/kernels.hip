@@ -1738,9 +1738,10 @@ void launch_cells_one(const Bufs& b, hipStream_t s) {
   else k_cells_one<0><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
-  if (!b.n) return;
-  k_star<<<b.n, 64, 0, s>>>(b);
-  k_star_wide<<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
+  if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
+}
+void launch_star_wide(const Bufs& b, hipStream_t s) {
+  if (b.n) k_star_wide<<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
 }
 void launch_stats(const Bufs& b, hipStream_t s) {
   if (b.n) k_stats<<<blocks(b.n, STATS_T), STATS_T, 0, s>>>(b);

@@ -130,7 +130,8 @@ void launch_count(const Bufs& b, hipStream_t s);
 void launch_scan(const Bufs& b, hipStream_t s);
 void launch_scatter(const Bufs& b, hipStream_t s);
 void launch_cells_one(const Bufs& b, hipStream_t s);
-void launch_star(const Bufs& b, hipStream_t s);
+void launch_star(const Bufs& b, hipStream_t s);        // fast pass over all atoms
+void launch_star_wide(const Bufs& b, hipStream_t s);   // atoms the fast pass queued
 // Largest single molecule whose cell list is built by one block.
 constexpr int64_t ONE_BLOCK_MAX_ATOMS = 65536;
 void launch_stats(const Bufs& b, hipStream_t s);
