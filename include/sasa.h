@@ -58,7 +58,17 @@ typedef enum { SASA_MEM_HOST = 0, SASA_MEM_DEVICE = 1 } sasa_mem;
 enum {
   SASA_FLAG_ASYNC = 1u, /* device-pointer calls return without synchronising the stream; capacity
                            overflow and input errors are then reported by the next sasa_diagnostics */
-  SASA_FLAG_TIMING = 2u /* record HIP events around every stage of a call (stage times in sasa_diag) */
+  SASA_FLAG_TIMING = 2u, /* record HIP events around every stage of a call (stage times in sasa_diag) */
+  SASA_FLAG_FRAMES = 4u  /* consecutive calls are frames of one trajectory (same atoms, small moves).
+                            The context keeps each atom's power cell (facet neighbours and vertices
+                            as plane triples) from the previous call of the same atom count.  A kept
+                            cell whose vertices, solved afresh, lie inside every neighbour plane
+                            they are not on is the new cell and is not clipped again; any other
+                            cell is clipped with the kept facets first.  The cells, the complex and
+                            every result are the same as without the flag (up to the summation
+                            order of the terms; near-degenerate decisions aside, which sasa_diag
+                            counts); a call with another atom count starts without.  Costs 516
+                            bytes of device memory per atom. */
 };
 
 typedef struct {
@@ -161,6 +171,7 @@ typedef struct {
   int64_t planes_used;        /* radical planes visited by the clipping loops (sum over atoms) */
   int64_t max_planes_used;    /* ... largest for one atom */
   int64_t atoms_over_64_planes; /* atoms whose clipping visited more than 64 planes */
+  int64_t reused_cells;       /* SASA_FLAG_FRAMES: atoms whose previous-frame cell was verified and kept */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

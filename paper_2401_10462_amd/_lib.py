@@ -24,6 +24,7 @@ SASA_MEM_HOST = 0
 SASA_MEM_DEVICE = 1
 SASA_FLAG_ASYNC = 1
 SASA_FLAG_TIMING = 2
+SASA_FLAG_FRAMES = 4
 
 # every entry point of include/sasa.h
 EXPORTS = (
@@ -51,7 +52,7 @@ class sasa_diag(ctypes.Structure):
         (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_star_wide", "ms_terms",
                                              "ms_gather")] + [
         (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "planes_used",
-                                            "max_planes_used", "atoms_over_64_planes")]
+                                            "max_planes_used", "atoms_over_64_planes", "reused_cells")]
 
 
 _lib = None

@@ -48,6 +48,7 @@ struct Ctx {
   hipStream_t last_stream = nullptr;  // stream of the last call (pending counters are read there)
   hipEvent_t ev[6] = {};  // stage boundaries (SASA_FLAG_TIMING)
   bool timed = false;     // events of the last call were recorded
+  int64_t fac_atoms = -1;  // atom count of the call that wrote the facet hints (-1: none)
   sasa_diag diag{};
   std::string err;
 };
@@ -108,6 +109,12 @@ int ensure(Ctx* c, int64_t n, int nmol) {
     HIP_TRY(c, grow(&c->rad_d, cap));
     HIP_TRY(c, grow(&c->out_d, cap * 3));
     HIP_TRY(c, grow(&c->u_d, cap));
+    if (c->flags & SASA_FLAG_FRAMES) {
+      HIP_TRY(c, grow(&b.fac, cap * FAC_CAP));
+      HIP_TRY(c, grow(&b.vtx, cap * FAC_CAP));
+      HIP_TRY(c, grow(&b.hint_n, cap));
+    }
+    c->fac_atoms = -1;
     c->cap_n = cap;
   }
   const int64_t cells = cell_capacity(n);
@@ -158,6 +165,7 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.planes_used = (int64_t)h[ctr_slot(C_PLANES_USED)];
   c->diag.max_planes_used = (int64_t)h[ctr_slot(C_MAX_PLANES)];
   c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
+  c->diag.reused_cells = (int64_t)h[ctr_slot(C_REUSED)];
   if (c->timed) {
     float ms[5] = {0, 0, 0, 0, 0};
     for (int k = 0; k < 5; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
@@ -229,6 +237,10 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
   const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+  if (b.fac && c->fac_atoms != n) {  // hints of another system: start without
+    if (n) launch_zero(b.hint_n, (size_t)n * sizeof(int), s);
+    c->fac_atoms = n;
+  }
   if (one_block) {
     launch_cells_one(b, s);  // also clears the counters
     if (!n) launch_zero(b.ctr, CTR_BYTES, s);
@@ -331,7 +343,7 @@ void sasa_destroy(void* ctx) {
   Bufs& b = c->b;
   void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos, b.smc,
                  b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.wide, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
-                 b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, c->xyz_d,
+                 b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, b.fac, b.vtx, b.hint_n, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -448,6 +460,9 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   b.n = (int)c->n;
   b.nmol = std::max(c->nmol, 1);
   b.export_on = 1;
+  b.fac = nullptr;  // the export leaves the trajectory's hints alone
+  b.vtx = nullptr;
+  b.hint_n = nullptr;
   b.ex_cap_e = c->ex_cap_e;
   b.ex_cap_t = c->ex_cap_t;
   b.ex_cap_q = c->ex_cap_q;

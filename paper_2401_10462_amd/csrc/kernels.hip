@@ -554,6 +554,11 @@ __device__ inline double rdl(double v, int l) {
 }
 __device__ inline int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Lowers the ranking key of a neighbour that was a facet in the previous frame
+// (plane distances are a few Angstrom; the shifted keys keep their order to
+// well below 1e-9 A, and exact ties fall back to the atom id).
+constexpr double kFirstShift = 1.0e6;
+
 // clipping order of candidate (k, i) before (kk, ii): nearest plane first, ties by atom id
 __device__ inline int before(double k, int i, double kk, int ii) { return (k < kk) || (k == kk && i < ii); }
 
@@ -566,7 +571,7 @@ __device__ inline double wave_max(double v) {
 // atom needs more than NBC neighbours or VC cell vertices and `last` is not
 // set (it is then left to a pass with larger capacities; nothing is written);
 // with `last` such an atom is reported as a capacity overflow.
-template <int NBC, int VC, int NPL>
+template <bool HINTS, int NBC, int VC, int NPL>
 __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, bool last) {
   // atoms in cell order (neighbouring blocks share neighbours in cache); the
   // atom's id, position, molecule and cell come from the cell-ordered copies
@@ -624,6 +629,20 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   const int total = __shfl(pre, 24, 64);
   const int row_s = pre - row_n;     // first flat index of the row
   const int row_d = row_a - row_s;   // sorted index = flat index + row_d of its row
+  // this atom's cell in the previous frame of a trajectory (loaded now, used
+  // once the candidates are ranked): facet neighbour ids and vertex triples.
+  // fslot maps a facet's list position to its slot in this frame (0xff: the
+  // neighbour is no longer a candidate).
+  int npf = 0, nvh = 0, pf = -1;
+  unsigned vh = 0u;
+  unsigned char* fslot = L.u.cl.w.eh.second;  // free until the star is read off
+  if constexpr (HINTS) {
+    const int hn = __builtin_amdgcn_readfirstlane(b.hint_n[i]);
+    npf = min(hn & 255, FAC_CAP);
+    nvh = min((hn >> 8) & 255, FAC_CAP);
+    if (lane < npf) pf = b.fac[(size_t)i * FAC_CAP + lane], fslot[lane] = 0xff;
+    if (lane < nvh) vh = b.vtx[(size_t)i * FAC_CAP + lane];
+  }
   int nn = 0;
   bool overflow = false;
   long long plane_tests = 0, new_verts = 0;
@@ -691,6 +710,28 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   if (ci0 >= 0) cp0 = b.pos[ci0];
   if (ci1 >= 0) cp1 = b.pos[ci1];
   if (ci2 >= 0) cp2 = b.pos[ci2];
+  // a neighbour whose plane bounded the previous frame's cell is clipped before
+  // all others: its key is lowered by far more than any plane distance (the
+  // order among such neighbours stays nearest plane first, ties by atom id).
+  // The cell is the same in any clipping order; this one makes few cuts and
+  // few vertices that a later cut removes.
+  int nfirst = 0;
+  int ft0 = -1, ft1 = -1, ft2 = -1;  // facet-list position of each candidate
+  if (HINTS && npf > 0) {
+    for (int t = 0; t < npf; ++t) {
+      const int id = rdl(pf, t);
+      if (id == ci0) ft0 = t;
+      if (id == ci1) ft1 = t;
+      if (id == ci2) ft2 = t;
+    }
+    if (ci0 < 0) ft0 = -1;
+    if (ci1 < 0) ft1 = -1;
+    if (ci2 < 0) ft2 = -1;
+    if (ft0 >= 0) ck0 -= kFirstShift;
+    if (ft1 >= 0) ck1 -= kFirstShift;
+    if (ft2 >= 0) ck2 -= kFirstShift;
+    nfirst = __popcll(__ballot(ft0 >= 0)) + __popcll(__ballot(ft1 >= 0)) + __popcll(__ballot(ft2 >= 0));
+  }
   int rk0 = 0, rk1 = 0, rk2 = 0;
   for (int hb = 0; hb < nsets; ++hb) {
     const double kk = hb == 0 ? ck0 : (hb == 1 ? ck1 : ck2);
@@ -726,6 +767,8 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     }
     L.sf.b[r] = 0;
     L.kidx[r] = -1;
+    const int ft = hb == 0 ? ft0 : (hb == 1 ? ft1 : ft2);
+    if (ft >= 0) fslot[ft] = (unsigned char)r;
   }
   // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
   // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
@@ -746,7 +789,70 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   int vmax = 8;
   int kstop = nn;  // planes visited
   __syncthreads();
-  for (int k = 0; k < nn && !overflow; ++k) {
+  // ---- 2a. a trajectory's previous cell.  Its facet neighbours are the
+  // first nfirst slots; its vertices (plane triples, now in this frame's
+  // slots) are solved afresh.  If each lies inside every one of those planes
+  // (and the cube's) that it is not on, the set is closed under the edges of
+  // their intersection Q (the segment between two feasible vertices on one
+  // line lies in Q), so it is Q's whole vertex set: Q is exactly what clipping
+  // the cube by the first nfirst planes would give, and the clipping goes on
+  // from there with the remaining planes.  Otherwise it starts from the cube.
+  bool reused = false;
+  int k0 = 0;
+  if (HINTS && nvh > 0 && nvh <= 64 && nvh <= VC && nfirst > 0 && !overflow) {
+    bool ok = true;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    unsigned vp = 0u;
+    if (lane < nvh) {
+      unsigned q[3];
+      for (int c = 0; c < 3; ++c) {
+        const unsigned hc = (vh >> (7 * c)) & 127u;
+        q[c] = hc;
+        if (hc >= 6) {
+          const unsigned sl = hc - 6 < (unsigned)npf ? fslot[hc - 6] : 0xffu;
+          if (sl == 0xffu) ok = false;
+          q[c] = 6u + sl;
+        }
+      }
+      vp = pack3(q[0], q[1], q[2]);
+      if (ok && pid0(vp) != pid1(vp) && pid1(vp) != pid2(vp)) {
+        solve3(plane_of(L, b, pi, wi, pid0(vp), half), plane_of(L, b, pi, wi, pid1(vp), half),
+               plane_of(L, b, pi, wi, pid2(vp), half), vx, vy, vz);
+        ok = isfinite(vx) && isfinite(vy) && isfinite(vz);
+        for (unsigned c = 0; c < 6 && ok; ++c) {  // the cube's planes
+          if (pid0(vp) == c || pid1(vp) == c || pid2(vp) == c) continue;
+          const double sg = (c & 1) ? -1.0 : 1.0;
+          const double t = (c >> 1) == 0 ? vx : ((c >> 1) == 1 ? vy : vz);
+          ok = half - sg * t >= 0.0;
+        }
+      } else {
+        ok = false;
+      }
+    }
+    // the previous facets' planes (slots 0 .. nfirst - 1, all in LDS), one
+    // vertex per lane, the same side test as the clipping
+    for (int k = 0; k < nfirst && __ballot(!ok) == 0ull; ++k) {
+      const Pl qk = slot_plane(L, b, pi, wi, k);
+      const unsigned pk = 6u + (unsigned)k;
+      if (lane < nvh && pid0(vp) != pk && pid1(vp) != pk && pid2(vp) != pk)
+        ok = qk.b - (qk.x * vx + qk.y * vy + qk.z * vz) >= 0.0;
+    }
+    plane_tests += (long long)nfirst * nvh;
+    if (__ballot(!ok) == 0ull) {
+      reused = true;
+      k0 = nfirst;
+      nv = nvh;
+      vmax = nvh;
+      new_verts += nvh;
+      x0 = vx, y0 = vy, z0 = vz, p0 = vp;
+      rho2 = wave_max(lane < nvh ? vx * vx + vy * vy + vz * vz : 0.0);
+      rho_exact = true;
+      // the star is read off LDS if no plane cuts Q further
+      if (lane < nvh) L.u.cl.vx[lane] = vx, L.u.cl.vy[lane] = vy, L.u.cl.vz[lane] = vz, L.u.cl.vp[lane] = vp;
+      __syncthreads();
+    }
+  }
+  for (int k = k0; k < nn && !overflow; ++k) {
     const Pl qk = slot_plane(L, b, pi, wi, k);
     const double qx = qk.x, qy = qk.y, qz = qk.z, qb = qk.b;
     // security radius: the plane's signed distance from p_i is b / |n| (its
@@ -758,7 +864,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     // (a cut never moves a vertex away from p_i) and made exact only when the
     // bound would end the loop.
     const double qn2 = qx * qx + qy * qy + qz * qz;
-    const bool far = qn2 > 0.0 && qb >= 0.0;
+    const bool far = k >= nfirst && qn2 > 0.0 && qb >= 0.0;  // the rest is in plane order
     if (far && qb * qb >= (rho2 * (1.0 + 1e-9) + 1e-12) * qn2) {
       if (!rho_exact) {
         double r2 = 0.0;
@@ -878,6 +984,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     if (lane == 0) {
       for (int q = S_TIES; q < S_COUNT; ++q) st[q] = 0;
       st[S_BAD] = 1;
+      if (HINTS) b.hint_n[i] = 0;
       b.vflag[i] = 0;
       b.kn_cnt[i] = 0;
       b.kt_cnt[i] = 0;
@@ -914,6 +1021,41 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     }
   }
   __syncthreads();
+  if constexpr (HINTS) {  // the cell for the next frame: facets in slot order, vertices
+    int nf = 0;
+    unsigned long long fm[(NBC + 63) / 64];
+#pragma unroll
+    for (int w = 0; w < (NBC + 63) / 64; ++w) {
+      const int s = 64 * w + lane;
+      const bool f = s < nn && (L.sf.b[s] & SF_FACET);
+      fm[w] = __ballot(f);
+      if (f) {
+        const int at = nf + prefix_below(fm[w]);
+        if (at < FAC_CAP) b.fac[(size_t)i * FAC_CAP + at] = L.idx[s];
+      }
+      nf += __popcll(fm[w]);
+    }
+    const bool keepv = nf <= FAC_CAP && nv <= FAC_CAP;
+    if (keepv && lane < nv) {
+      unsigned code = 0u;
+      for (int c = 0; c < 3; ++c) {
+        const unsigned pc = c == 0 ? pid0(p0) : (c == 1 ? pid1(p0) : pid2(p0));
+        unsigned hc = pc;
+        if (pc >= 6) {  // its position in the facet list
+          const int sl = (int)pc - 6;
+          int f = 0;
+#pragma unroll
+          for (int w = 0; w < (NBC + 63) / 64; ++w)
+            if (64 * w + 64 <= sl) f += __popcll(fm[w]);
+            else if (64 * w <= sl) f += __popcll(fm[w] & ((1ull << (sl - 64 * w)) - 1ull));
+          hc = 6u + (unsigned)f;
+        }
+        code |= hc << (7 * c);
+      }
+      b.vtx[(size_t)i * FAC_CAP + lane] = code;
+    }
+    if (lane == 0) b.hint_n[i] = min(nf, FAC_CAP) | ((keepv ? nv : 0) << 8);
+  }
   // cell edges: the two end vertices of an edge (a plane pair) meet in a small
   // LDS hash table keyed by the pair: the first to arrive claims an entry
   // (atomic compare-and-swap), the second finds it and leaves its slot there.
@@ -1083,9 +1225,12 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     const int at = h ? __popcll(tm0) + prefix_below(tm1) : prefix_below(tm0);
     const int sa = (int)pid0(p) - 6, sb = (int)pid1(p) - 6, sc = (int)pid2(p) - 6;
     const int ka = L.kidx[sa], kb = L.kidx[sb], kc = L.kidx[sc];
-    if (ka < 0 || kb < 0 || kc < 0 || ka >= KN_CAP || kb >= KN_CAP || kc >= KN_CAP) bad_lane = true;
-    else if (at < KT_CAP)
-      b.ktet[(size_t)i * KT_CAP + at] = (unsigned)ka | ((unsigned)kb << 8) | ((unsigned)kc << 16);
+    if (ka < 0 || kb < 0 || kc < 0 || ka >= KN_CAP || kb >= KN_CAP || kc >= KN_CAP) {
+      bad_lane = true;
+    } else if (at < KT_CAP) {  // K-neighbour indices ascending: the terms do not depend on the clipping order
+      const unsigned k3 = pack3(ka, kb, kc);
+      b.ktet[(size_t)i * KT_CAP + at] = pid0(k3) | (pid1(k3) << 8) | (pid2(k3) << 16);
+    }
     int ja = L.idx[sa], jb = L.idx[sb], jc = L.idx[sc];
     if (i < ja && i < jb && i < jc) {
       ++own_tet;
@@ -1116,7 +1261,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       const int ka = L.kidx[sa], kb = L.kidx[sb];
       keep = nt <= 1;
       if (ka < 0 || kb < 0 || ka >= KN_CAP || kb >= KN_CAP) bad_lane = true, keep = false;
-      word = (unsigned)ka | ((unsigned)kb << 8) | (nt << 16);
+      word = (unsigned)min(ka, kb) | ((unsigned)max(ka, kb) << 8) | (nt << 16);
       const int ja = L.idx[sa], jb = L.idx[sb];
       if (i < ja && i < jb) {
         ++own_tri;
@@ -1179,7 +1324,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       b.ktr_cnt[i] = next_tri;
     }
     st[S_TIES] = ties;
-    st[S_BAD] = bad ? 1 : 0;
+    st[S_BAD] = (bad ? 1 : 0) | (reused ? 2 : 0);
     st[S_VERT] = inK ? 1 : 0;
     st[S_EXTV] = ext ? 1 : 0;
     st[S_TET] = own_tet;
@@ -1194,12 +1339,14 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
 // Fast pass over all atoms with LDS sized for 20 wavefronts per CU (planes of
 // the 128 nearest neighbours in LDS, cells of up to 64 vertices); the rare
 // atoms whose cell grows past 64 vertices are queued for the wide pass.
+// HINTS: a trajectory's calls (the previous frame's cells are kept).
 constexpr int V_FAST = 64, NPL_FAST = 128;
 
+template <bool HINTS>
 __global__ __launch_bounds__(64) void k_star(Bufs b) {
   __shared__ StarLds<NB_CAP, V_FAST, NPL_FAST> L;
   if ((int)blockIdx.x >= b.n) return;
-  if (!star_atom(b, L, blockIdx.x, false) && threadIdx.x == 0) {
+  if (!star_atom<HINTS>(b, L, blockIdx.x, false) && threadIdx.x == 0) {
     const unsigned long long q = atomicAdd(&b.ctr[ctr_slot(C_WIDE)], 1ull);
     b.wide[q] = (int)blockIdx.x;
   }
@@ -1209,12 +1356,13 @@ __global__ __launch_bounds__(64) void k_star(Bufs b) {
 // over the queue (it returns at once when the queue is empty).
 constexpr int WIDE_BLOCKS = 64;
 
+template <bool HINTS>
 __global__ __launch_bounds__(64) void k_star_wide(Bufs b) {
   __shared__ StarLds<NB_CAP, V_CAP, NB_CAP> L;
   const int cnt = (int)b.ctr[ctr_slot(C_WIDE)];
   for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
     __syncthreads();
-    star_atom(b, L, b.wide[q], true);
+    star_atom<HINTS>(b, L, b.wide[q], true);
   }
 }
 
@@ -1248,9 +1396,11 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
   static_assert(STAT_STRIDE == 16 && S_COUNT < 16, "a record is four int4 with one spare slot");
   constexpr int S_KMAX = 15;  // spare slot: the largest S_KSTOP of the block
   constexpr int S_KGT = 16;   // extra slot: atoms that visited more than 64 planes
-  __shared__ int part[STATS_T / 64][17];
+  constexpr int S_REUSE = 17;  // extra slot: atoms that kept their previous-frame cell
+  constexpr int NV = 18;
+  __shared__ int part[STATS_T / 64][NV];
   const int a = blockIdx.x * STATS_T + threadIdx.x;
-  int v[17];
+  int v[NV];
   if (a < b.n) {
     const int4* r = (const int4*)(b.stat + (size_t)a * STAT_STRIDE);
     for (int c = 0; c < 4; ++c) {
@@ -1262,20 +1412,22 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
   }
   v[S_KMAX] = v[S_KSTOP];
   v[S_KGT] = v[S_KSTOP] > 64 ? 1 : 0;
+  v[S_REUSE] = v[S_BAD] >> 1;
+  v[S_BAD] &= 1;
   auto is_max = [](int q) { return q == S_NN || q == S_VMAX || q == S_KMAX; };
-  for (int q = 0; q < 17; ++q)
+  for (int q = 0; q < NV; ++q)
     for (int off = 32; off > 0; off >>= 1) {
       const int o = __shfl_xor(v[q], off, 64);
       v[q] = is_max(q) ? max(v[q], o) : v[q] + o;
     }
   if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < 17; ++q) part[threadIdx.x >> 6][q] = v[q];
+    for (int q = 0; q < NV; ++q) part[threadIdx.x >> 6][q] = v[q];
   __syncthreads();
-  if (threadIdx.x < 17 && (threadIdx.x < S_COUNT || threadIdx.x >= S_KMAX)) {
+  if (threadIdx.x < NV && (threadIdx.x < S_COUNT || threadIdx.x >= S_KMAX)) {
     const int q = threadIdx.x;
     long long t = part[0][q];
     for (int w = 1; w < STATS_T / 64; ++w) t = is_max(q) ? max(t, (long long)part[w][q]) : t + part[w][q];
-    const int ctr = q == S_KMAX ? C_MAX_PLANES : q == S_KGT ? C_PLANES_GT64 : stat_counter(q);
+    const int ctr = q == S_KMAX ? C_MAX_PLANES : q == S_KGT ? C_PLANES_GT64 : q == S_REUSE ? C_REUSED : stat_counter(q);
     if (is_max(q)) atomicMax(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
     else if (t) atomicAdd(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
   }
@@ -1738,10 +1890,14 @@ void launch_cells_one(const Bufs& b, hipStream_t s) {
   else k_cells_one<0><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
-  if (b.n) k_star<<<b.n, 64, 0, s>>>(b);
+  if (!b.n) return;
+  if (b.fac) k_star<true><<<b.n, 64, 0, s>>>(b);
+  else k_star<false><<<b.n, 64, 0, s>>>(b);
 }
 void launch_star_wide(const Bufs& b, hipStream_t s) {
-  if (b.n) k_star_wide<<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
+  if (!b.n) return;
+  if (b.fac) k_star_wide<true><<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
+  else k_star_wide<false><<<min(b.n, WIDE_BLOCKS), 64, 0, s>>>(b);
 }
 void launch_stats(const Bufs& b, hipStream_t s) {
   if (b.n) k_stats<<<blocks(b.n, STATS_T), STATS_T, 0, s>>>(b);

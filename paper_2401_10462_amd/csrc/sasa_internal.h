@@ -10,6 +10,12 @@ namespace sasa {
 constexpr int NB_CAP = 160;  // overlapping neighbours of one atom
 constexpr int V_CAP = 128;   // vertices of the clipped power cell (two slots per lane)
 // Per-atom capacities of the kept complex (HBM).
+// A cell kept per atom between the frames of a trajectory: up to 64 facets and
+// 64 vertices (a simple polytope with 64 vertices has 34 facets); a larger
+// cell keeps no vertices and at most 64 facets (the facets only order the
+// clipping and the vertices are verified before use, so no hint changes a
+// result).
+constexpr int FAC_CAP = 64;
 constexpr int KN_CAP = 64;    // K-edges at an atom (bit mask of exterior edges is one u64)
 constexpr int KT_CAP = 160;   // K-tetrahedra at an atom
 constexpr int KTR_CAP = 160;  // exterior K-triangles at an atom
@@ -42,6 +48,7 @@ enum Counter {
   C_MAX_PLANES,
   C_PLANES_GT64,   // atoms whose clipping visited more than 64 planes
   C_WIDE,          // atoms queued for the star kernel's wide pass
+  C_REUSED,        // atoms whose previous-frame cell was verified and kept
   C_COUNT
 };
 // Counters sit 128 bytes apart, so that atomics on different counters never
@@ -60,7 +67,7 @@ enum Stat {
   S_TESTS,    // (vertex, plane) side tests
   S_NEWV,     // vertices created
   S_TIES,     // near-degenerate decisions
-  S_BAD,      // capacity exceeded or broken star
+  S_BAD,      // capacity exceeded or broken star (bit 0); previous-frame cell kept (bit 1)
   S_VERT,     // atom is a vertex of K
   S_EXTV,     // ... an exterior one
   S_TET,      // owned simplices (lowest index)
@@ -110,6 +117,13 @@ struct Bufs {
   unsigned* ktri = nullptr;            // n * KTR_CAP, 2 x 8-bit slots + n_tet << 16
   int* stat = nullptr;       // n * STAT_STRIDE per-atom records of the star kernel
   int* wide = nullptr;       // cell-ordered positions queued for the star's wide pass (n)
+  // each atom's cell in the previous call of a trajectory (null when the
+  // context does not keep them): its facet neighbours (ids, FAC_CAP per atom),
+  // its vertices as triples of facet-list positions (FAC_CAP per atom), and
+  // the two counts (facets | vertices << 8)
+  int* fac = nullptr;
+  unsigned* vtx = nullptr;
+  int* hint_n = nullptr;
   // results
   double* area = nullptr;
   double* rows = nullptr;    // n * ROW * 3

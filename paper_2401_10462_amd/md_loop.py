@@ -15,16 +15,18 @@ from .context import SasaContext
 
 
 def md_loop(xyz, radii, frames, sigma=0.02, gamma=0.005, seed=33, probe=1.4, precision="mixed",
-            keep_frames=(), ctx=None):
+            keep_frames=(), ctx=None, frame_hints=True):
     """Run ``frames`` frames; return per-frame latencies (ms) and the kept frames.
 
     keep_frames: frame indices whose coordinates, areas and forces are copied to
     the host (for checks against the oracle).
+    frame_hints: clip each atom's cell first by the previous frame's facet
+    neighbours (the library's trajectory mode; results are unchanged).
     """
     dev = torch.device("cuda", torch.cuda.current_device())
     X = torch.as_tensor(xyz, dtype=torch.float64, device=dev).clone()
     R = torch.as_tensor(radii, dtype=torch.float64, device=dev).contiguous()
-    ctx = ctx or SasaContext(device=dev.index, precision=precision, max_atoms=X.shape[0])
+    ctx = ctx or SasaContext(device=dev.index, precision=precision, max_atoms=X.shape[0], frames=frame_hints)
     gen = torch.Generator(device=dev)
     kept = {}
     lat = []
