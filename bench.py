@@ -44,8 +44,9 @@ def parse():
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--batch", type=int, default=32, help="molecules in the batched form (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU leg (0: skip)")
-    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md"],
-                   help="globule: the headline line; serving: Poisson stream sweep; md: MD-like frames")
+    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md", "gbsa"],
+                   help="globule: the headline line; serving: Poisson stream sweep; md: MD-like frames; "
+                        "gbsa: Langevin harness with SASA forces through autograd")
     p.add_argument("--serve-requests", type=int, default=600, help="requests per arrival rate (serving)")
     p.add_argument("--rates", default="100,500,2000,5000", help="arrival rates, req/s (serving)")
     p.add_argument("--md-atoms", type=int, default=20000)
@@ -110,6 +111,33 @@ def md(args, precision):
         out[key] = {"frames_per_s": 1e3 / lat.mean(), "atoms_per_s": len(rad) * 1e3 / lat.mean(),
                     "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
     return out
+
+
+def gbsa(args, precision):
+    """Langevin steps (1 fs, 300 K) of the headline molecule, nonpolar forces through SASAFunction + bonds."""
+    import torch
+    from synth.globule import globule
+    from paper_2401_10462_amd.gbsa_md import (NonpolarBondedModel, bonds_by_distance, langevin_baoab,
+                                              masses_from_radii, thermal_velocities)
+    xyz, rad = globule(args.heavy, args.seed, hydrogens=True)
+    dev = torch.device("cuda:0")
+    bonds, r0 = bonds_by_distance(xyz)
+    m = masses_from_radii(rad).to(dev)
+    g = torch.Generator().manual_seed(3)
+    v0 = thermal_velocities(m.cpu(), 300.0, g).to(dev)
+    model = NonpolarBondedModel(torch.tensor(rad, device=dev), bonds.to(dev), r0.to(dev), gamma=0.007,
+                                precision=precision)
+    x = torch.tensor(xyz, device=dev)
+    x, v0, _ = langevin_baoab(model, x, v0, m, 1.0, max(args.warmup, 3), 300.0, 5.0, g)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 10)
+    t0 = time.perf_counter()
+    _, _, tr = langevin_baoab(model, x, v0, m, 1.0, steps, 300.0, 5.0, g)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"atoms": len(rad), "steps": steps, "dt_fs": 1.0, "gamma": 0.007, "steps_per_s": steps / el,
+            "ms_per_step": 1e3 * el / steps, "ns_per_day": steps / el * 86400 * 1e-6,
+            "nonpolar_kcal_mol": tr[-1][2]}
 
 
 def measured_traffic():
@@ -178,6 +206,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps({"workload": "serving", "precision": args.precision, **serving(args, args.precision)}))
+        return
+    if args.workload == "gbsa":
+        print(json.dumps({"workload": "gbsa", "precision": args.precision, **gbsa(args, args.precision)}))
         return
     if args.workload == "md":
         print(json.dumps({"workload": "md", "precision": args.precision, **md(args, args.precision)}))
