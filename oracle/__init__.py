@@ -27,7 +27,7 @@ def lib():
     global _lib
     if _lib is None:
         path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(q) for q in _build.SOURCES):
             _build.build(force=True)
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
@@ -51,6 +51,9 @@ def lib():
             f.argtypes = [dp, dp, dp, dp]
         L.oracle_cap_area.restype = ctypes.c_double
         L.oracle_cap_area.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double]
+        L.oracle_facet_area.restype = ctypes.c_double
+        L.oracle_facet_area.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_volume.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp, dp]
         L.oracle_triple_term.restype = ctypes.c_double
         L.oracle_triple_term.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double, dp, ctypes.c_double]
         _lib = L
@@ -150,3 +153,29 @@ def triple_term(pi, Ri, pj, Rj, pk, Rk):
     """Area of sphere i inside both balls j and k (Eq. 6, both halves)."""
     a, b, c = _v3(pi), _v3(pj), _v3(pk)
     return lib().oracle_triple_term(_dp(a), float(Ri), _dp(b), float(Rj), _dp(c), float(Rk))
+
+
+def volume(xyz, radii, probe=1.4, area=None):
+    """Per-atom volumes of the cells B_i ∩ L_i (A^3) and the gradient of their sum (n x 3).
+
+    3 V_i = R_i A_i + sum_j h_ij F_ij (divergence theorem over the cell) with
+    A_i from Eq. 1 (``run``, unless given) and each flat face F_ij computed
+    from its definition; dV/dp_i = -sum_j F_ij (p_j - p_i) / |p_j - p_i|.
+    """
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    if area is None:
+        area = run(xyz, radii, probe).area
+    area = np.ascontiguousarray(area, dtype=np.float64)
+    n = len(radii)
+    vol = np.zeros(n)
+    grad = np.zeros((n, 3))
+    lib().oracle_volume(n, _dp(xyz), _dp(radii), probe, _dp(area), _dp(vol), _dp(grad))
+    return vol, grad
+
+
+def facet_area(xyz, radii, probe, i, j):
+    """Area of the flat face of B_i ∩ L_i on the radical plane of atoms i and j."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    return lib().oracle_facet_area(len(radii), _dp(xyz), _dp(radii), probe, int(i), int(j))

@@ -8,18 +8,19 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sasa_oracle.cc")
+SOURCES = [SRC, os.path.join(HERE, "volume_oracle.cc")]
 LIB = os.path.join(HERE, "libsasa_oracle.so")
 
 
 def build(force=True, march_native=False):
     """Compile the oracle with g++ (plain -O2; -march=native only if asked)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(os.path.getmtime(p) for p in SOURCES):
         return LIB
     flags = ["-O2", "-std=c++17", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off"]
     if march_native:
         flags.append("-march=native")
     tmp = LIB + ".tmp"
-    cmd = ["g++", *flags, SRC, "-o", tmp]
+    cmd = ["g++", *flags, *SOURCES, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
