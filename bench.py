@@ -265,6 +265,21 @@ def main():
     eh = time.perf_counter() - th
     host = {"atoms_per_s": n * kh / eh, "ms_per_call": 1e3 * eh / kh, "calls": kh}
 
+    # ---- cell volumes and the molecular-volume gradient of the same molecule
+    # (FP64: the areas are recomputed in FP64, then the faces)
+    for _ in range(2):
+        ctx.compute(X, R, 1.4)
+        ctx.volume()
+    kv = max(5, args.steps // 3)
+    tv = 0.0
+    for _ in range(kv):
+        ctx.compute(X, R, 1.4)
+        s = time.perf_counter()
+        vol, _ = ctx.volume()
+        tv += time.perf_counter() - s
+    volume = {"ms_per_call": 1e3 * tv / kv, "atoms_per_s": n * kv / tv, "calls": kv,
+              "volume_A3": float(vol.sum().item())}
+
     # ---- dominant kernel roofline (VALU-bound FP64 clipping): k_star alone
     dom = max(stage, key=stage.get)
     star_s = stage["star"] / 1e3 / args.steps
@@ -326,6 +341,7 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "batched": batched,
         "host_pointers": host,
+        "volume": volume,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,

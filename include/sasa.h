@@ -130,6 +130,22 @@ int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* r
 int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream);
 
 /*
+ * Volumes of the last compute (the Discussion's extension of the method to
+ * volumes and their derivatives on the same Laguerre intersection cells):
+ *   volume[i] = volume of B_i ∩ L_i (A^3; sum = volume of the union of the balls)
+ *   dV_dx[m]  = d(sum_i volume[i]) / dp_m (n*3 doubles, A^2)
+ * From the kept complex and that compute's coordinates: 3 V_i = R_i A_i +
+ * sum_j h_ij F_ij over the flat faces of the cell, each face area by
+ * inclusion-exclusion over the K-triangles and K-tetrahedra at its edge, and
+ * dV/dp_i = -sum_j F_ij (p_j - p_i) / |p_j - p_i|.  Always FP64 (the areas are
+ * recomputed in FP64 whatever the context's precision).  The caller owns both
+ * output buffers (host or device per mem); the gradient is that of the
+ * molecular volume, not a per-atom Jacobian.  SASA_E_STATE without a kept
+ * compute, SASA_E_INVAL for NULL outputs.
+ */
+int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream);
+
+/*
  * Sizes of the kept complex: counts[0..7] = vertices in K, edges, triangles,
  * tetrahedra, exterior vertices, exterior edges, exterior triangles, atoms.
  */

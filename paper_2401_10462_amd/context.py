@@ -21,6 +21,7 @@ class SasaContext:
         flags = ((_lib.SASA_FLAG_ASYNC if async_calls else 0) | (_lib.SASA_FLAG_TIMING if timing else 0)
                  | (_lib.SASA_FLAG_FRAMES if frames else 0))
         self._h = _lib.sasa_create(device, prec, max_atoms, flags)
+        self._n, self._like_last = 0, np.zeros(0)
 
     def close(self):
         if self._h is not None:
@@ -39,6 +40,7 @@ class SasaContext:
         n = xyz.shape[0]
         area, dadx = self._outputs(xyz, n, grad)
         _lib.sasa_compute(self._h, n, _c(xyz), _c(radii), probe, area, dadx)
+        self._n, self._like_last = n, _like(xyz, (0,))
         return area, dadx
 
     def compute_batch(self, offsets, xyz, radii, probe=1.4, grad=True):
@@ -46,6 +48,7 @@ class SasaContext:
         n = xyz.shape[0]
         area, dadx = self._outputs(xyz, n, grad)
         _lib.sasa_compute_batch(self._h, offsets, _c(xyz), _c(radii), probe, area, dadx)
+        self._n, self._like_last = n, _like(xyz, (0,))
         return area, dadx
 
     def forces(self, xyz, radii, gamma, probe=1.4):
@@ -53,6 +56,7 @@ class SasaContext:
         n = xyz.shape[0]
         area, f = self._outputs(xyz, n, True)
         _lib.sasa_compute_forces(self._h, n, _c(xyz), _c(radii), probe, gamma, area, f)
+        self._n, self._like_last = n, _like(xyz, (0,))
         return area, f
 
     def backward(self, dL_dA):
@@ -61,6 +65,14 @@ class SasaContext:
         out = _like(dL_dA, (n, 3))
         _lib.sasa_backward(self._h, _c(dL_dA), out)
         return out
+
+    def volume(self):
+        """Per-atom cell volumes (n,) of the last compute and d(sum V)/dx (n, 3), FP64, like its inputs."""
+        n = self._n
+        like = self._like_last
+        vol, grad = _like(like, (n,)), _like(like, (n, 3))
+        _lib.sasa_volume(self._h, vol, grad)
+        return vol, grad
 
     def counts(self):
         c = _lib.sasa_complex_counts(self._h)

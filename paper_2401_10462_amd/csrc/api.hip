@@ -412,6 +412,37 @@ int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, vo
   return SASA_OK;
 }
 
+int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (c->n > 0 && (!volume || !dV_dx)) return fail(c, SASA_E_INVAL, "volume / dV_dx must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  b.area = c->area_d;  // the areas again, in FP64, for R_i A_i
+  double* vol = volume;
+  double* grad = dV_dx;
+  if (mem == SASA_MEM_HOST) {
+    vol = c->u_d;
+    grad = c->out_d;
+  }
+  launch_terms(b, SASA_FP64, 0, s);
+  launch_volume(b, vol, grad, s);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == SASA_MEM_HOST && c->n) {
+    HIP_TRY(c, hipMemcpyAsync(volume, vol, (size_t)c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(dV_dx, grad, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  } else if (!(c->flags & SASA_FLAG_ASYNC)) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return SASA_OK;
+}
+
 int sasa_complex_counts(void* ctx, int64_t counts[8]) {
   auto* c = (Ctx*)ctx;
   if (!c || !counts) return fail(c, SASA_E_INVAL, "NULL argument");

@@ -151,6 +151,8 @@ constexpr int64_t ONE_BLOCK_MAX_ATOMS = 65536;
 void launch_stats(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
+// Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64).
+void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int scan_blocks(unsigned hb);
 // Grid cells a batch of n atoms may use: a molecule of m > 0 atoms gets at most

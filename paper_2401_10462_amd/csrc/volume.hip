@@ -1,0 +1,225 @@
+// volume.hip -- per-atom volumes of the cells B_i ∩ L_i and the gradient of
+// the molecular volume, from the dual complex K kept by the last compute.
+//
+// The same cells whose spherical boundary gives the area of Eq. 1 give the
+// volume (the Discussion names volumes and their derivatives as the next
+// measure on them).  The divergence theorem over B_i ∩ L_i with the field
+// x - p_i gives
+//   3 V_i = R_i A_i + sum_j h_j F_j,
+// j over the K-edges at i (the facets that meet B_i), h_j the signed distance
+// of the radical plane of i and j from p_i and F_j the area of the flat face.
+// On the plane the face is the disk D_j (centre c_j, radius rho_j) cut by the
+// cell's edges, and the divergence theorem in the plane with x - c_j gives
+//   2 F_j = rho_j^2 theta_j + sum over the face's boundary segments of
+//           delta_t l_t,
+// theta_j the angle of the exposed arcs of the circle (the circle where
+// spheres i and j meet), delta_t the signed distance from c_j of the line of
+// the cell edge t = (i, j, k) and l_t the length of its part in B_i.  Both
+// come from K by the same inclusion-exclusion as Eq. 1, one dimension down:
+//   theta_j / 2 pi = Phi_j - sum_{exterior t = ijk} c_t 2 phi_ij(T_x),
+//   sum_t delta_t l_t = sum_{exterior t} c_t delta_t 2 a_t
+//                     + sum_{K-tets T at ij} sum_{faces t of T at ij} delta_t sigma_t zeta_t,
+// with Phi_j = 1 - sum over K-tetrahedra at ij of phi_ij(T) (Eq. 4), c_t =
+// 1 - n_t / 2, phi_ij(T_x) the dihedral fraction along ij between the planes
+// (i, j, k) and (i, j, x) for the triple point x (the half-angle of the arc
+// of the circle inside B_k), a_t the half-chord of the cell edge's line in
+// B_i, zeta_t the position of the tetrahedron's orthocentre on that line
+// (from the chord's middle) and sigma_t = +1 or -1 as the fourth vertex lies
+// ahead or behind along the line (every cell edge is the chord less the parts
+// cut off at its K-tetrahedra; interior triangles are counted through the two
+// tetrahedra that share them).
+// The gradient of V = sum_i V_i is the flux of a translation of sphere i
+// through its exposed part, and the cell's closed boundary turns it into
+//   dV/dp_i = - sum_j F_j (p_j - p_i) / |p_j - p_i|,
+// so every atom's gradient comes from its own faces: no gather.
+#include <hip/hip_runtime.h>
+
+#include "sasa_internal.h"
+
+namespace sasa {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct D3 {
+  double x, y, z;
+};
+__device__ inline D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 operator*(D3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline D3 cross(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline double len(D3 a) { return sqrt(dot(a, a)); }
+
+struct VolLds {
+  double px[KN_CAP], py[KN_CAP], pz[KN_CAP], pw[KN_CAP];  // K-neighbours relative to p_i, weights
+  unsigned tet[KT_CAP];
+  unsigned tri[KTR_CAP];
+  double tphi[KT_CAP][3];  // dihedral fraction of each K-tetrahedron along (i,a), (i,b), (i,c)
+  double tseg[KT_CAP][3];  // its segment terms for the faces on planes a, b, c
+  double rarc[KTR_CAP][2];  // exterior triangle (i,a,b): c_t 2 phi(T_x) along (i,a) and (i,b)
+  double rseg[KTR_CAP][2];  // c_t delta 2 a_t on planes a and b
+};
+
+__device__ inline D3 at(const VolLds& L, int k) { return {L.px[k], L.py[k], L.pz[k]}; }
+
+// Dihedral fraction along the axis e between the half-planes through u and v.
+__device__ inline double dihedral_frac(D3 e, D3 u, D3 v) {
+  const D3 n1 = cross(e, u), n2 = cross(e, v);
+  return atan2(len(cross(n1, n2)), dot(n1, n2)) / kTwoPi;
+}
+
+// Point y of the plane of (0, a, b) with equal power to i, a and b:
+// 2 a.y = ra, 2 b.y = rb, y in span(a, b); returns false when degenerate.
+__device__ inline bool ortho2(D3 a, D3 b, double ra, double rb, D3& y) {
+  const double aa = dot(a, a), bb = dot(b, b), ab = dot(a, b);
+  const double det = 2.0 * (aa * bb - ab * ab);
+  if (!(det != 0.0)) return false;
+  const double al = (ra * bb - rb * ab) / det, be = (aa * rb - ab * ra) / det;
+  y = a * al + b * be;
+  return true;
+}
+
+// Signed distance from the disk centre c_j of plane j to the line of the cell
+// edge (i, j, k), whose closest point to c_j is y: positive when c_j lies on
+// i's side of plane k.
+__device__ inline double delta_of(D3 aj, D3 ak, D3 y, double hj) {
+  const double dj = len(aj);
+  const D3 nj = aj * (1.0 / dj);
+  const D3 m = ak - nj * dot(ak, nj);  // towards k, in the plane of j
+  const D3 cj = nj * hj;
+  return dot(y - cj, m) / len(m);
+}
+
+__device__ inline double plane_offset(const VolLds& L, int k, double wi) {
+  const double d2 = L.px[k] * L.px[k] + L.py[k] * L.py[k] + L.pz[k] * L.pz[k];
+  return (d2 + wi - L.pw[k]) / (2.0 * sqrt(d2));
+}
+
+__global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad) {
+  __shared__ VolLds L;
+  const int i = blockIdx.x;
+  if (i >= b.n) return;
+  const int lane = threadIdx.x;
+  const uint8_t vf = b.vflag[i];
+  if (!(vf & VF_IN)) {
+    if (lane == 0) vol[i] = 0.0;
+    if (lane < 3) grad[3 * (size_t)i + lane] = 0.0;
+    return;
+  }
+  const double4 pi = b.pos[i];
+  const double Ri = pi.w, wi = Ri * Ri;
+  const int nk = min(b.kn_cnt[i], KN_CAP), nt = min(b.kt_cnt[i], KT_CAP), nr = min(b.ktr_cnt[i], KTR_CAP);
+  if (lane < nk) {
+    const double4 pj = b.pos[b.knbr[(size_t)i * KN_CAP + lane]];
+    L.px[lane] = pj.x - pi.x;
+    L.py[lane] = pj.y - pi.y;
+    L.pz[lane] = pj.z - pi.z;
+    L.pw[lane] = pj.w * pj.w;
+  }
+  for (int t = lane; t < nt; t += 64) L.tet[t] = b.ktet[(size_t)i * KT_CAP + t];
+  for (int t = lane; t < nr; t += 64) L.tri[t] = b.ktri[(size_t)i * KTR_CAP + t];
+  __syncthreads();
+  // K-tetrahedra (i, a, b, c): dihedral fractions and the segment terms of
+  // their three faces at i, each on the two planes it lies in
+  for (int t = lane; t < nt; t += 64) {
+    const unsigned w = L.tet[t];
+    const int ks[3] = {(int)(w & 255u), (int)((w >> 8) & 255u), (int)((w >> 16) & 255u)};
+    double ph[3] = {0.0, 0.0, 0.0}, sg[3] = {0.0, 0.0, 0.0};
+    if (ks[0] < nk && ks[1] < nk && ks[2] < nk) {
+      const D3 P[3] = {at(L, ks[0]), at(L, ks[1]), at(L, ks[2])};
+      double r[3], h[3];
+      for (int c = 0; c < 3; ++c) {
+        r[c] = dot(P[c], P[c]) - L.pw[ks[c]] + wi;
+        h[c] = plane_offset(L, ks[c], wi);
+      }
+      // orthocentre z: 2 P_c . z = r_c
+      const D3 bc = cross(P[1], P[2]), ca = cross(P[2], P[0]), ab = cross(P[0], P[1]);
+      const double det = 2.0 * dot(P[0], bc);
+      const D3 z = (bc * r[0] + ca * r[1] + ab * r[2]) * (1.0 / det);
+      for (int c = 0; c < 3; ++c) ph[c] = dihedral_frac(P[c], P[(c + 1) % 3], P[(c + 2) % 3]);
+      // face (e, f) with fourth vertex o
+      for (int o = 0; o < 3; ++o) {
+        const int e = (o + 1) % 3, f = (o + 2) % 3;
+        D3 y;
+        if (!ortho2(P[e], P[f], r[e], r[f], y)) continue;
+        const D3 u = cross(P[e], P[f]);
+        const double zeta = dot(z - y, u) / len(u);
+        const double sz = dot(P[o], u) > 0.0 ? zeta : -zeta;
+        sg[e] += delta_of(P[e], P[f], y, h[e]) * sz;
+        sg[f] += delta_of(P[f], P[e], y, h[f]) * sz;
+      }
+    }
+    for (int c = 0; c < 3; ++c) L.tphi[t][c] = ph[c], L.tseg[t][c] = sg[c];
+  }
+  // exterior K-triangles (i, a, b): the arc of circle (i,a) inside B_b and of
+  // (i,b) inside B_a, and the full-chord segment terms, weighted by c_t
+  for (int t = lane; t < nr; t += 64) {
+    const unsigned w = L.tri[t];
+    const int ka = (int)(w & 255u), kb = (int)((w >> 8) & 255u);
+    const double ct = 1.0 - 0.5 * (double)(w >> 16);
+    double arc_a = 0.0, arc_b = 0.0, seg_a = 0.0, seg_b = 0.0;
+    if (ka < nk && kb < nk) {
+      const D3 A = at(L, ka), B = at(L, kb);
+      const double ra = dot(A, A) - L.pw[ka] + wi, rb = dot(B, B) - L.pw[kb] + wi;
+      D3 y;
+      if (ortho2(A, B, ra, rb, y)) {
+        const double s = dot(y, y) - wi;
+        const double half = s < 0.0 ? sqrt(-s) : 0.0;
+        const D3 u = cross(A, B);
+        const D3 x = y + u * (half / len(u));  // a triple point (either one)
+        arc_a = ct * 2.0 * dihedral_frac(A, B, x);
+        arc_b = ct * 2.0 * dihedral_frac(B, A, x);
+        seg_a = ct * delta_of(A, B, y, plane_offset(L, ka, wi)) * 2.0 * half;
+        seg_b = ct * delta_of(B, A, y, plane_offset(L, kb, wi)) * 2.0 * half;
+      }
+    }
+    L.rarc[t][0] = arc_a, L.rarc[t][1] = arc_b;
+    L.rseg[t][0] = seg_a, L.rseg[t][1] = seg_b;
+  }
+  __syncthreads();
+  // faces: one K-edge per lane (KN_CAP = 64), sums in a fixed order
+  double hv = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  const int k = lane;
+  if (k < nk) {
+    double phi = 0.0, seg = 0.0, arc = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const unsigned w = L.tet[t];
+      const int c = (int)(w & 255u) == k ? 0 : (int)((w >> 8) & 255u) == k ? 1 : (int)((w >> 16) & 255u) == k ? 2 : -1;
+      if (c >= 0) phi += L.tphi[t][c], seg += L.tseg[t][c];
+    }
+    for (int t = 0; t < nr; ++t) {
+      const unsigned w = L.tri[t];
+      const int c = (int)(w & 255u) == k ? 0 : (int)((w >> 8) & 255u) == k ? 1 : -1;
+      if (c >= 0) arc += L.rarc[t][c], seg += L.rseg[t][c];
+    }
+    const D3 P = at(L, k);
+    const double d = len(P);
+    const double h = plane_offset(L, k, wi);
+    const double rho2 = fmax(wi - h * h, 0.0);
+    const double theta = kTwoPi * (1.0 - phi - arc);
+    const double F = 0.5 * (rho2 * theta + seg);
+    hv = h * F;
+    gx = -F * P.x / d, gy = -F * P.y / d, gz = -F * P.z / d;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    hv += __shfl_xor(hv, off, 64);
+    gx += __shfl_xor(gx, off, 64);
+    gy += __shfl_xor(gy, off, 64);
+    gz += __shfl_xor(gz, off, 64);
+  }
+  if (lane == 0) {
+    vol[i] = (Ri * b.area[i] + hv) / 3.0;
+    grad[3 * (size_t)i] = gx;
+    grad[3 * (size_t)i + 1] = gy;
+    grad[3 * (size_t)i + 2] = gz;
+  }
+}
+
+}  // namespace
+
+void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s) {
+  if (b.n) k_volume<<<b.n, 64, 0, s>>>(b, vol, grad);
+}
+
+}  // namespace sasa
