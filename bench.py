@@ -280,6 +280,14 @@ def main():
     volume = {"ms_per_call": 1e3 * tv / kv, "atoms_per_s": n * kv / tv, "calls": kv,
               "volume_A3": float(vol.sum().item())}
 
+    # ---- the paper's sorted-face extraction of the same complex (A/B against
+    # the classification the star kernel does per atom)
+    ctx.compute(X, R, 1.4)
+    ctx.triangles_by_sort()
+    sort_ms = [ctx.triangles_by_sort()[2] for _ in range(5)]
+    sorted_extraction = {"ms": float(np.median(sort_ms)), "triangles": int(ctx.counts()["triangles"]),
+                         "star_kernel_ms": stage["star"] / args.steps}
+
     # ---- dominant kernel roofline (VALU-bound FP64 clipping): k_star alone
     dom = max(stage, key=stage.get)
     star_s = stage["star"] / 1e3 / args.steps
@@ -342,6 +350,7 @@ def main():
         "batched": batched,
         "host_pointers": host,
         "volume": volume,
+        "sorted_extraction": sorted_extraction,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,

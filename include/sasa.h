@@ -152,6 +152,27 @@ int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip
 int sasa_complex_counts(void* ctx, int64_t counts[8]);
 
 /*
+ * The unique K-triangles of the last compute and their n_t, found the way the
+ * paper's GPU section extracts them (for comparison with the star kernel,
+ * which decides n_t per atom): the four faces of every K-tetrahedron are
+ * listed, radix-sorted as 63-bit keys and run-length counted (n_t = 1 or 2);
+ * K-triangles on no K-tetrahedron (n_t = 0) come from the stars.
+ *   tris      3*capacity int32 out (host): ascending atom ids per triangle;
+ *             the tetrahedron faces in lexicographic order, then the n_t = 0
+ *             triangles
+ *   tri_ntet  capacity uint8 out (host): n_t
+ *   count     out: number of triangles (= sasa_complex_counts()[2]); with tris
+ *             or tri_ntet NULL only the count (and ms) is returned
+ *   ms        out (may be NULL): GPU time of the extraction (emit, sort,
+ *             count, unpack) on the null stream
+ * Allocates its work buffers on first use.  SASA_E_CAPACITY if count >
+ * capacity, SASA_E_INVAL for 2^21 atoms or more, SASA_E_STATE without a kept
+ * compute.
+ */
+int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
+                           float* ms);
+
+/*
  * Copy the kept complex to host arrays sized by sasa_complex_counts: each
  * simplex once, vertex indices ascending inside a tuple (batch-global atom
  * indices), in no particular order between tuples.

@@ -29,7 +29,7 @@ SASA_FLAG_FRAMES = 4
 # every entry point of include/sasa.h
 EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
-    "sasa_volume", "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_footprint", "sasa_capacity",
+    "sasa_volume", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_footprint", "sasa_capacity",
     "sasa_strerror", "sasa_last_error",
 )
 
@@ -83,6 +83,7 @@ def load():
     L.sasa_compute_forces.argtypes = [P, I64, P, P, D, D, P, P, I32, P]
     L.sasa_backward.argtypes = [P, P, P, I32, P]
     L.sasa_volume.argtypes = [P, P, P, I32, P]
+    L.sasa_triangles_by_sort.argtypes = [P, P, P, I64, P, P]
     L.sasa_complex_counts.argtypes = [P, P]
     L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
     L.sasa_diagnostics.argtypes = [P, ctypes.POINTER(sasa_diag), I64]
@@ -95,7 +96,7 @@ def load():
     L.sasa_last_error.argtypes = [P]
     L.sasa_last_error.restype = ctypes.c_char_p
     for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
-                 "sasa_volume", "sasa_complex_counts",
+                 "sasa_volume", "sasa_triangles_by_sort", "sasa_complex_counts",
                  "sasa_complex_export", "sasa_diagnostics"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -189,6 +190,19 @@ def sasa_volume(ctx, volume, dV_dx, mem=None, stream=None):
     mem = mem_of(*arrs) if mem is None else mem
     stream = stream_of(arrs) if stream is None else stream
     return check(load().sasa_volume(ctx, ptr(volume), ptr(dV_dx), mem, stream), ctx)
+
+
+def sasa_triangles_by_sort(ctx):
+    """(tris (m, 3) int32, n_t (m,) uint8, GPU ms) of the sorted-face extraction."""
+    L = load()
+    m = ctypes.c_int64(0)
+    ms = ctypes.c_float(0.0)
+    check(L.sasa_triangles_by_sort(ctx, None, None, 0, ctypes.byref(m), ctypes.byref(ms)), ctx)
+    tris = np.zeros((max(m.value, 1), 3), np.int32)
+    nt = np.zeros(max(m.value, 1), np.uint8)
+    check(L.sasa_triangles_by_sort(ctx, ctypes.c_void_p(tris.ctypes.data), ctypes.c_void_p(nt.ctypes.data),
+                                   int(m.value), ctypes.byref(m), ctypes.byref(ms)), ctx)
+    return tris[:m.value], nt[:m.value], float(ms.value)
 
 
 def sasa_complex_counts(ctx):

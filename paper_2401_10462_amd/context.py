@@ -74,6 +74,10 @@ class SasaContext:
         _lib.sasa_volume(self._h, vol, grad)
         return vol, grad
 
+    def triangles_by_sort(self):
+        """The kept complex's triangles and n_t by the sorted-face extraction, and its GPU time (ms)."""
+        return _lib.sasa_triangles_by_sort(self._h)
+
     def counts(self):
         c = _lib.sasa_complex_counts(self._h)
         keys = ("vertices", "edges", "triangles", "tetrahedra", "ext_vertices", "ext_edges", "ext_triangles", "atoms")

@@ -49,6 +49,8 @@ struct Ctx {
   hipEvent_t ev[6] = {};  // stage boundaries (SASA_FLAG_TIMING)
   bool timed = false;     // events of the last call were recorded
   int64_t fac_atoms = -1;  // atom count of the call that wrote the facet hints (-1: none)
+  SortedFaces sf;           // buffers of the sorted-face extraction (grown on demand)
+  int64_t sf_cap_faces = -1, sf_cap_free = -1;
   sasa_diag diag{};
   std::string err;
 };
@@ -343,7 +345,9 @@ void sasa_destroy(void* ctx) {
   Bufs& b = c->b;
   void* dev[] = {b.pos,  b.mol,   b.cellid,   b.cnt,      b.start,  b.scan_tmp, b.sorted, b.spos, b.smc,
                  b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.wide, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
-                 b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, b.fac, b.vtx, b.hint_n, c->xyz_d,
+                 b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, b.fac, b.vtx, b.hint_n,
+                 c->sf.faces, c->sf.sorted, c->sf.uniq, c->sf.counts, c->sf.nruns, c->sf.free_tris, c->sf.cursors,
+                 c->sf.tris, c->sf.ntet, c->sf.temp, c->xyz_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -439,6 +443,74 @@ int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip
     HIP_TRY(c, hipStreamSynchronize(s));
   } else if (!(c->flags & SASA_FLAG_ASYNC)) {
     HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return SASA_OK;
+}
+
+int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
+                           float* ms) {
+  auto* c = (Ctx*)ctx;
+  if (!c || !count) return fail(c, SASA_E_INVAL, "NULL argument");
+  int64_t cnt[8];
+  int rc = sasa_complex_counts(ctx, cnt);
+  if (rc) return rc;
+  if (c->n >= (int64_t)1 << 21) return fail(c, SASA_E_INVAL, "the sorted extraction packs atom ids in 21 bits");
+  HIP_TRY(c, hipSetDevice(c->device));
+  SortedFaces& w = c->sf;
+  const int64_t nfaces = 4 * cnt[3], cap_free = cnt[6];
+  if (nfaces > c->sf_cap_faces || cap_free > c->sf_cap_free) {
+    const int64_t nf = std::max<int64_t>(nfaces, 1), nz = std::max<int64_t>(cap_free, 1);
+    HIP_TRY(c, grow(&w.faces, nf));
+    HIP_TRY(c, grow(&w.sorted, nf));
+    HIP_TRY(c, grow(&w.uniq, nf));
+    HIP_TRY(c, grow(&w.counts, nf));
+    HIP_TRY(c, grow(&w.free_tris, nz));
+    HIP_TRY(c, grow(&w.tris, 3 * (nf + nz)));
+    HIP_TRY(c, grow(&w.ntet, nf + nz));
+    if (!w.nruns) HIP_TRY(c, grow(&w.nruns, 4));
+    if (!w.cursors) HIP_TRY(c, grow(&w.cursors, 2));
+    const size_t tb = sorted_faces_temp_bytes(nf);
+    if (tb > w.temp_bytes) {
+      HIP_TRY(c, grow((char**)&w.temp, tb));
+      w.temp_bytes = tb;
+    }
+    c->sf_cap_faces = nfaces;
+    c->sf_cap_free = cap_free;
+  }
+  w.nfaces = nfaces;
+  w.cap_free = cap_free;
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  launch_zero(w.cursors, 2 * sizeof(unsigned long long), s);
+  launch_zero(w.nruns, sizeof(unsigned), s);
+  HIP_TRY(c, hipEventRecord(e0, s));
+  const hipError_t le = launch_sorted_faces(b, w, s);
+  HIP_TRY(c, hipEventRecord(e1, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  float t = 0.0f;
+  HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(c, le);
+  unsigned nruns = 0;
+  unsigned long long cur[2] = {0, 0};
+  HIP_TRY(c, hipMemcpy(&nruns, w.nruns, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(cur, w.cursors, sizeof(cur), hipMemcpyDeviceToHost));
+  if ((int64_t)cur[0] != nfaces || (int64_t)cur[1] > cap_free)
+    return fail(c, SASA_E_DEVICE, "sorted extraction: face count differs from the complex's counters");
+  const int64_t m = (int64_t)nruns + (int64_t)cur[1];
+  *count = m;
+  if (ms) *ms = t;
+  if (!tris || !tri_ntet) return SASA_OK;  // size query
+  if (m > capacity) return fail(c, SASA_E_CAPACITY, "sorted extraction: output capacity too small");
+  if (m) {
+    HIP_TRY(c, hipMemcpy(tris, w.tris, (size_t)m * 3 * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(tri_ntet, w.ntet, (size_t)m, hipMemcpyDeviceToHost));
   }
   return SASA_OK;
 }

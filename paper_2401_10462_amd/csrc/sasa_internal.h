@@ -153,6 +153,28 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 // Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64).
 void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s);
+
+// Unique triangles of the kept complex by sorting the faces of its
+// tetrahedra (the paper's extraction, for comparison with the stars).
+// nfaces = 4 x owned K-tetrahedra, cap_free >= owned tetrahedron-free
+// K-triangles; cursors (2) and nruns start at 0; tris / ntet hold
+// nfaces + cap_free entries.
+struct SortedFaces {
+  unsigned long long* faces = nullptr;      // nfaces keys (emitted)
+  unsigned long long* sorted = nullptr;     // nfaces keys (sorted)
+  unsigned long long* uniq = nullptr;       // nfaces (runs)
+  unsigned* counts = nullptr;               // nfaces (run lengths = n_t)
+  unsigned* nruns = nullptr;                // 1
+  unsigned long long* free_tris = nullptr;  // cap_free keys
+  unsigned long long* cursors = nullptr;    // 2
+  int* tris = nullptr;                      // 3 (nfaces + cap_free)
+  uint8_t* ntet = nullptr;                  // nfaces + cap_free
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  long long nfaces = 0, cap_free = 0;
+};
+size_t sorted_faces_temp_bytes(int64_t nfaces);
+hipError_t launch_sorted_faces(const Bufs& b, const SortedFaces& w, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int scan_blocks(unsigned hb);
 // Grid cells a batch of n atoms may use: a molecule of m > 0 atoms gets at most
