@@ -6,9 +6,10 @@ synthetic molecule whose coordinates are already resident in HBM.
 
 Workload (default): a 5,000-atom globule -- 2,500 heavy atoms (compact
 self-avoiding chain, C/N/O/S radii) plus 2,500 hydrogens (r = 1.20 A) --,
-probe 1.4 A, FP64 throughout (MI355X runs FP64 vector arithmetic at the
-rate of unpacked FP32, and the MIXED form, float area terms, measures
-slower), per-atom SASA and d(sum A)/dx.
+probe 1.4 A, MIXED precision as the workload names it (float area terms,
+double predicates and accumulation), per-atom SASA and d(sum A)/dx.  The
+same plain loop in FP64 is reported beside it: MI355X runs FP64 vector
+arithmetic at the rate of unpacked FP32, and FP64 measures faster.
 
 Prints one JSON line.  Extra keys: p50/p99 per-step latency, the batched
 form (many molecules per launch sequence), the roofline of the dominant kernel
@@ -28,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SASA+gradient atoms/s at 1 GPU (batched vs plain, \u22641e-4 rel err); p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64
+HBM_PEAK = 8.0e12        # MI355X HBM3E, bytes/s
 # FP64 operations per unit of star-kernel work, counted from the kernel source:
 #   side test of a cell vertex against a plane: 3 mul + 3 add/sub        =  6
 #   new cell vertex from three planes (cross products, det, 1 div, 3 dots) = 51
@@ -40,7 +42,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=30)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--precision", default="fp64", choices=["mixed", "fp64"])
+    p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     p.add_argument("--heavy", type=int, default=2500, help="heavy atoms (hydrogens double it)")
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--batch", type=int, default=32, help="molecules in the batched form (0: skip)")
@@ -295,10 +297,13 @@ def main():
     flops = (FLOP_PER_TEST * work["plane_tests"] + FLOP_PER_VERTEX * work["new_vertices"]
              + FLOP_PER_CANDIDATE * work["candidates"]) / args.steps
     achieved = flops / star_s / 1e12
+    traffic = measured_traffic() if args.heavy == 2500 and args.seed == 2 else None
     roofline = {"kernel": "k_star", "dominant_stage": dom, "bound": "alu", "achieved": achieved,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": measured_traffic() if args.heavy == 2500 and args.seed == 2 else None,
+                "traffic": traffic,
                 "flop_per_launch": flops, "ms_per_launch": star_s * 1e3,
+                "hbm_gbs": (traffic / star_s / 1e9) if traffic else None,
+                "hbm_frac": (traffic / star_s / HBM_PEAK) if traffic else None,
                 "stage_ms_per_step": {k: v / args.steps for k, v in stage.items()}}
 
     # ---- batched form: many molecules (rigid copies) in one launch sequence
@@ -326,6 +331,20 @@ def main():
                    "atoms_per_s": n * args.batch * kb / eb, "ms_per_step": 1e3 * eb / kb,
                    "speedup_vs_plain": (n * args.batch * kb / eb) / value}
 
+    # ---- the same plain loop in the other precision
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    octx = SasaContext(precision=other, max_atoms=n)
+    for _ in range(args.warmup):
+        octx.compute(X, R, 1.4)
+    torch.cuda.synchronize()
+    to = time.perf_counter()
+    for _ in range(args.steps):
+        octx.compute(X, R, 1.4)
+    torch.cuda.synchronize()
+    eo = time.perf_counter() - to
+    other_precision = {"precision": other, "atoms_per_s": n * args.steps / eo, "ms_per_step": 1e3 * eo / args.steps}
+    octx.close()
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(xyz, rad, args.cpu_seconds, area.cpu().numpy(), dadx.cpu().numpy())
@@ -349,6 +368,7 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "batched": batched,
+        "other_precision": other_precision,
         "host_pointers": host,
         "volume": volume,
         "sorted_extraction": sorted_extraction,
