@@ -539,7 +539,12 @@ __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, 
   const double bcx = B.y * C.z - B.z * C.y, bcy = B.z * C.x - B.x * C.z, bcz = B.x * C.y - B.y * C.x;
   const double cax = C.y * A.z - C.z * A.y, cay = C.z * A.x - C.x * A.z, caz = C.x * A.y - C.y * A.x;
   const double abx = A.y * B.z - A.z * B.y, aby = A.z * B.x - A.x * B.z, abz = A.x * B.y - A.y * B.x;
-  const double inv = 1.0 / (A.x * bcx + A.y * bcy + A.z * bcz);
+  // 1 / det from the hardware estimate and two Newton steps (a fixed sequence,
+  // so a vertex still has one value however it is reached)
+  const double det = A.x * bcx + A.y * bcy + A.z * bcz;
+  double inv = __builtin_amdgcn_rcp(det);
+  inv = fma(inv, fma(-det, inv, 1.0), inv);
+  inv = fma(inv, fma(-det, inv, 1.0), inv);
   x = (A.b * bcx + B.b * cax + C.b * abx) * inv;
   y = (A.b * bcy + B.b * cay + C.b * aby) * inv;
   z = (A.b * bcz + B.b * caz + C.b * abz) * inv;
@@ -942,10 +947,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       if (cross) {
         const int slot = nkeep + ncross + prefix_below(cm);
         if (slot < VC) {
-          const unsigned tri3 = pack3(pr & 1023u, pr >> 10, pid);
+          // the pair is stored ascending and the cutting plane has the highest id
+          // so far, so the triple is already in ascending order
+          const unsigned tri3 = pr | (pid << 20);
           double x, y, z;
-          solve3(plane_of(L, b, pi, wi, pid0(tri3), half), plane_of(L, b, pi, wi, pid1(tri3), half),
-                 plane_of(L, b, pi, wi, pid2(tri3), half), x, y, z);
+          solve3(plane_of(L, b, pi, wi, pr & 1023u, half), plane_of(L, b, pi, wi, pr >> 10, half), qk, x, y, z);
           L.u.cl.vx[slot] = x;
           L.u.cl.vy[slot] = y;
           L.u.cl.vz[slot] = z;

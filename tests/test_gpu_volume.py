@@ -32,6 +32,7 @@ CASES = [
     ("cluster-80-wide-radii", lambda: random_cluster(80, 4, rmin=0.6, rmax=2.4)),
     ("globule-300", lambda: heavy_chain(300, 1)[:2]),
     ("globule-1000H", lambda: globule(500, 3, hydrogens=True)),
+    ("globule-5000H-benchmark", lambda: globule(2500, 2, hydrogens=True)),
 ]
 
 
