@@ -564,8 +564,22 @@ __device__ inline int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l)
 // well below 1e-9 A, and exact ties fall back to the atom id).
 constexpr double kFirstShift = 1.0e6;
 
-// clipping order of candidate (k, i) before (kk, ii): nearest plane first, ties by atom id
-__device__ inline int before(double k, int i, double kk, int ii) { return (k < kk) || (k == kk && i < ii); }
+// Clipping order of a candidate as one 64-bit integer: its plane distance
+// rounded to float (as order-preserving bits) above its atom id, so that
+// nearest plane comes first and ties go by atom id, and ranking compares one
+// lane pair per candidate.  Rounding to float can only reorder planes whose
+// distances agree to about 1e-7 relative; the stopping test keeps a margin
+// above that.
+__device__ inline unsigned long long order_key(double key, int id) {
+  const unsigned u = __float_as_uint((float)key);
+  const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((unsigned long long)o << 32) | (unsigned)id;
+}
+__device__ inline unsigned long long rdl64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
 
 __device__ inline double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -737,27 +751,25 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     if (ft2 >= 0) ck2 -= kFirstShift;
     nfirst = __popcll(__ballot(ft0 >= 0)) + __popcll(__ballot(ft1 >= 0)) + __popcll(__ballot(ft2 >= 0));
   }
+  const unsigned long long ok0 = order_key(ck0, ci0), ok1 = order_key(ck1, ci1), ok2 = order_key(ck2, ci2);
   int rk0 = 0, rk1 = 0, rk2 = 0;
   for (int hb = 0; hb < nsets; ++hb) {
-    const double kk = hb == 0 ? ck0 : (hb == 1 ? ck1 : ck2);
-    const int ii = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
+    const unsigned long long kk = hb == 0 ? ok0 : (hb == 1 ? ok1 : ok2);
     const int lim = min(64, nn - 64 * hb);
     if (nsets == 1) {
-      for (int t = 0; t < lim; ++t) rk0 += before(rdl(kk, t), rdl(ii, t), ck0, ci0);
+      for (int t = 0; t < lim; ++t) rk0 += rdl64(kk, t) < ok0;
     } else if (nsets == 2) {
       for (int t = 0; t < lim; ++t) {
-        const double kt = rdl(kk, t);
-        const int it = rdl(ii, t);
-        rk0 += before(kt, it, ck0, ci0);
-        rk1 += before(kt, it, ck1, ci1);
+        const unsigned long long kt = rdl64(kk, t);
+        rk0 += kt < ok0;
+        rk1 += kt < ok1;
       }
     } else {
       for (int t = 0; t < lim; ++t) {
-        const double kt = rdl(kk, t);
-        const int it = rdl(ii, t);
-        rk0 += before(kt, it, ck0, ci0);
-        rk1 += before(kt, it, ck1, ci1);
-        rk2 += before(kt, it, ck2, ci2);
+        const unsigned long long kt = rdl64(kk, t);
+        rk0 += kt < ok0;
+        rk1 += kt < ok1;
+        rk2 += kt < ok2;
       }
     }
   }
@@ -863,14 +875,15 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     // security radius: the plane's signed distance from p_i is b / |n| (its
     // ranking key); once it reaches the largest |v| of the cell, no plane from
     // here on can cut it.  Tested without a root or division as b >= 0 and
-    // b^2 >= rho^2 |n|^2, with a margin for the last-bit differences between
-    // this form and the ranking key.  A neighbour at the same centre (n = 0)
+    // b^2 >= rho^2 |n|^2, with a margin (1e-6 on the squares) above the float
+    // rounding of the ranking key, which may put a plane up to about 1e-7
+    // nearer after this one.  A neighbour at the same centre (n = 0)
     // has no plane and never ends the loop.  rho^2 is kept as an upper bound
     // (a cut never moves a vertex away from p_i) and made exact only when the
     // bound would end the loop.
     const double qn2 = qx * qx + qy * qy + qz * qz;
     const bool far = k >= nfirst && qn2 > 0.0 && qb >= 0.0;  // the rest is in plane order
-    if (far && qb * qb >= (rho2 * (1.0 + 1e-9) + 1e-12) * qn2) {
+    if (far && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) {
       if (!rho_exact) {
         double r2 = 0.0;
         if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
@@ -878,7 +891,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         rho2 = wave_max(r2);
         rho_exact = true;
       }
-      if (qb * qb >= (rho2 * (1.0 + 1e-9) + 1e-12) * qn2) {
+      if (qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) {
         kstop = k;
         break;
       }
@@ -1349,7 +1362,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
 constexpr int V_FAST = 64, NPL_FAST = 128;
 
 template <bool HINTS>
-__global__ __launch_bounds__(64) void k_star(Bufs b) {
+__global__ __launch_bounds__(64, 5) void k_star(Bufs b) {
   __shared__ StarLds<NB_CAP, V_FAST, NPL_FAST> L;
   if ((int)blockIdx.x >= b.n) return;
   if (!star_atom<HINTS>(b, L, blockIdx.x, false) && threadIdx.x == 0) {
