@@ -47,9 +47,10 @@ def parse():
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--batch", type=int, default=32, help="molecules in the batched form (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU leg (0: skip)")
-    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md", "gbsa"],
+    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md", "gbsa", "small", "autograd"],
                    help="globule: the headline line; serving: Poisson stream sweep; md: MD-like frames; "
-                        "gbsa: Langevin harness with SASA forces through autograd")
+                        "gbsa: Langevin harness with SASA forces through autograd; small: one 300-heavy-atom "
+                        "globule in FP64; autograd: 64 conformations of 2,000 atoms, forward + backward")
     p.add_argument("--serve-requests", type=int, default=600, help="requests per arrival rate (serving)")
     p.add_argument("--rates", default="100,500,2000,5000", help="arrival rates, req/s (serving)")
     p.add_argument("--md-atoms", type=int, default=20000)
@@ -143,6 +144,68 @@ def gbsa(args, precision):
             "nonpolar_kcal_mol": tr[-1][2]}
 
 
+def small(args):
+    """One 300-heavy-atom globule, FP64, plain calls: atoms/s and p50/p99 latency."""
+    import torch
+    from paper_2401_10462_amd import SasaContext
+    from synth.globule import heavy_chain
+    xyz, rad, _ = heavy_chain(300, 1)
+    dev = torch.device("cuda:0")
+    X, R = torch.tensor(xyz, device=dev), torch.tensor(rad, device=dev)
+    ctx = SasaContext(precision="fp64", max_atoms=len(rad))
+    for _ in range(max(args.warmup, 3)):
+        ctx.compute(X, R, 1.4)
+    torch.cuda.synchronize()
+    lat = []
+    steps = max(args.steps, 100)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        ctx.compute(X, R, 1.4)
+        lat.append(time.perf_counter() - s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    return {"atoms": len(rad), "steps": steps, "atoms_per_s": len(rad) * steps / el, "ms_per_step": 1e3 * el / steps,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+
+
+def autograd(args):
+    """64 conformations of 2,000 atoms in one batch through SASAFunction: loss = sum w_i A_i, forward + backward."""
+    import torch
+    from paper_2401_10462_amd.autograd import sasa
+    from synth.globule import heavy_chains, md_frames
+    base = heavy_chains([(2000, 50_000 + m) for m in range(8)])
+    mols = [(xf, r) for m, (x, r, _) in enumerate(base) for xf in md_frames(x, 500 + m, 8, sigma=0.02)]
+    offs = np.cumsum([0] + [len(r) for _, r in mols]).astype(np.int64)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(np.vstack([x for x, _ in mols]), device=dev)
+    R = torch.tensor(np.concatenate([r for _, r in mols]), device=dev)
+    w = torch.tensor(np.random.default_rng(5).uniform(-1, 1, len(R)), device=dev)
+
+    def step():
+        x = X.detach().requires_grad_(True)
+        (w * sasa(x, R, 1.4, offsets=offs, precision=args.precision)).sum().backward()
+        return x.grad
+
+    for _ in range(max(args.warmup, 2)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(args.steps // 3, 5)
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s)
+    el = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    return {"molecules": 64, "atoms": int(len(R)), "steps": steps, "atoms_per_s": len(R) * steps / el,
+            "ms_per_step": 1e3 * el / steps, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99))}
+
+
 def measured_traffic():
     """HBM bytes per k_star launch from the committed rocprofv3 counter runs, or
     None when kernels.hip has changed since those counters were taken."""
@@ -209,6 +272,12 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps({"workload": "serving", "precision": args.precision, **serving(args, args.precision)}))
+        return
+    if args.workload == "small":
+        print(json.dumps({"workload": "small", "precision": "fp64", **small(args)}))
+        return
+    if args.workload == "autograd":
+        print(json.dumps({"workload": "autograd", "precision": args.precision, **autograd(args)}))
         return
     if args.workload == "gbsa":
         print(json.dumps({"workload": "gbsa", "precision": args.precision, **gbsa(args, args.precision)}))
