@@ -11,9 +11,13 @@
  *   - its interior / exterior classification (GPU section, extraction of
  *     exterior simplices);
  *   - the per-atom inclusion-exclusion area of Eq. 1 with the vertex, edge and
- *     triangle terms of Eqs. 3, 4 and 6, and the derivatives of Eqs. 2, 5, 7.
+ *     triangle terms of Eqs. 3, 4 and 6, and the derivatives of Eqs. 2, 5, 7;
+ *   - the volumes of the same cells and the molecular-volume gradient
+ *     (sasa_volume; the Discussion's extension to volumes);
+ *   - the paper's sort-based extraction of unique triangles, for comparison
+ *     (sasa_triangles_by_sort).
  *
- * Units: lengths in Angstrom, areas in A^2, gradients in A^2/A.
+ * Units: lengths in Angstrom, areas in A^2, volumes in A^3, gradients in A^2/A.
  *
  * Memory.  Every data pointer is either host or device memory, as the `mem`
  * argument says; all pointers of one call live in the same space.  The caller

@@ -1,6 +1,8 @@
 // kernels.hip -- HIP kernels (gfx950, wave64) of the exact analytic SASA path.
 //
 // Pipeline for one batch of molecules (each molecule is one segment of atoms):
+//   k_cells_one one molecule of up to 65,536 atoms: the whole cell-list stage
+//               below in one block (weights, box, grid, counts, scan, scatter)
 //   k_prep      weights R_i = r_i + probe, molecule ids, input checks, R_max and
 //               each molecule's bounding box
 //   k_grid      one dense cell grid per molecule (cell side >= R_max)
@@ -11,10 +13,13 @@
 //   k_star      one wavefront per atom: its power (Laguerre) cell clipped by the
 //               radical planes of its overlapping neighbours, restricted to its
 //               ball; yields the atom's star in the dual complex K, the
-//               exterior classification, and the owned simplex counts
+//               exterior classification, and a per-atom statistics record
+//               (a trajectory's calls start from the previous frame's cell)
+//   k_star_wide the atoms whose cell outgrew the fast pass, with full capacities
+//   k_stats     the statistics records folded into the counters
 //   k_terms     one wavefront per exterior atom: Eq. 1 area from the star and,
 //               on request, the gradient blocks dA_i/dp_m of Eq. 2
-//   k_gather    one thread per atom: segmented sum over its K-neighbours of
+//   k_gather    16 lanes per atom: segmented sum over its K-neighbours of
 //               u_i dA_i/dp_m (deterministic order)
 #include <hip/hip_runtime.h>
 
@@ -458,10 +463,6 @@ __device__ inline unsigned pack3(unsigned a, unsigned b, unsigned c) {
 __device__ inline unsigned pid0(unsigned p) { return p & 1023u; }
 __device__ inline unsigned pid1(unsigned p) { return (p >> 10) & 1023u; }
 __device__ inline unsigned pid2(unsigned p) { return p >> 20; }
-__device__ inline bool has2(unsigned p, unsigned a, unsigned b) {
-  const unsigned x = pid0(p), y = pid1(p), z = pid2(p);
-  return (x == a || y == a || z == a) && (x == b || y == b || z == b);
-}
 
 constexpr int EH_BITS = 8, EH_SIZE = 1 << EH_BITS;  // > 2 x the 1.5 VC edges of a cell
 
