@@ -54,6 +54,9 @@ def lib():
         L.oracle_facet_area.restype = ctypes.c_double
         L.oracle_facet_area.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64]
         L.oracle_volume.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp, dp]
+        L.oracle_facet_centroid.restype = ctypes.c_double
+        L.oracle_facet_centroid.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, dp]
+        L.oracle_volume_vjp.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp]
         L.oracle_triple_term.restype = ctypes.c_double
         L.oracle_triple_term.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double, dp, ctypes.c_double]
         _lib = L
@@ -179,3 +182,22 @@ def facet_area(xyz, radii, probe, i, j):
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
     radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
     return lib().oracle_facet_area(len(radii), _dp(xyz), _dp(radii), probe, int(i), int(j))
+
+
+def facet_centroid(xyz, radii, probe, i, j):
+    """(area, absolute centroid) of the flat face of B_i ∩ L_i on the radical plane of i and j."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    c = np.zeros(3)
+    f = lib().oracle_facet_centroid(len(radii), _dp(xyz), _dp(radii), probe, int(i), int(j), _dp(c))
+    return f, c
+
+
+def volume_vjp(xyz, radii, probe, u):
+    """sum_i u_i dV_i/dp_m (n x 3) of the per-atom cell volumes, through the faces' areas and centroids."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    out = np.zeros((len(radii), 3))
+    lib().oracle_volume_vjp(len(radii), _dp(xyz), _dp(radii), probe, _dp(u), _dp(out))
+    return out

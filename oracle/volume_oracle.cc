@@ -78,6 +78,47 @@ double tri_disk(P2 a, P2 b, double r) {
   return s;
 }
 
+// First moment (integral of y over the region, origin at the disk centre) of
+// the same signed piece as tri_disk: triangles contribute area x centroid,
+// sectors (r^2 / 3) rot(q - p) for the sweep from p to q.
+void tri_disk_moment(P2 a, P2 b, double r, double m[2]) {
+  const double r2 = r * r;
+  const P2 d = {b.x - a.x, b.y - a.y};
+  const double A = d.x * d.x + d.y * d.y;
+  if (A == 0.0) return;
+  const double B = a.x * d.x + a.y * d.y;
+  const double C = a.x * a.x + a.y * a.y - r2;
+  double ts[4] = {0.0, 0.0, 0.0, 1.0};
+  int nt = 1;
+  const double disc = B * B - A * C;
+  if (disc > 0.0) {
+    const double sq = std::sqrt(disc);
+    const double t1 = (-B - sq) / A, t2 = (-B + sq) / A;
+    if (t1 > 0.0 && t1 < 1.0) ts[nt++] = t1;
+    if (t2 > 0.0 && t2 < 1.0) ts[nt++] = t2;
+  }
+  ts[nt++] = 1.0;
+  for (int k = 0; k + 1 < nt; ++k) {
+    const P2 p = {a.x + ts[k] * d.x, a.y + ts[k] * d.y};
+    const P2 q = {a.x + ts[k + 1] * d.x, a.y + ts[k + 1] * d.y};
+    const double tm = 0.5 * (ts[k] + ts[k + 1]);
+    const P2 mm = {a.x + tm * d.x, a.y + tm * d.y};
+    if (mm.x * mm.x + mm.y * mm.y <= r2) {
+      const double ar = 0.5 * cross(p, q);
+      m[0] += ar * (p.x + q.x) / 3.0;
+      m[1] += ar * (p.y + q.y) / 3.0;
+    } else {
+      // the sector swept from p to q the short way (as tri_disk's atan2)
+      const double ang = std::atan2(cross(p, q), p.x * q.x + p.y * q.y);
+      const P2 pu = {p.x * r / std::sqrt(p.x * p.x + p.y * p.y), p.y * r / std::sqrt(p.x * p.x + p.y * p.y)};
+      const double c0 = std::atan2(pu.y, pu.x);
+      const double c1 = c0 + ang;
+      m[0] += r2 * r / 3.0 * (std::sin(c1) - std::sin(c0));
+      m[1] += r2 * r / 3.0 * (std::cos(c0) - std::cos(c1));
+    }
+  }
+}
+
 struct Atoms {
   int64_t n;
   const double* x;
@@ -85,7 +126,7 @@ struct Atoms {
   std::vector<std::vector<int64_t>> nbr;  // atoms whose ball meets B_i (all-pairs search)
 };
 
-double facet(const Atoms& at, int64_t i, int64_t j) {
+double facet(const Atoms& at, int64_t i, int64_t j, double* centroid = nullptr) {
   const double* pi = at.x + 3 * i;
   const double* pj = at.x + 3 * j;
   const double u[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
@@ -127,8 +168,13 @@ double facet(const Atoms& at, int64_t i, int64_t j) {
     poly = clip(poly, ca, cb, rhs);
   }
   if (poly.size() < 3) return 0.0;
-  double area = 0.0;
-  for (size_t k = 0; k < poly.size(); ++k) area += tri_disk(poly[k], poly[(k + 1) % poly.size()], rho);
+  double area = 0.0, m[2] = {0.0, 0.0};
+  for (size_t k = 0; k < poly.size(); ++k) {
+    area += tri_disk(poly[k], poly[(k + 1) % poly.size()], rho);
+    if (centroid) tri_disk_moment(poly[k], poly[(k + 1) % poly.size()], rho, m);
+  }
+  if (centroid && area > 0.0)  // absolute position of the face's centroid
+    for (int q = 0; q < 3; ++q) centroid[q] = pi[q] + c[q] + (m[0] * e1[q] + m[1] * e2[q]) / area;
   return area;
 }
 
@@ -176,6 +222,39 @@ void oracle_volume(int64_t n, const double* xyz, const double* radii, double pro
     }
     vol[i] = s / 3.0;
     for (int c = 0; c < 3; ++c) grad[3 * i + c] = g[c];
+  }
+}
+
+// Centroid (3 doubles out, absolute) and area of the flat face of B_i ∩ L_i on
+// the radical plane of i and j.
+double oracle_facet_centroid(int64_t n, const double* xyz, const double* radii, double probe, int64_t i, int64_t j,
+                             double* centroid) {
+  const Atoms at = make(n, xyz, radii, probe);
+  return facet(at, i, j, centroid);
+}
+
+// Vector-Jacobian product of the per-atom volumes: out[m] = sum_i u_i dV_i/dp_m.
+// Moving p_j moves only the face (i, j) of cell i, with normal speed
+// -(x - p_j).delta / d_ij, so dV_i/dp_j = -F_ij (c_ij - p_j) / d_ij (c_ij the
+// face centroid); moving p_i moves its sphere rigidly and every face of its
+// cell, so dV_i/dp_i = sum_j F_ij [(c_ij - p_i) / d_ij - u_ij].  Together:
+//   out[m] = sum_j F_mj [(u_m - u_j) (c_mj - p_m) / d_mj - u_m (p_j - p_m) / d_mj].
+void oracle_volume_vjp(int64_t n, const double* xyz, const double* radii, double probe, const double* u,
+                       double* out) {
+  const Atoms at = make(n, xyz, radii, probe);
+  for (int64_t m = 0; m < n; ++m) {
+    double g[3] = {0.0, 0.0, 0.0};
+    for (const int64_t j : at.nbr[m]) {
+      double cen[3];
+      const double f = facet(at, m, j, cen);
+      if (f == 0.0) continue;
+      const double* pm = xyz + 3 * m;
+      const double* pj = xyz + 3 * j;
+      const double dv[3] = {pj[0] - pm[0], pj[1] - pm[1], pj[2] - pm[2]};
+      const double d = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      for (int q = 0; q < 3; ++q) g[q] += f * ((u[m] - u[j]) * (cen[q] - pm[q]) / d - u[m] * dv[q] / d);
+    }
+    for (int q = 0; q < 3; ++q) out[3 * m + q] = g[q];
   }
 }
 

@@ -85,3 +85,35 @@ def test_invariants():
     assert np.abs(v2 - v).max() < 1e-9 and np.abs(g2 - g @ q.T).max() < 1e-9
     v3, g3 = oracle.volume(2.0 * xyz, 2.0 * rad, 2.8)           # scaling by s = 2
     assert np.abs(v3 - 8.0 * v).max() < 1e-8 and np.abs(g3 - 4.0 * g).max() < 1e-8
+
+
+def test_face_centroids():
+    # a face that is a whole disk has its centre as centroid; a face is one set
+    # of points, so (i, j) and (j, i) give the same centroid
+    x = np.array([[0.0, 0.0, 0.0], [2.5, 0.0, 0.0]])
+    f, c = oracle.facet_centroid(x, np.array([1.6, 1.2]), 1.4, 0, 1)
+    h = (2.5 ** 2 + 3.0 ** 2 - 2.6 ** 2) / (2 * 2.5)
+    assert abs(f - math.pi * (9.0 - h * h)) < 1e-10 and np.abs(c - [h, 0.0, 0.0]).max() < 1e-12
+    xyz, rad = random_cluster(12, 7, rmin=1.0, rmax=2.0)
+    for i in range(12):
+        for j in range(i + 1, 12):
+            fa, ca = oracle.facet_centroid(xyz, rad, 1.4, i, j)
+            fb, cb = oracle.facet_centroid(xyz, rad, 1.4, j, i)
+            if fa > 1e-6:
+                assert np.abs(ca - cb).max() < 1e-9
+
+
+def test_volume_vjp_finite_differences():
+    xyz, rad = globule(15, 4, hydrogens=True)
+    u = np.random.default_rng(1).uniform(-1.0, 1.0, len(rad))
+    g = oracle.volume_vjp(xyz, rad, 1.4, u)
+    h = 1e-5
+    for m in range(len(rad)):
+        for c in range(3):
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[m, c] += h
+            xm[m, c] -= h
+            fd = (u @ oracle.volume(xp, rad, 1.4)[0] - u @ oracle.volume(xm, rad, 1.4)[0]) / (2 * h)
+            assert abs(fd - g[m, c]) < 1e-6 * max(1.0, abs(g[m, c])), (m, c, fd, g[m, c])
+    # u = 1 gives the molecular-volume gradient
+    assert np.abs(oracle.volume_vjp(xyz, rad, 1.4, np.ones(len(rad))) - oracle.volume(xyz, rad, 1.4)[1]).max() < 1e-10
