@@ -12,8 +12,9 @@
  *     exterior simplices);
  *   - the per-atom inclusion-exclusion area of Eq. 1 with the vertex, edge and
  *     triangle terms of Eqs. 3, 4 and 6, and the derivatives of Eqs. 2, 5, 7;
- *   - the volumes of the same cells and the molecular-volume gradient
- *     (sasa_volume; the Discussion's extension to volumes);
+ *   - the volumes of the same cells, the molecular-volume gradient and the
+ *     per-atom volume VJP (sasa_volume, sasa_volume_backward; the
+ *     Discussion's extension to volumes);
  *   - the paper's sort-based extraction of unique triangles, for comparison
  *     (sasa_triangles_by_sort).
  *
@@ -148,6 +149,19 @@ int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, vo
  * compute, SASA_E_INVAL for NULL outputs.
  */
 int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream);
+
+/*
+ * Vector-Jacobian product of the per-atom volumes of the last compute:
+ *   dL_dx[m] = sum_i dL_dV[i] dV_i/dp_m   (n*3 doubles, FP64)
+ * Moving p_j moves only the face (i, j) of cell i and moving p_i moves its
+ * sphere and all its faces, so the product comes from each atom's own faces:
+ *   dL_dx[m] = sum_j F_mj [(u_m - u_j)(cbar_mj - p_m) - u_m (p_j - p_m)] / d_mj
+ * with u = dL_dV, F the face areas and cbar their centroids (first moments
+ * by inclusion-exclusion over the K-triangles and K-tetrahedra, as the areas).
+ * dL_dV = 1 gives the molecular-volume gradient of sasa_volume.  Buffers and
+ * errors as sasa_backward.
+ */
+int sasa_volume_backward(void* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream);
 
 /*
  * Sizes of the kept complex: counts[0..7] = vertices in K, edges, triangles,

@@ -29,8 +29,8 @@ SASA_FLAG_FRAMES = 4
 # every entry point of include/sasa.h
 EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
-    "sasa_volume", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export", "sasa_diagnostics", "sasa_footprint", "sasa_capacity",
-    "sasa_strerror", "sasa_last_error",
+    "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export",
+    "sasa_diagnostics", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
 )
 
 
@@ -83,6 +83,7 @@ def load():
     L.sasa_compute_forces.argtypes = [P, I64, P, P, D, D, P, P, I32, P]
     L.sasa_backward.argtypes = [P, P, P, I32, P]
     L.sasa_volume.argtypes = [P, P, P, I32, P]
+    L.sasa_volume_backward.argtypes = [P, P, P, I32, P]
     L.sasa_triangles_by_sort.argtypes = [P, P, P, I64, P, P]
     L.sasa_complex_counts.argtypes = [P, P]
     L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
@@ -96,7 +97,7 @@ def load():
     L.sasa_last_error.argtypes = [P]
     L.sasa_last_error.restype = ctypes.c_char_p
     for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
-                 "sasa_volume", "sasa_triangles_by_sort", "sasa_complex_counts",
+                 "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts",
                  "sasa_complex_export", "sasa_diagnostics"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -190,6 +191,13 @@ def sasa_volume(ctx, volume, dV_dx, mem=None, stream=None):
     mem = mem_of(*arrs) if mem is None else mem
     stream = stream_of(arrs) if stream is None else stream
     return check(load().sasa_volume(ctx, ptr(volume), ptr(dV_dx), mem, stream), ctx)
+
+
+def sasa_volume_backward(ctx, dL_dV, dL_dx, mem=None, stream=None):
+    arrs = (dL_dV, dL_dx)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_volume_backward(ctx, ptr(dL_dV), ptr(dL_dx), mem, stream), ctx)
 
 
 def sasa_triangles_by_sort(ctx):

@@ -81,3 +81,44 @@ class SASAFunction(torch.autograd.Function):
 def sasa(xyz, radii, probe=1.4, offsets=None, precision="fp64"):
     """Differentiable per-atom SASA (A^2) of one molecule, or of a batch with ``offsets``."""
     return SASAFunction.apply(xyz, radii, probe, offsets, precision)
+
+
+class VolumeFunction(torch.autograd.Function):
+    """V = VolumeFunction.apply(xyz, radii, probe, offsets) -> per-atom cell volumes (float64, A^3).
+
+    Forward computes the complex (``sasa_compute``) and the volumes of the
+    cells B_i ∩ L_i (``sasa_volume``); backward is the library's volume VJP
+    (``sasa_volume_backward``), from the faces' areas and centroids.  FP64.
+    """
+
+    @staticmethod
+    def forward(fctx, xyz, radii, probe=1.4, offsets=None):
+        if not xyz.is_cuda:
+            raise ValueError("VolumeFunction needs HIP tensors (the library has no CPU path)")
+        dev = xyz.device.index if xyz.device.index is not None else torch.cuda.current_device()
+        held = _Held(_pool.acquire(dev, "fp64"))
+        x = xyz.detach().to(torch.float64).contiguous()
+        r = radii.detach().to(torch.float64, copy=False).contiguous()
+        if offsets is None:
+            held.ctx.compute(x, r, probe, grad=False)
+        else:
+            held.ctx.compute_batch(offsets, x, r, probe, grad=False)
+        vol, _ = held.ctx.volume()
+        fctx.held = held
+        fctx.dtype = xyz.dtype
+        return vol
+
+    @staticmethod
+    def backward(fctx, grad_vol):
+        held = fctx.held
+        if held is None:
+            raise RuntimeError("VolumeFunction.backward called twice on one graph (retain_graph is not supported)")
+        g = held.ctx.volume_backward(grad_vol.detach().to(torch.float64).contiguous())
+        fctx.held = None
+        held.done()
+        return g.to(fctx.dtype), None, None, None
+
+
+def volume(xyz, radii, probe=1.4, offsets=None):
+    """Differentiable per-atom cell volumes (A^3) of one molecule, or of a batch with ``offsets``."""
+    return VolumeFunction.apply(xyz, radii, probe, offsets)

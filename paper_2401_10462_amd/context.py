@@ -74,6 +74,13 @@ class SasaContext:
         _lib.sasa_volume(self._h, vol, grad)
         return vol, grad
 
+    def volume_backward(self, dL_dV):
+        """sum_i dL_dV[i] dV_i/dx of the last compute's cell volumes (FP64)."""
+        n = dL_dV.shape[0]
+        out = _like(dL_dV, (n, 3))
+        _lib.sasa_volume_backward(self._h, _c(dL_dV), out)
+        return out
+
     def triangles_by_sort(self):
         """The kept complex's triangles and n_t by the sorted-face extraction, and its GPU time (ms)."""
         return _lib.sasa_triangles_by_sort(self._h)

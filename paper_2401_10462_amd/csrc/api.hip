@@ -447,6 +447,35 @@ int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip
   return SASA_OK;
 }
 
+int sasa_volume_backward(void* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (c->n > 0 && (!dL_dV || !dL_dx)) return fail(c, SASA_E_INVAL, "dL_dV / dL_dx must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  const double* u = dL_dV;
+  double* out = dL_dx;
+  if (mem == SASA_MEM_HOST && c->n) {
+    HIP_TRY(c, hipMemcpyAsync(c->u_d, dL_dV, (size_t)c->n * sizeof(double), hipMemcpyHostToDevice, s));
+    u = c->u_d;
+    out = c->out_d;
+  }
+  launch_volume_vjp(b, u, out, s);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == SASA_MEM_HOST && c->n) {
+    HIP_TRY(c, hipMemcpyAsync(dL_dx, out, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  } else if (!(c->flags & SASA_FLAG_ASYNC)) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return SASA_OK;
+}
+
 int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms) {
   auto* c = (Ctx*)ctx;

@@ -153,6 +153,8 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 // Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64).
 void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s);
+// out[m] = sum_i u_i dV_i/dp_m (faces' areas and first moments).
+void launch_volume_vjp(const Bufs& b, const double* u, double* out, hipStream_t s);
 
 // Unique triangles of the kept complex by sorting the faces of its
 // tetrahedra (the paper's extraction, for comparison with the stars).

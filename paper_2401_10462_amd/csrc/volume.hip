@@ -32,6 +32,17 @@
 // through its exposed part, and the cell's closed boundary turns it into
 //   dV/dp_i = - sum_j F_j (p_j - p_i) / |p_j - p_i|,
 // so every atom's gradient comes from its own faces: no gather.
+// Per-atom derivatives follow from the same flux argument: moving p_j moves
+// only the face (i, j) of cell i, with normal speed -(x - p_j).delta / d_ij,
+// and moving p_i moves its sphere and all its faces, so for weights u
+//   sum_i u_i dV_i/dp_m = sum_j F_mj [(u_m - u_j)(cbar_mj - p_m) - u_m (p_j - p_m)] / d_mj
+// with cbar the face's centroid.  Its first moment about the disk centre
+// comes from the divergence theorem in the plane with (x - c)(x - c):
+//   3 M = rho int_arcs (x - c) ds + sum_t delta_t int_t (x - c) ds,
+// where an arc's integral is rho (x_end - x_start) x n (so only the exposed
+// triple points count, each with the sign of the arc it ends or starts), and
+// each edge's integral is its chord's, 2 a_t (y_t - c), less the parts cut off
+// at its K-tetrahedra, through the same decomposition as the lengths.
 #include <hip/hip_runtime.h>
 
 #include "sasa_internal.h"
@@ -51,6 +62,7 @@ __device__ inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * 
 __device__ inline D3 cross(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 __device__ inline double len(D3 a) { return sqrt(dot(a, a)); }
 
+template <bool MOM>
 struct VolLds {
   double px[KN_CAP], py[KN_CAP], pz[KN_CAP], pw[KN_CAP];  // K-neighbours relative to p_i, weights
   unsigned tet[KT_CAP];
@@ -59,9 +71,12 @@ struct VolLds {
   double tseg[KT_CAP][3];  // its segment terms for the faces on planes a, b, c
   double rarc[KTR_CAP][2];  // exterior triangle (i,a,b): c_t 2 phi(T_x) along (i,a) and (i,b)
   double rseg[KTR_CAP][2];  // c_t delta 2 a_t on planes a and b
+  double tmom[MOM ? KT_CAP : 1][3][3];   // first-moment terms of the tetrahedra's faces on planes a, b, c
+  double rmom[MOM ? KTR_CAP : 1][2][3];  // and of the exterior triangles on planes a and b
 };
 
-__device__ inline D3 at(const VolLds& L, int k) { return {L.px[k], L.py[k], L.pz[k]}; }
+template <class LT>
+__device__ inline D3 at(const LT& L, int k) { return {L.px[k], L.py[k], L.pz[k]}; }
 
 // Dihedral fraction along the axis e between the half-planes through u and v.
 __device__ inline double dihedral_frac(D3 e, D3 u, D3 v) {
@@ -91,19 +106,23 @@ __device__ inline double delta_of(D3 aj, D3 ak, D3 y, double hj) {
   return dot(y - cj, m) / len(m);
 }
 
-__device__ inline double plane_offset(const VolLds& L, int k, double wi) {
+template <class LT>
+__device__ inline double plane_offset(const LT& L, int k, double wi) {
   const double d2 = L.px[k] * L.px[k] + L.py[k] * L.py[k] + L.pz[k] * L.pz[k];
   return (d2 + wi - L.pw[k]) / (2.0 * sqrt(d2));
 }
 
-__global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad) {
-  __shared__ VolLds L;
+// MOM = false: vol[i] and the molecular-volume gradient grad[i].
+// MOM = true: grad[i] = sum_k u_k dV_k/dp_i for the weights u (vol unused).
+template <bool MOM>
+__global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* vol, double* grad) {
+  __shared__ VolLds<MOM> L;
   const int i = blockIdx.x;
   if (i >= b.n) return;
   const int lane = threadIdx.x;
   const uint8_t vf = b.vflag[i];
   if (!(vf & VF_IN)) {
-    if (lane == 0) vol[i] = 0.0;
+    if (!MOM && lane == 0) vol[i] = 0.0;
     if (lane < 3) grad[3 * (size_t)i + lane] = 0.0;
     return;
   }
@@ -126,6 +145,7 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
     const unsigned w = L.tet[t];
     const int ks[3] = {(int)(w & 255u), (int)((w >> 8) & 255u), (int)((w >> 16) & 255u)};
     double ph[3] = {0.0, 0.0, 0.0}, sg[3] = {0.0, 0.0, 0.0};
+    D3 mo[3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     if (ks[0] < nk && ks[1] < nk && ks[2] < nk) {
       const D3 P[3] = {at(L, ks[0]), at(L, ks[1]), at(L, ks[2])};
       double r[3], h[3];
@@ -143,14 +163,28 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
         const int e = (o + 1) % 3, f = (o + 2) % 3;
         D3 y;
         if (!ortho2(P[e], P[f], r[e], r[f], y)) continue;
-        const D3 u = cross(P[e], P[f]);
-        const double zeta = dot(z - y, u) / len(u);
-        const double sz = dot(P[o], u) > 0.0 ? zeta : -zeta;
-        sg[e] += delta_of(P[e], P[f], y, h[e]) * sz;
-        sg[f] += delta_of(P[f], P[e], y, h[f]) * sz;
+        const D3 ul = cross(P[e], P[f]);
+        const double zeta = dot(z - y, ul) / len(ul);
+        const bool ahead = dot(P[o], ul) > 0.0;  // the fourth vertex's side of the line
+        const double sz = ahead ? zeta : -zeta;
+        const double de = delta_of(P[e], P[f], y, h[e]), df = delta_of(P[f], P[e], y, h[f]);
+        sg[e] += de * sz;
+        sg[f] += df * sz;
+        if (MOM) {  // the edge's chord, less its part beyond the fourth vertex's plane
+          const D3 un = ul * (1.0 / len(ul));
+          const double a = sqrt(fmax(wi - dot(y, y), 0.0));
+          const double sgn = ahead ? 1.0 : -1.0;
+          const double cut = a - sgn * zeta, mid = 0.5 * (zeta + sgn * a);
+          const D3 ce = P[e] * (h[e] / len(P[e])), cf = P[f] * (h[f] / len(P[f]));
+          const D3 pc = y + un * mid;
+          mo[e] = mo[e] + ((y - ce) * a - (pc - ce) * cut) * (de / 3.0);
+          mo[f] = mo[f] + ((y - cf) * a - (pc - cf) * cut) * (df / 3.0);
+        }
       }
     }
     for (int c = 0; c < 3; ++c) L.tphi[t][c] = ph[c], L.tseg[t][c] = sg[c];
+    if (MOM)
+      for (int c = 0; c < 3; ++c) L.tmom[t][c][0] = mo[c].x, L.tmom[t][c][1] = mo[c].y, L.tmom[t][c][2] = mo[c].z;
   }
   // exterior K-triangles (i, a, b): the arc of circle (i,a) inside B_b and of
   // (i,b) inside B_a, and the full-chord segment terms, weighted by c_t
@@ -159,6 +193,7 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
     const int ka = (int)(w & 255u), kb = (int)((w >> 8) & 255u);
     const double ct = 1.0 - 0.5 * (double)(w >> 16);
     double arc_a = 0.0, arc_b = 0.0, seg_a = 0.0, seg_b = 0.0;
+    D3 mo_a = {0.0, 0.0, 0.0}, mo_b = {0.0, 0.0, 0.0};
     if (ka < nk && kb < nk) {
       const D3 A = at(L, ka), B = at(L, kb);
       const double ra = dot(A, A) - L.pw[ka] + wi, rb = dot(B, B) - L.pw[kb] + wi;
@@ -166,16 +201,58 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
       if (ortho2(A, B, ra, rb, y)) {
         const double s = dot(y, y) - wi;
         const double half = s < 0.0 ? sqrt(-s) : 0.0;
-        const D3 u = cross(A, B);
-        const D3 x = y + u * (half / len(u));  // a triple point (either one)
+        const D3 ul = cross(A, B);
+        const D3 un = ul * (1.0 / len(ul));
+        const D3 x = y + un * half;  // a triple point (either one)
         arc_a = ct * 2.0 * dihedral_frac(A, B, x);
         arc_b = ct * 2.0 * dihedral_frac(B, A, x);
-        seg_a = ct * delta_of(A, B, y, plane_offset(L, ka, wi)) * 2.0 * half;
-        seg_b = ct * delta_of(B, A, y, plane_offset(L, kb, wi)) * 2.0 * half;
+        const double ha = plane_offset(L, ka, wi), hb = plane_offset(L, kb, wi);
+        const double da = delta_of(A, B, y, ha), db = delta_of(B, A, y, hb);
+        seg_a = ct * da * 2.0 * half;
+        seg_b = ct * db * 2.0 * half;
+        if (MOM) {
+          // the exposed triple points: both when no K-tetrahedron holds the
+          // triangle, else the one inside its tetrahedron's fourth half-space
+          bool keep_p = true, keep_m = true;
+          if ((w >> 16) == 1u) {
+            int kl = -1;
+            for (int q = 0; q < nt && kl < 0; ++q) {
+              const unsigned tq = L.tet[q];
+              const int q0 = (int)(tq & 255u), q1 = (int)((tq >> 8) & 255u), q2 = (int)((tq >> 16) & 255u);
+              const bool ha_ = q0 == ka || q1 == ka || q2 == ka, hb_ = q0 == kb || q1 == kb || q2 == kb;
+              if (ha_ && hb_) kl = q0 != ka && q0 != kb ? q0 : (q1 != ka && q1 != kb ? q1 : q2);
+            }
+            if (kl >= 0 && kl < nk) {
+              const D3 Pl = at(L, kl);
+              const double rl = dot(Pl, Pl) - L.pw[kl] + wi;
+              keep_p = 2.0 * dot(Pl, y + un * half) <= rl;
+              keep_m = !keep_p;
+            }
+          }
+          const D3 na = A * (1.0 / len(A)), nb = B * (1.0 / len(B));
+          const D3 ca = na * ha, cb = nb * hb;
+          const double rho2a = fmax(wi - ha * ha, 0.0), rho2b = fmax(wi - hb * hb, 0.0);
+          const D3 ta = B - na * dot(B, na), tb = A - nb * dot(A, nb);  // towards the other ball, in each plane
+          mo_a = (y - ca) * (ct * da * 2.0 * half / 3.0);
+          mo_b = (y - cb) * (ct * db * 2.0 * half / 3.0);
+          for (int e = 0; e < 2; ++e) {
+            if (!(e == 0 ? keep_p : keep_m)) continue;
+            const D3 xe = y + un * (e == 0 ? half : -half);
+            // an exposed arc ends (+) or starts (-) at xe, going round the normal
+            const double sa = dot(cross(na, xe - ca), ta) > 0.0 ? 1.0 : -1.0;
+            const double sb = dot(cross(nb, xe - cb), tb) > 0.0 ? 1.0 : -1.0;
+            mo_a = mo_a + cross(xe - ca, na) * (rho2a * sa / 3.0);
+            mo_b = mo_b + cross(xe - cb, nb) * (rho2b * sb / 3.0);
+          }
+        }
       }
     }
     L.rarc[t][0] = arc_a, L.rarc[t][1] = arc_b;
     L.rseg[t][0] = seg_a, L.rseg[t][1] = seg_b;
+    if (MOM) {
+      L.rmom[t][0][0] = mo_a.x, L.rmom[t][0][1] = mo_a.y, L.rmom[t][0][2] = mo_a.z;
+      L.rmom[t][1][0] = mo_b.x, L.rmom[t][1][1] = mo_b.y, L.rmom[t][1][2] = mo_b.z;
+    }
   }
   __syncthreads();
   // faces: one K-edge per lane (KN_CAP = 64), sums in a fixed order
@@ -183,15 +260,22 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
   const int k = lane;
   if (k < nk) {
     double phi = 0.0, seg = 0.0, arc = 0.0;
+    D3 mom = {0.0, 0.0, 0.0};
     for (int t = 0; t < nt; ++t) {
       const unsigned w = L.tet[t];
       const int c = (int)(w & 255u) == k ? 0 : (int)((w >> 8) & 255u) == k ? 1 : (int)((w >> 16) & 255u) == k ? 2 : -1;
-      if (c >= 0) phi += L.tphi[t][c], seg += L.tseg[t][c];
+      if (c >= 0) {
+        phi += L.tphi[t][c], seg += L.tseg[t][c];
+        if (MOM) mom = mom + D3{L.tmom[t][c][0], L.tmom[t][c][1], L.tmom[t][c][2]};
+      }
     }
     for (int t = 0; t < nr; ++t) {
       const unsigned w = L.tri[t];
       const int c = (int)(w & 255u) == k ? 0 : (int)((w >> 8) & 255u) == k ? 1 : -1;
-      if (c >= 0) arc += L.rarc[t][c], seg += L.rseg[t][c];
+      if (c >= 0) {
+        arc += L.rarc[t][c], seg += L.rseg[t][c];
+        if (MOM) mom = mom + D3{L.rmom[t][c][0], L.rmom[t][c][1], L.rmom[t][c][2]};
+      }
     }
     const D3 P = at(L, k);
     const double d = len(P);
@@ -200,7 +284,14 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
     const double theta = kTwoPi * (1.0 - phi - arc);
     const double F = 0.5 * (rho2 * theta + seg);
     hv = h * F;
-    gx = -F * P.x / d, gy = -F * P.y / d, gz = -F * P.z / d;
+    if (MOM) {
+      // F (cbar - p_i) = F c + M, c = h P / d the disk centre
+      const double ui = u[i], uj = u[b.knbr[(size_t)i * KN_CAP + k]];
+      const D3 g = (P * (F * h / d) + mom) * ((ui - uj) / d) - P * (ui * F / d);
+      gx = g.x, gy = g.y, gz = g.z;
+    } else {
+      gx = -F * P.x / d, gy = -F * P.y / d, gz = -F * P.z / d;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     hv += __shfl_xor(hv, off, 64);
@@ -209,7 +300,7 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
     gz += __shfl_xor(gz, off, 64);
   }
   if (lane == 0) {
-    vol[i] = (Ri * b.area[i] + hv) / 3.0;
+    if (!MOM) vol[i] = (Ri * b.area[i] + hv) / 3.0;
     grad[3 * (size_t)i] = gx;
     grad[3 * (size_t)i + 1] = gy;
     grad[3 * (size_t)i + 2] = gz;
@@ -219,7 +310,11 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, double* vol, double* grad
 }  // namespace
 
 void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s) {
-  if (b.n) k_volume<<<b.n, 64, 0, s>>>(b, vol, grad);
+  if (b.n) k_volume<false><<<b.n, 64, 0, s>>>(b, nullptr, vol, grad);
+}
+
+void launch_volume_vjp(const Bufs& b, const double* u, double* out, hipStream_t s) {
+  if (b.n) k_volume<true><<<b.n, 64, 0, s>>>(b, u, nullptr, out);
 }
 
 }  // namespace sasa
