@@ -349,8 +349,15 @@ def main():
         s = time.perf_counter()
         vol, _ = ctx.volume()
         tv += time.perf_counter() - s
+    uv = torch.linspace(-1.0, 1.0, n, dtype=torch.float64, device=dev)
+    ctx.volume_backward(uv)
+    tb = 0.0
+    for _ in range(kv):
+        s = time.perf_counter()
+        ctx.volume_backward(uv)
+        tb += time.perf_counter() - s
     volume = {"ms_per_call": 1e3 * tv / kv, "atoms_per_s": n * kv / tv, "calls": kv,
-              "volume_A3": float(vol.sum().item())}
+              "volume_A3": float(vol.sum().item()), "vjp_ms_per_call": 1e3 * tb / kv}
 
     # ---- the paper's sorted-face extraction of the same complex (A/B against
     # the classification the star kernel does per atom)
