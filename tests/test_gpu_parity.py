@@ -2,7 +2,7 @@
 
 Bars (per atom i, Q17-style floors so that buried atoms are not divided by 0):
   FP64 : |A - A_ref| <= 1e-9 max(A_ref, 1 A^2);  |g - g_ref| <= 1e-9 max(|g_ref|, 1 A^2/A)
-  MIXED: the same with 1e-4 (areas and gradients, spec tolerance)
+  MIXED: the same with 1e-4 (areas and gradients, the tolerance of the FP32 area terms)
   the dual complex K (edges, triangles, tetrahedra, n_tet, vertex flags) bit-exact.
 """
 import numpy as np
