@@ -201,7 +201,13 @@ int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t 
 int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
                         uint8_t* vert_flags);
 
-/* Diagnostics of the last call (fills as many bytes as given, up to the struct). */
+/*
+ * Diagnostics of the last call (fills as many bytes as given, up to the struct).
+ * The size and work counts of a compute (and sasa_complex_counts) are summed
+ * from per-atom records on the device the first time they are asked for after
+ * that compute: one small launch on the call's stream and a synchronisation,
+ * which a compute itself does not spend.
+ */
 typedef struct {
   int64_t n_atoms;
   int64_t n_mol;
@@ -216,7 +222,7 @@ typedef struct {
   /* stage times of the last call (SASA_FLAG_TIMING; HIP events on the call's stream) */
   double ms_cells;            /* weights, per-molecule cell grid, scan, scatter */
   double ms_star;             /* per-atom power-cell clipping and the star in K (fast pass) */
-  double ms_star_wide;        /* the star's pass for cells too large for the fast pass, and its counters */
+  double ms_star_wide;        /* the star's pass for cells too large for the fast pass */
   double ms_terms;            /* Eq. 1 area terms (and gradient blocks) */
   double ms_gather;           /* segmented gradient sums */
   /* algorithmic work of the last call's star kernel */
@@ -229,6 +235,13 @@ typedef struct {
   int64_t reused_cells;       /* SASA_FLAG_FRAMES: atoms whose previous-frame cell was verified and kept */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
+
+/*
+ * Error status of the last call: for a SASA_FLAG_ASYNC call, waits for its
+ * stream and returns SASA_E_CAPACITY / SASA_E_INVAL as sasa_diagnostics would,
+ * without summing the diagnostics counts; SASA_OK otherwise.
+ */
+int sasa_status(void* ctx);
 
 /*
  * Device bytes a context needs for a call of n atoms in total (all molecules of

@@ -30,7 +30,7 @@ SASA_FLAG_FRAMES = 4
 EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
     "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export",
-    "sasa_diagnostics", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
+    "sasa_diagnostics", "sasa_status", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
 )
 
 
@@ -88,6 +88,7 @@ def load():
     L.sasa_complex_counts.argtypes = [P, P]
     L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
     L.sasa_diagnostics.argtypes = [P, ctypes.POINTER(sasa_diag), I64]
+    L.sasa_status.argtypes = [P]
     L.sasa_footprint.argtypes = [I64, P]
     L.sasa_footprint.restype = ctypes.c_int
     L.sasa_capacity.argtypes = [P]
@@ -98,7 +99,7 @@ def load():
     L.sasa_last_error.restype = ctypes.c_char_p
     for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
                  "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts",
-                 "sasa_complex_export", "sasa_diagnostics"):
+                 "sasa_complex_export", "sasa_diagnostics", "sasa_status"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -234,6 +235,10 @@ def sasa_diagnostics(ctx):
     d = sasa_diag()
     check(load().sasa_diagnostics(ctx, ctypes.byref(d), ctypes.sizeof(d)), ctx)
     return {f: getattr(d, f) for f, _ in d._fields_}
+
+
+def sasa_status(ctx):
+    check(load().sasa_status(ctx), ctx)
 
 
 def sasa_footprint(n):

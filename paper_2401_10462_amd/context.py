@@ -97,6 +97,10 @@ class SasaContext:
     def diagnostics(self):
         return _lib.sasa_diagnostics(self._h)
 
+    def status(self):
+        """Raise if the last call failed (for async calls: waits for its stream)."""
+        _lib.sasa_status(self._h)
+
     @staticmethod
     def _outputs(xyz, n, grad):
         return _like(xyz, (n,)), (_like(xyz, (n, 3)) if grad else None)

@@ -37,6 +37,8 @@ struct Ctx {
   int64_t* off_d = nullptr;
   int64_t* off_h = nullptr;  // pinned
   unsigned long long* ctr_h = nullptr;  // pinned copy of the counters
+  unsigned long long* status_h = nullptr;  // pinned words the terms kernel of a compute writes (Bufs::status)
+  unsigned long long* status_d = nullptr;  // ... their device address
   // export buffers
   int64_t ex_cap_e = 0, ex_cap_t = 0, ex_cap_q = 0;
   // kept state
@@ -45,6 +47,7 @@ struct Ctx {
   int nmol = 0;
   double probe = 0;
   bool pending = false;  // an async call whose counters were not read yet
+  bool stats_due = false;  // the star records of the last compute are not summed into the counters yet
   hipStream_t last_stream = nullptr;  // stream of the last call (pending counters are read there)
   hipEvent_t ev[6] = {};  // stage boundaries (SASA_FLAG_TIMING)
   bool timed = false;     // events of the last call were recorded
@@ -150,7 +153,48 @@ bool host_inputs_ok(int64_t n, const double* xyz, const double* radii) {
   return true;
 }
 
-int read_counters(Ctx* c, hipStream_t s) {
+// Stage times of the last call (SASA_FLAG_TIMING), once its stream is done.
+void read_times(Ctx* c) {
+  if (!c->timed) return;
+  c->timed = false;
+  float ms[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < 5; ++k)
+    if (hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]) != hipSuccess) ms[k] = -1.0f;
+  c->diag.ms_cells = ms[0];
+  c->diag.ms_star = ms[1];
+  c->diag.ms_star_wide = ms[2];
+  c->diag.ms_terms = ms[3];
+  c->diag.ms_gather = ms[4];
+}
+
+int check_errors(Ctx* c, unsigned long long bad_input, unsigned long long overflow) {
+  if (bad_input) {
+    c->kept = false;
+    return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
+  }
+  if (overflow) {
+    c->kept = false;
+    return fail(c, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
+  }
+  return SASA_OK;
+}
+
+// Waits for the stream of the last call and reports its errors.  full: copies
+// all counters back (diagnostics, complex counts); otherwise only the error
+// counts that the call's terms kernel wrote to pinned host memory are read
+// (a compute with no atoms has none).
+int read_counters(Ctx* c, hipStream_t s, bool full = true) {
+  if (!full) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->pending = false;
+    const volatile unsigned long long* st = c->status_h;
+    if (c->n > 0 && st[2] != 1ull) return fail(c, SASA_E_DEVICE, "the call's status words were not written");
+    const unsigned long long bad_input = c->n > 0 ? st[0] : 0ull, overflow = c->n > 0 ? st[1] : 0ull;
+    c->diag.input_errors = (int64_t)bad_input;
+    c->diag.overflow = (int64_t)overflow;
+    read_times(c);
+    return check_errors(c, bad_input, overflow);
+  }
   HIP_TRY(c, hipMemcpyAsync(c->ctr_h, c->b.ctr, CTR_BYTES, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   c->pending = false;
@@ -168,25 +212,25 @@ int read_counters(Ctx* c, hipStream_t s) {
   c->diag.max_planes_used = (int64_t)h[ctr_slot(C_MAX_PLANES)];
   c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
   c->diag.reused_cells = (int64_t)h[ctr_slot(C_REUSED)];
-  if (c->timed) {
-    float ms[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < 5; ++k) HIP_TRY(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
-    c->diag.ms_cells = ms[0];
-    c->diag.ms_star = ms[1];
-    c->diag.ms_star_wide = ms[2];
-    c->diag.ms_terms = ms[3];
-    c->diag.ms_gather = ms[4];
-    c->timed = false;
-  }
-  if (h[ctr_slot(C_BAD_INPUT)]) {
-    c->kept = false;
-    return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
-  }
-  if (h[ctr_slot(C_OVERFLOW)]) {
-    c->kept = false;
-    return fail(c, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
-  }
-  return SASA_OK;
+  read_times(c);
+  return check_errors(c, h[ctr_slot(C_BAD_INPUT)], h[ctr_slot(C_OVERFLOW)]);
+}
+
+// The star kernel's per-atom records of the last compute, summed into the
+// counters when they are asked for (diagnostics, complex counts) rather than
+// by a launch in every call.  Capacity failures are counted by the star kernel
+// itself and were reported by the compute; only a HIP error is returned here.
+int sum_stats(Ctx* c) {
+  if (!c->stats_due) return SASA_OK;
+  c->stats_due = false;
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  HIP_TRY(c, hipSetDevice(c->device));
+  launch_stats(b, c->last_stream);
+  HIP_TRY(c, hipGetLastError());
+  const int rc = read_counters(c, c->last_stream);
+  return rc == SASA_E_DEVICE ? rc : SASA_OK;
 }
 
 int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const double* radii, double probe,
@@ -203,10 +247,11 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   if (n > 0 && (!xyz || !radii)) return fail(c, SASA_E_INVAL, "xyz / radii must not be NULL");
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->pending) {
-    int rc = read_counters(c, s);
+    int rc = read_counters(c, c->last_stream, false);
     (void)rc;
   }
   c->kept = false;
+  c->stats_due = false;  // the buffers may be reallocated below
   if (mem == SASA_MEM_HOST && n > 0 && !host_inputs_ok(n, xyz, radii))
     return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
   int rc = ensure(c, n, nmol);
@@ -238,6 +283,8 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   b.area = (mem == SASA_MEM_DEVICE && area) ? area : c->area_d;
   double* out = (mem == SASA_MEM_DEVICE && dA_dx) ? dA_dx : c->out_d;
   const bool timing = (c->flags & SASA_FLAG_TIMING) != 0;
+  b.status = c->status_d;
+  c->status_h[0] = c->status_h[1] = c->status_h[2] = 0ull;  // no kernel of this context is in flight
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (b.fac && c->fac_atoms != n) {  // hints of another system: start without
     if (n) launch_zero(b.hint_n, (size_t)n * sizeof(int), s);
@@ -260,13 +307,13 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   launch_star(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
   launch_star_wide(b, s);
-  launch_stats(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
   launch_terms(b, c->precision, dA_dx != nullptr, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[4], s));
   if (dA_dx) launch_gather(b, nullptr, out, scale, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[5], s));
   c->timed = timing;
+  c->stats_due = true;
   HIP_TRY(c, hipGetLastError());
   if (mem == SASA_MEM_HOST && n) {
     if (area) HIP_TRY(c, hipMemcpyAsync(area, b.area, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -284,7 +331,7 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
     c->pending = true;
     return SASA_OK;
   }
-  rc = read_counters(c, s);
+  rc = read_counters(c, s, false);
   c->diag.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
 }
@@ -315,11 +362,14 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->b.ctr, CTR_BYTES);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->ctr_h, CTR_BYTES);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->status_h, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->status_d, c->status_h, 0);
   if (e != hipSuccess) {
     sasa_destroy(c);
     return fail(nullptr, SASA_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
   }
   std::memset(c->ctr_h, 0, CTR_BYTES);
+  std::memset(c->status_h, 0, 4 * sizeof(unsigned long long));
   if (c->flags & SASA_FLAG_TIMING)
     for (auto& ev : c->ev)
       if (hipEventCreate(&ev) != hipSuccess) {
@@ -355,6 +405,7 @@ void sasa_destroy(void* ctx) {
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (c->ctr_h) (void)hipHostFree(c->ctr_h);
+  if (c->status_h) (void)hipHostFree(c->status_h);
   delete c;
 }
 
@@ -552,6 +603,8 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]) {
     int rc = read_counters(c, c->last_stream);
     if (rc) return rc;
   }
+  int rc = sum_stats(c);
+  if (rc) return rc;
   const unsigned long long* h = c->ctr_h;
   counts[0] = (int64_t)h[ctr_slot(C_VERT)];
   counts[1] = (int64_t)h[ctr_slot(C_EDGE)];
@@ -609,6 +662,7 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(s));
   c->timed = false;
+  c->stats_due = false;
   rc = read_counters(c, s);
   if (rc) return rc;
   if (edges && cnt[1]) HIP_TRY(c, hipMemcpy(edges, b.ex_edges, (size_t)cnt[1] * 2 * sizeof(int), hipMemcpyDeviceToHost));
@@ -624,8 +678,15 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
   if (!c || !out || size < 0) return fail(c, SASA_E_INVAL, "NULL argument");
   int rc = SASA_OK;
   if (c->pending) rc = read_counters(c, c->last_stream);
+  if (!rc) rc = sum_stats(c);
   std::memcpy(out, &c->diag, (size_t)std::min<int64_t>(size, sizeof(sasa_diag)));
   return rc;
+}
+
+int sasa_status(void* ctx) {
+  auto* c = (Ctx*)ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  return c->pending ? read_counters(c, c->last_stream, false) : SASA_OK;
 }
 
 int sasa_footprint(int64_t n, int64_t* bytes) {

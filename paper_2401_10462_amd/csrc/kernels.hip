@@ -16,7 +16,8 @@
 //               exterior classification, and a per-atom statistics record
 //               (a trajectory's calls start from the previous frame's cell)
 //   k_star_wide the atoms whose cell outgrew the fast pass, with full capacities
-//   k_stats     the statistics records folded into the counters
+//   k_stats     the statistics records folded into the counters (on demand:
+//               diagnostics and complex counts, not every call)
 //   k_terms     one wavefront per exterior atom: Eq. 1 area from the star and,
 //               on request, the gradient blocks dA_i/dp_m of Eq. 2
 //   k_gather    16 lanes per atom: segmented sum over its K-neighbours of
@@ -1004,6 +1005,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     if (lane == 0) {
       for (int q = S_TIES; q < S_COUNT; ++q) st[q] = 0;
       st[S_BAD] = 1;
+      atomicAdd(&b.ctr[ctr_slot(C_OVERFLOW)], 1ull);  // counted here: the record sums run on demand
       if (HINTS) b.hint_n[i] = 0;
       b.vflag[i] = 0;
       b.kn_cnt[i] = 0;
@@ -1345,6 +1347,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     }
     st[S_TIES] = ties;
     st[S_BAD] = (bad ? 1 : 0) | (reused ? 2 : 0);
+    if (bad) atomicAdd(&b.ctr[ctr_slot(C_OVERFLOW)], 1ull);
     st[S_VERT] = inK ? 1 : 0;
     st[S_EXTV] = ext ? 1 : 0;
     st[S_TET] = own_tet;
@@ -1389,7 +1392,8 @@ __global__ __launch_bounds__(64) void k_star_wide(Bufs b) {
 // ------------------------------------------------------------------ stats
 // Sums (maxima for the sizes) of the star kernel's per-atom records into the
 // counters: one atom per thread (a record is four int4 loads), a block folds
-// its 1,024 records and one thread per counter issues the block's atomic.
+// its 256 records and one thread per counter issues the block's atomic.  It
+// runs when the counts are asked for, after the call that wrote the records.
 constexpr int STATS_T = 256;
 
 __device__ inline int stat_counter(int q) {
@@ -1443,7 +1447,8 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
   if ((threadIdx.x & 63) == 0)
     for (int q = 0; q < NV; ++q) part[threadIdx.x >> 6][q] = v[q];
   __syncthreads();
-  if (threadIdx.x < NV && (threadIdx.x < S_COUNT || threadIdx.x >= S_KMAX)) {
+  // (capacity failures are counted by the star kernel itself)
+  if (threadIdx.x < NV && threadIdx.x != S_BAD && (threadIdx.x < S_COUNT || threadIdx.x >= S_KMAX)) {
     const int q = threadIdx.x;
     long long t = part[0][q];
     for (int w = 1; w < STATS_T / 64; ++w) t = is_max(q) ? max(t, (long long)part[w][q]) : t + part[w][q];
@@ -1653,6 +1658,13 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   __shared__ TermsLds L;
   if ((int)blockIdx.x >= b.n) return;
+  if (b.status && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the call's error counts are final here (cells and stars are done): the
+    // host reads them after its wait instead of copying the counters back
+    b.status[0] = b.ctr[ctr_slot(C_BAD_INPUT)];
+    b.status[1] = b.ctr[ctr_slot(C_OVERFLOW)];
+    b.status[2] = 1ull;
+  }
   const int i = b.sorted[blockIdx.x];  // cell order, as in k_star
   const int lane = threadIdx.x;
   const uint8_t vf = b.vflag[i];

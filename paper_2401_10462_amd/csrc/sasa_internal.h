@@ -128,6 +128,9 @@ struct Bufs {
   double* area = nullptr;
   double* rows = nullptr;    // n * ROW * 3
   unsigned long long* ctr = nullptr;
+  // pinned host words that the terms kernel of a compute fills from the
+  // counters: [0] input errors, [1] capacity failures, [2] = 1 (written)
+  unsigned long long* status = nullptr;
   // export (optional)
   int export_on = 0;
   int64_t ex_cap_e = 0, ex_cap_t = 0, ex_cap_q = 0;

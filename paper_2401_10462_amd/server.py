@@ -81,7 +81,7 @@ class _Slot:
 
     def finish(self):
         self.event.synchronize()
-        diag = self.ctx.diagnostics()  # raises on capacity / input errors of this batch
+        self.ctx.status()  # raises on capacity / input errors of this batch
         a, g = self.host_out[0].numpy(), self.host_out[1].numpy()
         out, o = [], 0
         for r in self.reqs:
