@@ -298,7 +298,7 @@ __global__ void k_scatter(Bufs b) {
 // fits), their scan and the scatter into cell order.  It replaces the ten
 // launches of the batched path for the common single-molecule call.
 constexpr int ONE_T = 1024;
-constexpr int ONE_LDS_CELLS = 8192;
+constexpr int ONE_LDS_CELLS = 32768;
 
 // PER > 0: every atom of the call stays in the registers of one thread
 // (n <= PER * ONE_T); PER == 0: the atoms are re-read from memory per phase.
@@ -317,31 +317,47 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   double rx[R], ry[R], rz[R], rr[R];
   int rc[R];
   int bad = 0;
-  auto load = [&](int i, double& x, double& y, double& z, double& Rw) {
+  // Every phase issues all of a thread's loads before its first store: the
+  // compiler cannot prove that the output arrays do not alias the inputs, so a
+  // load after a store would wait for it (one memory round trip per atom).
+  auto load = [&](int i, double& x, double& y, double& z, double& r) {
     x = b.xyz[3 * i], y = b.xyz[3 * i + 1], z = b.xyz[3 * i + 2];
-    double r = b.radii[i];
+    r = b.radii[i];
+  };
+  auto weigh = [&](int i, double& x, double& y, double& z, double& r) {  // r becomes R_i
     if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(r) && r > 0.0)) {
       ++bad;
       x = y = z = 0.0;
       r = 1.0;
     }
-    Rw = r + b.probe;
-    b.pos[i] = make_double4(x, y, z, Rw);
+    r += b.probe;
+    b.pos[i] = make_double4(x, y, z, r);
     b.mol[i] = 0;
     v[0] = fmin(v[0], x), v[1] = fmin(v[1], y), v[2] = fmin(v[2], z);
     v[3] = fmax(v[3], x), v[4] = fmax(v[4], y), v[5] = fmax(v[5], z);
-    v[6] = fmax(v[6], Rw);
+    v[6] = fmax(v[6], r);
   };
+  constexpr int U = 8;  // atoms per thread in flight together when they do not stay in registers
   if (PER > 0) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int i = t + k * ONE_T;
       if (i < b.n) load(i, rx[k], ry[k], rz[k], rr[k]);
     }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t + k * ONE_T;
+      if (i < b.n) weigh(i, rx[k], ry[k], rz[k], rr[k]);
+    }
   } else {
-    for (int i = t; i < b.n; i += ONE_T) {
-      double x, y, z, Rw;
-      load(i, x, y, z, Rw);
+    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
+      double x[U], y[U], z[U], r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) load(i0 + u * ONE_T, x[u], y[u], z[u], r[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) weigh(i0 + u * ONE_T, x[u], y[u], z[u], r[u]);
     }
   }
   for (int q = 0; q < 7; ++q) v[q] = q < 3 ? wave_min_d(v[q]) : wave_max_d(v[q]);
@@ -389,11 +405,21 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
       }
     }
   } else {
-    for (int i = t; i < b.n; i += ONE_T) {
-      const double4 p = b.pos[i];
-      const int c = cell_of(p.x, p.y, p.z);
-      b.cellid[i] = c;
-      atomicAdd(&cnt[c], 1);
+    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
+      double x[U] = {}, y[U] = {}, z[U] = {};
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) {
+          const double* q = &b.pos[i0 + u * ONE_T].x;
+          x[u] = q[0], y[u] = q[1], z[u] = q[2];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) {
+          const int c = cell_of(x[u], y[u], z[u]);
+          b.cellid[i0 + u * ONE_T] = c;
+          atomicAdd(&cnt[c], 1);
+        }
     }
   }
   __syncthreads();
@@ -413,12 +439,16 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   int run = scan_lds[t] - sum;
   for (int c = c0; c < c1; ++c) {
     const int k = cnt[c];
-    b.start[c] = run;
+    if (!in_lds) b.start[c] = run;
     cnt[c] = run;  // becomes the fill cursor of the cell
     run += k;
   }
   if (t == ONE_T - 1) b.start[cells] = scan_lds[ONE_T - 1];
   __syncthreads();
+  if (in_lds) {  // the cell starts leave LDS in coalesced stores (a thread's own cells are strided)
+    for (int c = t; c < cells; c += ONE_T) b.start[c] = lcnt[c];
+    __syncthreads();
+  }
   if (PER > 0) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -431,12 +461,24 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
       }
     }
   } else {
-    for (int i = t; i < b.n; i += ONE_T) {
-      const int c = b.cellid[i];
-      const int slot = atomicAdd(&cnt[c], 1);
-      b.sorted[slot] = i;
-      b.spos[slot] = b.pos[i];
-      b.smc[slot] = make_int2(0, c);
+    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
+      double x[U] = {}, y[U] = {}, z[U] = {}, w[U] = {};
+      int c[U] = {};
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) {
+          const double* q = &b.pos[i0 + u * ONE_T].x;
+          x[u] = q[0], y[u] = q[1], z[u] = q[2], w[u] = q[3];
+          c[u] = b.cellid[i0 + u * ONE_T];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * ONE_T < b.n) {
+          const int slot = atomicAdd(&cnt[c[u]], 1);
+          b.sorted[slot] = i0 + u * ONE_T;
+          b.spos[slot] = make_double4(x[u], y[u], z[u], w[u]);
+          b.smc[slot] = make_int2(0, c[u]);
+        }
     }
   }
 }
