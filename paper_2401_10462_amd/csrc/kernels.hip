@@ -569,14 +569,24 @@ __device__ inline Pl slot_plane(const LT& L, const Bufs& b, const double4& pi, d
   return radical_plane(pi, wi, b.pos[L.idx[q]]);
 }
 
+// Plane of id pid (a cube face or a neighbour slot) for a per-lane id: the
+// cube faces come from selects and the stored planes from an LDS read that
+// every lane makes (its index clamped into range), so that the reads of a
+// vertex solve's two planes are in flight together; only a slot past the
+// stored planes takes a branch.
 template <class LT>
 __device__ inline Pl plane_of(const LT& L, const Bufs& b, const double4& pi, double wi, unsigned pid, double half) {
-  if (pid < 6) {
+  const bool cube = pid < 6;
+  const int q = cube ? 0 : (int)pid - 6;
+  const int qs = q < LT::kPlanes ? q : LT::kPlanes - 1;
+  Pl p = {L.nx[qs], L.ny[qs], L.nz[qs], L.nb[qs]};
+  if (q >= LT::kPlanes) p = radical_plane(pi, wi, b.pos[L.idx[q]]);
+  if (cube) {
     const double s = (pid & 1) ? -1.0 : 1.0;
     const unsigned ax = pid >> 1;
-    return {ax == 0 ? s : 0.0, ax == 1 ? s : 0.0, ax == 2 ? s : 0.0, half};
+    p = {ax == 0 ? s : 0.0, ax == 1 ? s : 0.0, ax == 2 ? s : 0.0, half};
   }
-  return slot_plane(L, b, pi, wi, (int)pid - 6);
+  return p;
 }
 
 __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, double& y, double& z) {
@@ -925,9 +935,10 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     // has no plane and never ends the loop.  rho^2 is kept as an upper bound
     // (a cut never moves a vertex away from p_i) and made exact only when the
     // bound would end the loop.
+    // (k >= nfirst: the rest is in plane order.  The plane and rho^2 are the
+    // same in every lane; voting on the tests makes their branches scalar.)
     const double qn2 = qx * qx + qy * qy + qz * qz;
-    const bool far = k >= nfirst && qn2 > 0.0 && qb >= 0.0;  // the rest is in plane order
-    if (far && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) {
+    if (k >= nfirst && __ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull) {
       if (!rho_exact) {
         double r2 = 0.0;
         if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
@@ -935,7 +946,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         rho2 = wave_max(r2);
         rho_exact = true;
       }
-      if (qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) {
+      if (__ballot(qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull) {
         kstop = k;
         break;
       }
