@@ -565,7 +565,7 @@ __device__ inline Pl radical_plane(const double4& pi, double wi, const double4& 
 // stored ones.
 template <class LT>
 __device__ inline Pl slot_plane(const LT& L, const Bufs& b, const double4& pi, double wi, int q) {
-  if (q < LT::kPlanes) return {L.nx[q], L.ny[q], L.nz[q], L.nb[q]};
+  if (__builtin_expect(q < LT::kPlanes, 1)) return {L.nx[q], L.ny[q], L.nz[q], L.nb[q]};
   return radical_plane(pi, wi, b.pos[L.idx[q]]);
 }
 
@@ -768,6 +768,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     overflow = true;
     nn = NBC;
   }
+  nn = __builtin_amdgcn_readfirstlane(nn);  // wave-uniform: keeps the loops over slots scalar
   __syncthreads();
   // ---- slots in clipping order: nearest plane first, ties by atom id.  Lane
   // s holds candidates s, s + 64, s + 128 in registers, ranks each against all
@@ -938,7 +939,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     // (k >= nfirst: the rest is in plane order.  The plane and rho^2 are the
     // same in every lane; voting on the tests makes their branches scalar.)
     const double qn2 = qx * qx + qy * qy + qz * qz;
-    if (k >= nfirst && __ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull) {
+    if (__builtin_expect(k >= nfirst && __ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull, 0)) {
       if (!rho_exact) {
         double r2 = 0.0;
         if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
@@ -957,8 +958,8 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
     const int nr0 = __popcll(m0);
     const int nrem = nr0 + __popcll(m1);
-    if (nrem == 0) continue;
-    if (nrem == nv) {
+    if (__builtin_expect(nrem == 0, 1)) continue;
+    if (__builtin_expect(nrem == nv, 0)) {
       empty = true;
       kstop = k + 1;
       break;
