@@ -27,7 +27,8 @@ def lib():
     global _lib
     if _lib is None:
         path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(q) for q in _build.SOURCES):
+        if not os.path.exists(path) or os.path.getmtime(path) < max(
+                os.path.getmtime(q) for q in _build.SOURCES + _build.HEADERS):
             _build.build(force=True)
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
@@ -89,10 +90,11 @@ class OracleResult:
         if not h:
             raise ValueError("invalid oracle input")
         try:
-            c = [L.oracle_count(h, k) for k in range(10)]
+            c = [L.oracle_count(h, k) for k in range(11)]
             self.counts = dict(zip(
                 ["vertices", "edges", "triangles", "tetrahedra", "ext_vertices",
-                 "ext_edges", "ext_triangles", "jac_nnz", "near_ties", "degenerate"], c))
+                 "ext_edges", "ext_triangles", "jac_nnz", "exact_predicates", "ties_broken",
+                 "flat_candidates"], c))
             self.area = np.zeros(n)
             L.oracle_area(h, _dp(self.area))
             self.dadx = np.zeros((n, 3))

@@ -12,6 +12,8 @@
 
 #include "sasa_oracle.h"
 
+#include "predicates.h"
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -22,7 +24,6 @@
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr double kNearTie = 1e-9;  // A^2: margins below this are counted as near-degenerate
 
 // ---------------------------------------------------------------- plain vectors
 struct V3 {
@@ -203,7 +204,8 @@ struct oracle_result {
   int64_t n = 0;
   std::vector<V3> p;
   std::vector<double> R, w;
-  std::vector<std::vector<int>> nb;  // overlapping neighbours, ascending
+  std::vector<oracle_pred::Atom> atom;  // the predicates' view of the input
+  std::vector<std::vector<int>> nb;     // neighbours (overlapping or touching), ascending
   std::vector<uint8_t> vin, vext;
   std::vector<std::array<int, 2>> edges;
   std::vector<uint8_t> eext;
@@ -212,31 +214,27 @@ struct oracle_result {
   std::vector<Tet> tets;
   std::vector<double> area;
   std::vector<std::map<int, V3>> jac;  // jac[i][m] = dA_i/dp_m
-  int64_t near_ties = 0, degenerate = 0;
+  oracle_pred::Stats st;               // predicates decided exactly / by the perturbation
+  int64_t flat = 0;                    // candidate simplices with coplanar / collinear centres
 
   bool ov(int i, int j) const { return std::binary_search(nb[i].begin(), nb[i].end(), j); }
-  // g_m(x) = pi_m(x) - pi_i(x) for x given relative to p_i; >= 0 means x is
-  // not cut away from L_i by atom m.
-  double gap(int i, int m, V3 xr) const {
-    const V3 a = sub(p[m], p[i]);
-    return nrm2(a) - w[m] + w[i] - 2.0 * dot(a, xr);
-  }
-  void tie(double margin) {
-    if (std::fabs(margin) < kNearTie) ++near_ties;
-  }
 };
 
 namespace {
 
+// Atoms j that can cut L_i cap B_i: for balls that are apart, the radical plane
+// separates them, so pi_i < pi_j everywhere in B_i.  The test is widened by a
+// relative 1e-9 so that touching balls (whose perturbed weights may overlap)
+// are always listed; a listed ball that is apart changes no decision, since
+// every decision about a point inside B_i finds it on the far side of that
+// ball's plane.
 void neighbours(oracle_result& r) {
-  // Only balls that overlap can cut L_i cap B_i: for disjoint balls the radical
-  // plane separates them, so pi_i < pi_j everywhere in B_i.
   const int n = (int)r.n;
   r.nb.assign(n, {});
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) {
       const double s = r.R[i] + r.R[j];
-      if (nrm2(sub(r.p[j], r.p[i])) < s * s) {
+      if (nrm2(sub(r.p[j], r.p[i])) <= s * s * (1.0 + 1e-9)) {
         r.nb[i].push_back(j);
         r.nb[j].push_back(i);
       }
@@ -244,15 +242,28 @@ void neighbours(oracle_result& r) {
   for (auto& v : r.nb) std::sort(v.begin(), v.end());
 }
 
-// Tetrahedron (i,j,k,l) is in K iff its orthocentre z (the point of equal power
-// to all four) is a vertex of the Laguerre diagram inside the balls: pi_i(z) <= 0
-// and pi_m(z) >= pi_i(z) for every other atom m.  An atom m that violates the
-// second condition while pi_i(z) <= 0 has z inside B_m and so overlaps B_i;
-// checking the neighbours of i is therefore the whole test.
+// The alpha = 0 dual complex K (Steps 1-2): sigma is in K iff the Laguerre
+// face shared by its atoms' cells meets their balls.  That face lies in an
+// affine space whose point y_sigma closest to the centres is the simplex's
+// orthocentre.  Either y_sigma itself belongs to the face and lies inside the
+// balls (sigma is "unattached" and of size pi(y_sigma) <= 0), or the face meets
+// the balls elsewhere and then it meets them where it ends on a face one
+// dimension lower, i.e. sigma is a face of a higher simplex of K.  So
+// tetrahedra are decided first, then triangles, edges and vertices.  All
+// signs are exact and symbolically perturbed (predicates.h), so the complex
+// is that of weights moved by an infinitesimal, index-ordered amount: one
+// consistent complex also for co-spherical inputs.
+//
+// An atom m that would cut y_sigma (pi_m(y) < pi_i(y)) while y is inside B_i
+// overlaps B_i, so testing the neighbours of i is the whole emptiness test.
+
+// Tetrahedron (i,j,k,l) is in K iff its orthocentre is inside the balls and no
+// other atom has lower power there.
 void tetrahedra(oracle_result& r) {
   const int n = (int)r.n;
   for (int i = 0; i < n; ++i) {
     const auto& N = r.nb[i];
+    const auto& A = r.atom;
     for (size_t a = 0; a < N.size(); ++a) {
       const int j = N[a];
       if (j < i) continue;
@@ -262,27 +273,15 @@ void tetrahedra(oracle_result& r) {
         for (size_t c = b + 1; c < N.size(); ++c) {
           const int l = N[c];
           if (!r.ov(j, l) || !r.ov(k, l)) continue;
-          // Solve 2 a_q . z = |a_q|^2 - w_q + w_i for q = j, k, l (z relative to p_i).
-          const V3 aj = sub(r.p[j], r.p[i]), ak = sub(r.p[k], r.p[i]), al = sub(r.p[l], r.p[i]);
-          const double bj = nrm2(aj) - r.w[j] + r.w[i];
-          const double bk = nrm2(ak) - r.w[k] + r.w[i];
-          const double bl = nrm2(al) - r.w[l] + r.w[i];
-          const V3 ckl = crs(ak, al), clj = crs(al, aj), cjk = crs(aj, ak);
-          const double det = 2.0 * dot(aj, ckl);
-          if (std::fabs(det) < 1e-12) {
-            ++r.degenerate;
+          if (oracle_pred::orient(A[i], A[j], A[k], A[l], r.st) == 0) {
+            ++r.flat;
             continue;
           }
-          const V3 z = scl(add(add(scl(ckl, bj), scl(clj, bk)), scl(cjk, bl)), 1.0 / det);
-          const double pz = nrm2(z) - r.w[i];
-          r.tie(pz);
-          if (pz > 0) continue;
+          if (oracle_pred::tet_size(A[i], A[j], A[k], A[l], r.st) > 0) continue;
           bool empty = true;
           for (int m : N) {
             if (m == j || m == k || m == l) continue;
-            const double g = r.gap(i, m, z);
-            r.tie(g);
-            if (g < 0) {
+            if (oracle_pred::tet_side(A[i], A[j], A[k], A[l], A[m], r.st) < 0) {
               empty = false;
               break;
             }
@@ -295,14 +294,20 @@ void tetrahedra(oracle_result& r) {
   std::sort(r.tets.begin(), r.tets.end());
 }
 
-// Triangle (i,j,k) is in K iff the Laguerre edge shared by L_i, L_j, L_k meets
-// the balls.  That edge lies on the line of equal power y + s n^ (y in the plane
-// of the centres); on it pi_i = s_t + s^2 with s_t = pi_i(y), so the ball part
-// is |s| <= sqrt(-s_t), and each other neighbour m keeps the half-line
-// g_m(y + s n^) >= 0.  The triangle is in K iff the intersection of these
-// intervals is not empty.
+// Triangle (i,j,k) is in K iff it is a face of a K-tetrahedron, or the point
+// of its Laguerre edge's line in the plane of the centres lies on the edge
+// (no other atom has lower power there) and inside the balls.
 void triangles(oracle_result& r) {
   const int n = (int)r.n;
+  std::vector<Tri> faces;
+  for (const auto& T : r.tets) {
+    faces.push_back({T[1], T[2], T[3]});
+    faces.push_back({T[0], T[2], T[3]});
+    faces.push_back({T[0], T[1], T[3]});
+    faces.push_back({T[0], T[1], T[2]});
+  }
+  std::sort(faces.begin(), faces.end());
+  const auto& A = r.atom;
   for (int i = 0; i < n; ++i) {
     const auto& N = r.nb[i];
     for (size_t a = 0; a < N.size(); ++a) {
@@ -311,51 +316,34 @@ void triangles(oracle_result& r) {
       for (size_t b = a + 1; b < N.size(); ++b) {
         const int k = N[b];
         if (!r.ov(j, k)) continue;
-        const V3 aj = sub(r.p[j], r.p[i]), ak = sub(r.p[k], r.p[i]);
-        const double bj = nrm2(aj) - r.w[j] + r.w[i];
-        const double bk = nrm2(ak) - r.w[k] + r.w[i];
-        const double g11 = 2 * dot(aj, aj), g12 = 2 * dot(aj, ak), g22 = 2 * dot(ak, ak);
-        const double det = g11 * g22 - g12 * g12;
-        if (std::fabs(det) < 1e-12 * g11 * g22) {
-          ++r.degenerate;
+        const Tri t = {i, j, k};
+        if (std::binary_search(faces.begin(), faces.end(), t)) {
+          r.tris.push_back(t);
           continue;
         }
-        const double al = (bj * g22 - bk * g12) / det, be = (g11 * bk - g12 * bj) / det;
-        const V3 y = add(scl(aj, al), scl(ak, be));
-        const double st = nrm2(y) - r.w[i];
-        r.tie(st);
-        if (st > 0) continue;
-        V3 nn = crs(aj, ak);
-        nn = scl(nn, 1.0 / std::sqrt(nrm2(nn)));
-        double lo = -std::sqrt(-st), hi = std::sqrt(-st);
+        if (oracle_pred::collinear(A[i], A[j], A[k], r.st)) {
+          ++r.flat;
+          continue;
+        }
+        if (oracle_pred::tri_size(A[i], A[j], A[k], r.st) > 0) continue;
+        bool on_edge = true;
         for (int m : N) {
           if (m == j || m == k) continue;
-          // g_m(y + s n) = g_m(y) - 2 (a_m . n) s >= 0
-          const V3 am = sub(r.p[m], r.p[i]);
-          const double g0 = r.gap(i, m, y);
-          const double g1 = -2.0 * dot(am, nn);
-          if (g1 == 0.0) {
-            if (g0 < 0) lo = 1, hi = 0;
-            continue;
+          if (oracle_pred::tri_side(A[i], A[j], A[k], A[m], r.st) < 0) {
+            on_edge = false;
+            break;
           }
-          const double root = -g0 / g1;
-          if (g1 > 0) lo = std::max(lo, root);
-          else hi = std::min(hi, root);
-          if (lo > hi) break;
         }
-        r.tie(hi - lo);
-        if (lo <= hi) r.tris.push_back({i, j, k});
+        if (on_edge) r.tris.push_back(t);
       }
     }
   }
   std::sort(r.tris.begin(), r.tris.end());
 }
 
-// Edge (i,j) is in K iff the Laguerre facet shared by L_i and L_j meets the
-// balls: the disk cut from B_i by the radical plane, intersected with the
-// facet, is not empty.  Both are convex, so either the facet boundary crosses
-// the disk -- then a triangle (i,j,k) of K exists -- or the disk centre y_e lies
-// in the facet, i.e. in L_i, and the disk is real (pi_i(y_e) <= 0).
+// Edge (i,j) is in K iff it lies on a K-triangle, or the centre of the disk
+// where the radical plane cuts the balls lies in the Laguerre facet of i and j
+// and inside the balls.
 void edges(oracle_result& r) {
   const int n = (int)r.n;
   std::vector<std::vector<int>> has_tri(n);  // j in has_tri[i] if (i,j) is on a K-triangle
@@ -368,6 +356,7 @@ void edges(oracle_result& r) {
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
   }
+  const auto& A = r.atom;
   for (int i = 0; i < n; ++i) {
     for (int j : r.nb[i]) {
       if (j < i) continue;
@@ -375,18 +364,15 @@ void edges(oracle_result& r) {
         r.edges.push_back({i, j});
         continue;
       }
-      const V3 aj = sub(r.p[j], r.p[i]);
-      const double bj = nrm2(aj) - r.w[j] + r.w[i];
-      const V3 ye = scl(aj, bj / (2.0 * nrm2(aj)));
-      const double se = nrm2(ye) - r.w[i];
-      r.tie(se);
-      if (se > 0) continue;
+      if (r.p[i].x == r.p[j].x && r.p[i].y == r.p[j].y && r.p[i].z == r.p[j].z) {
+        ++r.flat;  // one centre, two radii: the smaller ball has no cell
+        continue;
+      }
+      if (oracle_pred::edge_size(A[i], A[j], r.st) > 0) continue;
       bool inside = true;
       for (int m : r.nb[i]) {
         if (m == j) continue;
-        const double g = r.gap(i, m, ye);
-        r.tie(g);
-        if (g < 0) {
+        if (oracle_pred::edge_side(A[i], A[j], A[m], r.st) < 0) {
           inside = false;
           break;
         }
@@ -408,9 +394,7 @@ void vertices(oracle_result& r) {
     if (r.vin[i]) continue;
     bool inside = true;
     for (int m : r.nb[i]) {
-      const double g = r.gap(i, m, V3{0, 0, 0});
-      r.tie(g);
-      if (g < 0) {
+      if (oracle_pred::vertex_side(r.atom[i], r.atom[m], r.st) < 0) {
         inside = false;
         break;
       }
@@ -569,12 +553,24 @@ oracle_result* oracle_run(int64_t n, const double* xyz, const double* radii, dou
   r->p.resize(n);
   r->R.resize(n);
   r->w.resize(n);
+  r->atom.resize(n);
   for (int64_t i = 0; i < n; ++i) {
     r->p[i] = load(xyz + 3 * i);
     r->R[i] = radii[i] + probe;  // probe-inflated sphere
     r->w[i] = r->R[i] * r->R[i];  // weight d_i = (r_i + probe)^2
+    r->atom[i] = {r->p[i].x, r->p[i].y, r->p[i].z, r->R[i], (int)i};
   }
   neighbours(*r);
+  // Two balls with one centre and one radius have the same cell: the complex
+  // (and each atom's share of the area) is undefined, so such input is refused.
+  // With different radii the smaller ball has no cell and is hidden.
+  for (int64_t i = 0; i < n; ++i)
+    for (int j : r->nb[i])
+      if (j > i && r->p[i].x == r->p[j].x && r->p[i].y == r->p[j].y && r->p[i].z == r->p[j].z &&
+          r->R[i] == r->R[j]) {
+        delete r;
+        return nullptr;
+      }
   tetrahedra(*r);
   triangles(*r);
   edges(*r);
@@ -604,8 +600,9 @@ int64_t oracle_count(const oracle_result* r, int what) {
       for (const auto& row : r->jac) c += (int64_t)row.size();
       return c;
     }
-    case 8: return r->near_ties;
-    case 9: return r->degenerate;
+    case 8: return r->st.exact;
+    case 9: return r->st.sos;
+    case 10: return r->flat;
   }
   return -1;
 }

@@ -12,7 +12,10 @@
  *   - the alpha = 0 dual complex K of the weighted Delaunay tetrahedrization,
  *     decided simplex by simplex from its definition: the restricted
  *     Laguerre-intersection cells L_i cap B_i of the simplex's atoms share a
- *     point                                          (Steps 1-2, Laguerre cell)
+ *     point                                          (Steps 1-2, Laguerre cell),
+ *     by exact predicates with ties broken by a symbolic perturbation of the
+ *     weights (predicates.h), so that co-spherical inputs get one consistent
+ *     complex
  *   - the interior / exterior classification of K           (GPU section,
  *     "Extraction of exterior simplices")
  *   - per-atom SASA by the inclusion-exclusion sum, Eq. 1, with the vertex,
@@ -35,15 +38,18 @@ extern "C" {
 typedef struct oracle_result oracle_result;
 
 /* Run the whole reference on n atoms (xyz: n*3 row-major, radii: n van der
- * Waals radii > 0, probe >= 0).  Returns NULL on invalid input. */
+ * Waals radii > 0, probe >= 0).  Returns NULL on invalid input, which
+ * includes two atoms with the same centre and the same radius. */
 oracle_result* oracle_run(int64_t n, const double* xyz, const double* radii, double probe);
 void oracle_free(oracle_result* r);
 
 /* Counts.  what: 0 = vertices in K, 1 = edges in K, 2 = triangles in K,
  * 3 = tetrahedra in K, 4 = exterior vertices, 5 = exterior edges,
  * 6 = exterior triangles, 7 = non-zero (atom, atom) blocks of the Jacobian,
- * 8 = near-degenerate predicate decisions (|margin| < 1e-9 A^2),
- * 9 = degenerate (coplanar / collinear) candidate simplices skipped. */
+ * 8 = predicates the FP64 filter left to exact arithmetic,
+ * 9 = exact ties decided by the symbolic perturbation of the weights,
+ * 10 = candidate simplices with coplanar / collinear / coincident centres
+ * (never in K) skipped. */
 int64_t oracle_count(const oracle_result* r, int what);
 
 /* Per-atom SASA A_i (n values). */

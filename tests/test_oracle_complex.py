@@ -27,7 +27,7 @@ def _sets(r):
 def test_complex_matches_qhull_random(n, seed):
     xyz, rad = random_cluster(n, seed)
     r = oracle.run(xyz, rad, 1.4)
-    assert r.counts["near_ties"] == 0
+    assert r.counts["ties_broken"] == 0  # general position: no exact tie
     K1, K2, K3 = alpha0_complex(xyz, rad, 1.4)
     E, T, Q = _sets(r)
     assert Q == K3
