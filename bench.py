@@ -403,9 +403,11 @@ def main():
         torch.cuda.synchronize()
         eb = time.perf_counter() - tb
         # the first molecule of the batch equals the plain result (rotated gradient aside)
+        bd = ctx.diagnostics()
         batched = {"molecules": args.batch, "atoms": n * args.batch, "steps": kb,
                    "atoms_per_s": n * args.batch * kb / eb, "ms_per_step": 1e3 * eb / kb,
-                   "speedup_vs_plain": (n * args.batch * kb / eb) / value}
+                   "speedup_vs_plain": (n * args.batch * kb / eb) / value,
+                   "second_pass_atoms": bd["second_pass_atoms"], "exact_side_tests": bd["near_ties"]}
 
     # ---- the same plain loop in the other precision
     other = "fp64" if args.precision == "mixed" else "mixed"
@@ -453,7 +455,8 @@ def main():
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,
         "diagnostics": {k: diag[k] for k in ("max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
                                              "overflow", "plane_tests", "new_vertices", "candidates",
-                                             "planes_used", "max_planes_used", "atoms_over_64_planes")},
+                                             "planes_used", "max_planes_used", "atoms_over_64_planes",
+                                             "second_pass_atoms")},
         "sasa_total": float(area.sum().item()),
     }
     print(json.dumps(out))

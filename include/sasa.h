@@ -44,7 +44,8 @@ extern "C" {
 
 enum {
   SASA_OK = 0,
-  SASA_E_INVAL = -1,    /* bad argument: n < 0, NaN/Inf coordinate, radius <= 0, probe < 0, NULL pointer */
+  SASA_E_INVAL = -1,    /* bad argument: n < 0, NaN/Inf coordinate, radius <= 0, probe < 0, NULL pointer,
+                           two atoms of one molecule with the same centre and the same radius */
   SASA_E_NOMEM = -2,    /* device allocation failed */
   SASA_E_DEVICE = -3,   /* HIP runtime error; the context should be destroyed */
   SASA_E_STATE = -4,    /* backward / export without a preceding compute on this context */
@@ -213,16 +214,16 @@ typedef struct {
   int64_t n_mol;
   int64_t max_neighbours;     /* largest overlapping-neighbour count of any atom */
   int64_t max_cell_vertices;  /* largest polytope size met while clipping */
-  int64_t near_ties;          /* decisions with |margin| < 1e-9 A^2 (topology may then be ambiguous) */
+  int64_t near_ties;          /* clipping side tests within their FP64 rounding bound, decided exactly */
   int64_t lost_pairs;         /* K-edges seen from one side only (near-degenerate inputs) */
   int64_t capacity_retries;   /* star storage regrown and recomputed */
-  int64_t input_errors;       /* NaN/Inf coordinates or radii <= 0 seen by the device */
+  int64_t input_errors;       /* NaN/Inf coordinates, radii <= 0 or equal coincident atoms seen by the device */
   int64_t overflow;           /* atoms beyond the kernels' neighbour / vertex capacity */
   double ms_total;            /* wall time of the last synchronous call */
   /* stage times of the last call (SASA_FLAG_TIMING; HIP events on the call's stream) */
   double ms_cells;            /* weights, per-molecule cell grid, scan, scatter */
   double ms_star;             /* per-atom power-cell clipping and the star in K (fast pass) */
-  double ms_star_wide;        /* the star's pass for cells too large for the fast pass */
+  double ms_star_wide;        /* the star's second pass (large cells; exact side tests) */
   double ms_terms;            /* Eq. 1 area terms (and gradient blocks) */
   double ms_gather;           /* segmented gradient sums */
   /* algorithmic work of the last call's star kernel */
@@ -233,6 +234,8 @@ typedef struct {
   int64_t max_planes_used;    /* ... largest for one atom */
   int64_t atoms_over_64_planes; /* atoms whose clipping visited more than 64 planes */
   int64_t reused_cells;       /* SASA_FLAG_FRAMES: atoms whose previous-frame cell was verified and kept */
+  int64_t second_pass_atoms;  /* atoms the fast star pass left to the second pass (cells past 64
+                                 vertices, or a side test within its rounding bound) */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

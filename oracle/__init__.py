@@ -138,6 +138,27 @@ def run(xyz, radii, probe=1.4):
     return OracleResult(xyz, radii, probe)
 
 
+def _run_job(job):
+    return OracleResult(*job)
+
+
+def run_many(jobs, workers=None):
+    """Run the oracle on many molecules [(xyz, radii, probe), ...] in worker
+    processes (started fresh, not forked, so a caller that holds a GPU context
+    passes none of it on); results in job order."""
+    import concurrent.futures
+    import multiprocessing
+
+    jobs = list(jobs)
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1, len(jobs))
+    if workers <= 1 or len(jobs) <= 1:
+        return [OracleResult(*j) for j in jobs]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        return list(ex.map(_run_job, jobs))
+
+
 def solid_angle(pi, pj, pk, pl):
     """Normalised solid angle at pi of tetrahedron (pi, pj, pk, pl)."""
     return lib().oracle_solid_angle(*[_dp(_v3(p)) for p in (pi, pj, pk, pl)])

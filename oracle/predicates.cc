@@ -2,10 +2,8 @@
 // INFRASTRUCTURE ONLY; see predicates.h for what is decided and why).
 //
 // Two number types evaluate the same polynomial expressions:
-//   Flt    an FP64 value with the same expression evaluated on absolute
-//          values; after k rounded operations |value - exact| <= k u * mag,
-//          so a value larger than 1e-12 * mag (far above any k used here)
-//          has the exact sign;
+//   Flt    an FP64 value with a running bound on its rounding error; a value
+//          larger than twice its bound has the exact sign;
 //   Exact  sign * magnitude * 2^exp with an arbitrary-precision integer
 //          magnitude: every double is such a number, and sums and products
 //          of them are computed without rounding.
@@ -21,19 +19,33 @@ namespace oracle_pred {
 namespace {
 
 // ---------------------------------------------------------------- Flt
+// A running error bound: the inputs (doubles) are exact, and every rounded
+// operation adds u |result| to the propagated bound (Wilkinson's running
+// error analysis), so |v - exact| <= e up to the rounding of e itself.
+constexpr double kU = 1.1102230246251565e-16;  // 2^-53
 struct Flt {
-  double v = 0.0, m = 0.0;
+  double v = 0.0, e = 0.0;
   Flt() = default;
-  explicit Flt(double d) : v(d), m(std::fabs(d)) {}
-  Flt(double v_, double m_) : v(v_), m(m_) {}
+  explicit Flt(double d) : v(d), e(0.0) {}
+  Flt(double v_, double e_) : v(v_), e(e_) {}
 };
-inline Flt operator+(const Flt& a, const Flt& b) { return {a.v + b.v, a.m + b.m}; }
-inline Flt operator-(const Flt& a, const Flt& b) { return {a.v - b.v, a.m + b.m}; }
-inline Flt operator*(const Flt& a, const Flt& b) { return {a.v * b.v, a.m * b.m}; }
-// Sign of the exact value if the bound decides it, else 2.
+inline Flt operator+(const Flt& a, const Flt& b) {
+  const double v = a.v + b.v;
+  return {v, a.e + b.e + kU * std::fabs(v)};
+}
+inline Flt operator-(const Flt& a, const Flt& b) {
+  const double v = a.v - b.v;
+  return {v, a.e + b.e + kU * std::fabs(v)};
+}
+inline Flt operator*(const Flt& a, const Flt& b) {
+  const double v = a.v * b.v;
+  return {v, std::fabs(a.v) * b.e + std::fabs(b.v) * a.e + a.e * b.e + kU * std::fabs(v)};
+}
+// Sign of the exact value if the bound decides it (with a factor 2 for the
+// rounding of the bound), else 2.
 inline int certain_sign(const Flt& f) {
-  if (!std::isfinite(f.v) || !std::isfinite(f.m)) return 2;
-  if (std::fabs(f.v) > 1e-12 * f.m + 1e-290) return f.v > 0 ? 1 : -1;
+  if (!std::isfinite(f.v) || !std::isfinite(f.e)) return 2;
+  if (std::fabs(f.v) > 2.0 * f.e + 1e-290) return f.v > 0 ? 1 : -1;
   return 2;
 }
 
@@ -251,6 +263,7 @@ struct TetP {
   Rel<N> j, k, l;
   V<N> cj, ck, cl, U;
   N D, wi;
+  TetP() = default;
   TetP(const Atom& I, const Atom& J, const Atom& K, const Atom& L) {
     j = rel<N>(I, J), k = rel<N>(I, K), l = rel<N>(I, L);
     cj = vcrs(k.a, l.a), ck = vcrs(l.a, j.a), cl = vcrs(j.a, k.a);
@@ -272,6 +285,7 @@ struct TriP {
   Rel<N> j, k;
   V<N> n, ej, ek, U;
   N N2, wi;
+  TriP() = default;
   TriP(const Atom& I, const Atom& J, const Atom& K) {
     j = rel<N>(I, J), k = rel<N>(I, K);
     n = vcrs(j.a, k.a);
@@ -451,6 +465,97 @@ int vertex_side(const Atom& I, const Atom& M, Stats& st) {
 
 int exact_sign_test(double a, double b, double c, double d, double e) {
   return sgn(Exact(a) + Exact(b) * Exact(c) - Exact(d) * Exact(e));
+}
+
+struct BaseFlt {
+  std::vector<Rel<Flt>> rel;  // neighbour q relative to atom i
+};
+struct TetFlt {
+  TetP<Flt> p;
+};
+struct TriFlt {
+  TriP<Flt> p;
+};
+struct EdgeFlt {
+  EdgeP<Flt> p;
+};
+
+Base::Base(const Atom* atoms, int i, const int* nb, int nnb, Stats& st)
+    : atoms_(atoms), i_(i), nb_(nb), st_(st), f_(new BaseFlt) {
+  f_->rel.reserve(nnb);
+  for (int q = 0; q < nnb; ++q) f_->rel.push_back(rel<Flt>(atoms[i], atoms[nb[q]]));
+}
+Base::~Base() { delete f_; }
+
+// The simplex polynomials from the cached relative data (the same operations
+// as TetP / TriP / EdgeP on the atoms, in the same order).
+template <class N>
+TetP<N> tet_from(const Rel<N>& j, const Rel<N>& k, const Rel<N>& l, const N& wi) {
+  TetP<N> t;
+  t.j = j, t.k = k, t.l = l;
+  t.cj = vcrs(k.a, l.a), t.ck = vcrs(l.a, j.a), t.cl = vcrs(j.a, k.a);
+  t.D = vdot(j.a, t.cj);
+  t.U = vadd(vadd(vscl(t.cj, j.b), vscl(t.ck, k.b)), vscl(t.cl, l.b));
+  t.wi = wi;
+  return t;
+}
+template <class N>
+TriP<N> tri_from(const Rel<N>& j, const Rel<N>& k, const N& wi) {
+  TriP<N> t;
+  t.j = j, t.k = k;
+  t.n = vcrs(j.a, k.a);
+  t.N2 = vdot(t.n, t.n);
+  t.ej = vcrs(k.a, t.n), t.ek = vcrs(t.n, j.a);
+  t.U = vadd(vscl(t.ej, j.b), vscl(t.ek, k.b));
+  t.wi = wi;
+  return t;
+}
+
+TetTest::TetTest(Base& b, int j, int k, int l) : b_(b), j_(j), k_(k), l_(l) {
+  static_assert(sizeof(TetFlt) <= sizeof(buf_), "buffer");
+  const auto& R = b.f_->rel;
+  f_ = new (buf_) TetFlt{tet_from(R[j], R[k], R[l], weight<Flt>(b.atom(-1)))};
+  const int s = certain_sign(f_->p.D);
+  sd_ = (s != 2) ? s : oracle_pred::orient(b.atom(-1), b.atom(j), b.atom(k), b.atom(l), b.st_);
+}
+TetTest::~TetTest() { f_->~TetFlt(); }
+int TetTest::size() {
+  const int s = certain_sign(f_->p.size());
+  return s != 2 ? s : tet_size(b_.atom(-1), b_.atom(j_), b_.atom(k_), b_.atom(l_), b_.st_);
+}
+int TetTest::side(int m) {
+  const int s = certain_sign(f_->p.side(b_.f_->rel[m]));
+  return s != 2 ? s * sd_ : tet_side(b_.atom(-1), b_.atom(j_), b_.atom(k_), b_.atom(l_), b_.atom(m), b_.st_);
+}
+
+TriTest::TriTest(Base& b, int j, int k) : b_(b), j_(j), k_(k) {
+  static_assert(sizeof(TriFlt) <= sizeof(buf_), "buffer");
+  const auto& R = b.f_->rel;
+  f_ = new (buf_) TriFlt{tri_from(R[j], R[k], weight<Flt>(b.atom(-1)))};
+}
+TriTest::~TriTest() { f_->~TriFlt(); }
+int TriTest::size() {
+  const int s = certain_sign(f_->p.size());
+  return s != 2 ? s : tri_size(b_.atom(-1), b_.atom(j_), b_.atom(k_), b_.st_);
+}
+int TriTest::side(int m) {
+  const int s = certain_sign(f_->p.side(b_.f_->rel[m]));
+  return s != 2 ? s : tri_side(b_.atom(-1), b_.atom(j_), b_.atom(k_), b_.atom(m), b_.st_);
+}
+
+EdgeTest::EdgeTest(Base& b, int j) : b_(b), j_(j) {
+  static_assert(sizeof(EdgeFlt) <= sizeof(buf_), "buffer");
+  EdgeP<Flt> e(b.atom(-1), b.atom(j));
+  f_ = new (buf_) EdgeFlt{e};
+}
+EdgeTest::~EdgeTest() { f_->~EdgeFlt(); }
+int EdgeTest::size() {
+  const int s = certain_sign(f_->p.size());
+  return s != 2 ? s : edge_size(b_.atom(-1), b_.atom(j_), b_.st_);
+}
+int EdgeTest::side(int m) {
+  const int s = certain_sign(f_->p.side(b_.f_->rel[m]));
+  return s != 2 ? s : edge_side(b_.atom(-1), b_.atom(j_), b_.atom(m), b_.st_);
 }
 
 }  // namespace oracle_pred

@@ -33,6 +33,8 @@
 #define SASA_ORACLE_PREDICATES_H
 #include <stdint.h>
 
+#include <new>
+
 namespace oracle_pred {
 
 struct Atom {
@@ -68,6 +70,64 @@ int vertex_side(const Atom& i, const Atom& m, Stats& st);
 // Exact sign of a + b*c - d*e (the building block is exercised on its own by
 // the tests of the exact arithmetic).
 int exact_sign_test(double a, double b, double c, double d, double e);
+
+// The same decisions with the FP64 data of atom i's neighbours and of each
+// simplex built once and reused for every tested atom m (the exact path,
+// rare, rebuilds what it needs).  Simplices and tested atoms are given as
+// positions in the neighbour list of the Base.
+struct BaseFlt;
+struct TetFlt;
+struct TriFlt;
+struct EdgeFlt;
+class Base {
+ public:
+  Base(const Atom* atoms, int i, const int* nb, int nnb, Stats& st);
+  ~Base();
+  const Atom& atom(int q) const { return q < 0 ? atoms_[i_] : atoms_[nb_[q]]; }
+  const Atom* atoms_;
+  int i_;
+  const int* nb_;
+  Stats& st_;
+  BaseFlt* f_;
+};
+class TetTest {
+ public:
+  TetTest(Base& b, int j, int k, int l);  // positions in b's neighbour list
+  ~TetTest();
+  int orient() const { return sd_; }  // exact sign of the orientation (0: flat)
+  int size();                         // as tet_size
+  int side(int m);                    // as tet_side (m a position in the list)
+ private:
+  Base& b_;
+  int j_, k_, l_;
+  TetFlt* f_;
+  int sd_;
+  alignas(double) unsigned char buf_[512];  // holds *f_
+};
+class TriTest {
+ public:
+  TriTest(Base& b, int j, int k);
+  ~TriTest();
+  int size();
+  int side(int m);
+ private:
+  Base& b_;
+  int j_, k_;
+  TriFlt* f_;
+  alignas(double) unsigned char buf_[512];
+};
+class EdgeTest {
+ public:
+  EdgeTest(Base& b, int j);
+  ~EdgeTest();
+  int size();
+  int side(int m);
+ private:
+  Base& b_;
+  int j_;
+  EdgeFlt* f_;
+  alignas(double) unsigned char buf_[256];
+};
 
 }  // namespace oracle_pred
 #endif

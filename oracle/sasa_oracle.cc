@@ -86,7 +86,6 @@ inline D dsqrt(const D& a) {
   for (int k = 0; k < NG; ++k) r.g[k] = a.g[k] / (2.0 * r.v);
   return r;
 }
-inline D dabs(const D& a) { return a.v < 0 ? a * -1.0 : a; }
 inline D datan2(const D& y, const D& x) {
   D r;
   r.v = std::atan2(y.v, x.v);
@@ -125,10 +124,15 @@ inline DV fixed(V3 p) { return {cst(p.x), cst(p.y), cst(p.z)}; }
 //   omega = atan2(|a.(b x c)|, abc + (a.b)c + (a.c)b + (b.c)a) / (2 pi),
 // a = p_j - p_i, b = p_k - p_i, c = p_l - p_i.  omega is the fraction of the
 // full sphere around p_i that the tetrahedron subtends.
-D solid_angle(const DV& pi, const DV& pj, const DV& pk, const DV& pl) {
+//
+// |a.(b x c)| is taken as s a.(b x c) with s the sign of the tetrahedron's
+// orientation det[a; b; c] given by the caller (exactly, for a K-tetrahedron):
+// the same value, and for a nearly flat tetrahedron the derivative of the
+// right branch, which rounding could otherwise flip.
+D solid_angle(const DV& pi, const DV& pj, const DV& pk, const DV& pl, int s) {
   const DV a = dsub(pj, pi), b = dsub(pk, pi), c = dsub(pl, pi);
   const D la = dnorm(a), lb = dnorm(b), lc = dnorm(c);
-  const D num = dabs(ddot(a, dcrs(b, c)));
+  const D num = ddot(a, dcrs(b, c)) * (double)s;
   const D den = la * lb * lc + ddot(a, b) * lc + ddot(a, c) * lb + ddot(b, c) * la;
   return datan2(num, den) * (1.0 / (2.0 * kPi));
 }
@@ -139,11 +143,16 @@ D solid_angle(const DV& pi, const DV& pj, const DV& pk, const DV& pl) {
 // with e = p_j - p_i, so the angle between them is the interior angle; it is
 // taken as atan2(|n_k x n_l|, n_k . n_l) rather than arccos of the normalised
 // dot product, which is the same angle without the loss of accuracy near 0, pi.
-D dihedral(const DV& pi, const DV& pj, const DV& pk, const DV& pl) {
+//
+// n_k x n_l = (e . (a_k x a_l)) e for n_k = e x a_k, n_l = e x a_l, so
+// |n_k x n_l| = |e| s det[e; a_k; a_l] with s the sign of that orientation,
+// given by the caller (exactly, for a K-tetrahedron; see solid_angle).
+D dihedral(const DV& pi, const DV& pj, const DV& pk, const DV& pl, int s) {
   const DV e = dsub(pj, pi);
-  const DV nk = dcrs(e, dsub(pk, pi));
-  const DV nl = dcrs(e, dsub(pl, pi));
-  return datan2(dnorm(dcrs(nk, nl)), ddot(nk, nl)) * (1.0 / (2.0 * kPi));
+  const DV ak = dsub(pk, pi), al = dsub(pl, pi);
+  const DV nk = dcrs(e, ak);
+  const DV nl = dcrs(e, al);
+  return datan2(dnorm(e) * (ddot(e, dcrs(ak, al)) * (double)s), ddot(nk, nl)) * (1.0 / (2.0 * kPi));
 }
 
 // Area of the cap of sphere i that lies inside ball j: S_ij^(i) = 2 pi sqrt(d_i) h_i
@@ -186,9 +195,10 @@ bool triple_point(const DV& pi, double wi, const DV& pj, double wj, const DV& pk
 D triple_term(const DV& pi, double Ri, const DV& pj, double Rj, const DV& pk, double Rk) {
   DV x;
   if (!triple_point(pi, Ri * Ri, pj, Rj * Rj, pk, Rk * Rk, &x)) return cst(0.0);
-  const D phij = dihedral(pi, pj, pk, x);
-  const D phik = dihedral(pi, pk, pj, x);
-  const D om = solid_angle(pi, pj, pk, x);
+  // x lies on the side of a x b (a = p_j - p_i, b = p_k - p_i): det[a; b; x - p_i] > 0
+  const D phij = dihedral(pi, pj, pk, x, +1);
+  const D phik = dihedral(pi, pk, pj, x, -1);
+  const D om = solid_angle(pi, pj, pk, x, +1);
   const D half = phij * cap_area(pi, Ri, pj, Rj) + phik * cap_area(pi, Ri, pk, Rk) -
                  om * (4.0 * kPi * Ri * Ri);
   return half * 2.0;
@@ -263,7 +273,7 @@ void tetrahedra(oracle_result& r) {
   const int n = (int)r.n;
   for (int i = 0; i < n; ++i) {
     const auto& N = r.nb[i];
-    const auto& A = r.atom;
+    oracle_pred::Base B(r.atom.data(), i, N.data(), (int)N.size(), r.st);
     for (size_t a = 0; a < N.size(); ++a) {
       const int j = N[a];
       if (j < i) continue;
@@ -273,15 +283,16 @@ void tetrahedra(oracle_result& r) {
         for (size_t c = b + 1; c < N.size(); ++c) {
           const int l = N[c];
           if (!r.ov(j, l) || !r.ov(k, l)) continue;
-          if (oracle_pred::orient(A[i], A[j], A[k], A[l], r.st) == 0) {
+          oracle_pred::TetTest T(B, (int)a, (int)b, (int)c);
+          if (T.orient() == 0) {
             ++r.flat;
             continue;
           }
-          if (oracle_pred::tet_size(A[i], A[j], A[k], A[l], r.st) > 0) continue;
+          if (T.size() > 0) continue;
           bool empty = true;
-          for (int m : N) {
-            if (m == j || m == k || m == l) continue;
-            if (oracle_pred::tet_side(A[i], A[j], A[k], A[l], A[m], r.st) < 0) {
+          for (size_t q = 0; q < N.size(); ++q) {
+            if (q == a || q == b || q == c) continue;
+            if (T.side((int)q) < 0) {
               empty = false;
               break;
             }
@@ -310,6 +321,7 @@ void triangles(oracle_result& r) {
   const auto& A = r.atom;
   for (int i = 0; i < n; ++i) {
     const auto& N = r.nb[i];
+    oracle_pred::Base B(A.data(), i, N.data(), (int)N.size(), r.st);
     for (size_t a = 0; a < N.size(); ++a) {
       const int j = N[a];
       if (j < i) continue;
@@ -325,11 +337,12 @@ void triangles(oracle_result& r) {
           ++r.flat;
           continue;
         }
-        if (oracle_pred::tri_size(A[i], A[j], A[k], r.st) > 0) continue;
+        oracle_pred::TriTest T(B, (int)a, (int)b);
+        if (T.size() > 0) continue;
         bool on_edge = true;
-        for (int m : N) {
-          if (m == j || m == k) continue;
-          if (oracle_pred::tri_side(A[i], A[j], A[k], A[m], r.st) < 0) {
+        for (size_t q = 0; q < N.size(); ++q) {
+          if (q == a || q == b) continue;
+          if (T.side((int)q) < 0) {
             on_edge = false;
             break;
           }
@@ -358,7 +371,10 @@ void edges(oracle_result& r) {
   }
   const auto& A = r.atom;
   for (int i = 0; i < n; ++i) {
-    for (int j : r.nb[i]) {
+    const auto& N = r.nb[i];
+    oracle_pred::Base B(A.data(), i, N.data(), (int)N.size(), r.st);
+    for (size_t a = 0; a < N.size(); ++a) {
+      const int j = N[a];
       if (j < i) continue;
       if (std::binary_search(has_tri[i].begin(), has_tri[i].end(), j)) {
         r.edges.push_back({i, j});
@@ -368,11 +384,12 @@ void edges(oracle_result& r) {
         ++r.flat;  // one centre, two radii: the smaller ball has no cell
         continue;
       }
-      if (oracle_pred::edge_size(A[i], A[j], r.st) > 0) continue;
+      oracle_pred::EdgeTest E(B, (int)a);
+      if (E.size() > 0) continue;
       bool inside = true;
-      for (int m : r.nb[i]) {
-        if (m == j) continue;
-        if (oracle_pred::edge_side(A[i], A[j], A[m], r.st) < 0) {
+      for (size_t q = 0; q < N.size(); ++q) {
+        if (q == a) continue;
+        if (E.side((int)q) < 0) {
           inside = false;
           break;
         }
@@ -446,6 +463,11 @@ void classify(oracle_result& r) {
     if (r.vin[i] && !has_edge[i]) r.vext[i] = 1;
 }
 
+// Exact sign of det[p_b - p_a; p_c - p_a; p_d - p_a] (never 0 for a K-tetrahedron).
+int orient_of(oracle_result& r, int a, int b, int c, int d) {
+  return oracle_pred::orient(r.atom[a], r.atom[b], r.atom[c], r.atom[d], r.st);
+}
+
 void add_grad(std::map<int, V3>& row, int atom, const D& f, int slot, double scale) {
   V3& g = row[atom];
   g.x += scale * f.g[3 * slot + 0];
@@ -489,7 +511,8 @@ void areas(oracle_result& r) {
       int o[3], c = 0;
       for (int v : T)
         if (v != i) o[c++] = v;
-      const D om = solid_angle(seed(r.p[i], 0), seed(r.p[o[0]], 1), seed(r.p[o[1]], 2), seed(r.p[o[2]], 3));
+      const D om = solid_angle(seed(r.p[i], 0), seed(r.p[o[0]], 1), seed(r.p[o[1]], 2), seed(r.p[o[2]], 3),
+                               orient_of(r, i, o[0], o[1], o[2]));
       Omega -= om.v;
       add_grad(row, i, om, 0, -Si);
       for (int s = 0; s < 3; ++s) add_grad(row, o[s], om, s + 1, -Si);
@@ -506,7 +529,8 @@ void areas(oracle_result& r) {
         int o[2], c = 0;
         for (int v : T)
           if (v != i && v != j) o[c++] = v;
-        const D ph = dihedral(seed(r.p[i], 0), seed(r.p[j], 1), seed(r.p[o[0]], 2), seed(r.p[o[1]], 3));
+        const D ph = dihedral(seed(r.p[i], 0), seed(r.p[j], 1), seed(r.p[o[0]], 2), seed(r.p[o[1]], 3),
+                              orient_of(r, i, j, o[0], o[1]));
         Phi -= ph.v;
         // d(Phi S) gets -S dphi
         add_grad(row, i, ph, 0, S.v);
@@ -668,10 +692,14 @@ void oracle_tetrahedra(const oracle_result* r, int32_t* t4) {
 }
 
 double oracle_solid_angle(const double* pi, const double* pj, const double* pk, const double* pl) {
-  return solid_angle(fixed(load(pi)), fixed(load(pj)), fixed(load(pk)), fixed(load(pl))).v;
+  const DV a = fixed(load(pi)), b = fixed(load(pj)), c = fixed(load(pk)), d = fixed(load(pl));
+  const D o = ddot(dsub(b, a), dcrs(dsub(c, a), dsub(d, a)));
+  return solid_angle(a, b, c, d, o.v < 0 ? -1 : 1).v;
 }
 double oracle_dihedral(const double* pi, const double* pj, const double* pk, const double* pl) {
-  return dihedral(fixed(load(pi)), fixed(load(pj)), fixed(load(pk)), fixed(load(pl))).v;
+  const DV a = fixed(load(pi)), b = fixed(load(pj)), c = fixed(load(pk)), d = fixed(load(pl));
+  const D o = ddot(dsub(b, a), dcrs(dsub(c, a), dsub(d, a)));
+  return dihedral(a, b, c, d, o.v < 0 ? -1 : 1).v;
 }
 double oracle_cap_area(const double* pi, double Ri, const double* pj, double Rj) {
   return cap_area(fixed(load(pi)), Ri, fixed(load(pj)), Rj).v;

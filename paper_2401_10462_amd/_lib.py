@@ -52,7 +52,8 @@ class sasa_diag(ctypes.Structure):
         (name, ctypes.c_double) for name in ("ms_total", "ms_cells", "ms_star", "ms_star_wide", "ms_terms",
                                              "ms_gather")] + [
         (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "planes_used",
-                                            "max_planes_used", "atoms_over_64_planes", "reused_cells")]
+                                            "max_planes_used", "atoms_over_64_planes", "reused_cells",
+                                            "second_pass_atoms")]
 
 
 _lib = None

@@ -170,7 +170,8 @@ void read_times(Ctx* c) {
 int check_errors(Ctx* c, unsigned long long bad_input, unsigned long long overflow) {
   if (bad_input) {
     c->kept = false;
-    return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
+    return fail(c, SASA_E_INVAL,
+                "NaN/Inf coordinate, radius <= 0, or two atoms with the same centre and radius in the input");
   }
   if (overflow) {
     c->kept = false;
@@ -212,6 +213,7 @@ int read_counters(Ctx* c, hipStream_t s, bool full = true) {
   c->diag.max_planes_used = (int64_t)h[ctr_slot(C_MAX_PLANES)];
   c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
   c->diag.reused_cells = (int64_t)h[ctr_slot(C_REUSED)];
+  c->diag.second_pass_atoms = (int64_t)h[ctr_slot(C_WIDE)];
   read_times(c);
   return check_errors(c, h[ctr_slot(C_BAD_INPUT)], h[ctr_slot(C_OVERFLOW)]);
 }

@@ -24,6 +24,7 @@
 //               u_i dA_i/dp_m (deterministic order)
 #include <hip/hip_runtime.h>
 
+#include "exact_side.h"
 #include "sasa_internal.h"
 
 namespace sasa {
@@ -31,7 +32,6 @@ namespace sasa {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr double kNearTie = 1e-9;  // A^2
 
 __device__ inline int prefix_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -530,6 +530,7 @@ struct StarLds {
     struct {  // the cell across a cut, then the star's lists
       double vx[VC], vy[VC], vz[VC];
       unsigned vp[VC];
+      signed char vt[VC];  // side-test bound of each vertex (thr_code)
       union {
         unsigned pairs[3 * VC];  // edges of the removed vertices of one cut
         struct {                 // cell edges by plane pair: code << 7 | first end, second end
@@ -555,10 +556,12 @@ enum SFlag : unsigned { SF_FACET = 1, SF_KTRI = 2, SF_EXTTRI = 4, SF_KEDGE = 8, 
 // Radical plane of neighbour j (position pj, weight R_j^2) seen from p_i:
 // n = 2 (p_j - p_i), b = |p_j - p_i|^2 - w_j + w_i, in a fixed order of
 // correctly rounded operations so that every evaluation gives the same bits.
+// (exact::radd / rsub / rmul: no contraction into fused operations)
 __device__ inline Pl radical_plane(const double4& pi, double wi, const double4& pj) {
-  const double ax = __dsub_rn(pj.x, pi.x), ay = __dsub_rn(pj.y, pi.y), az = __dsub_rn(pj.z, pi.z);
-  const double a2 = __dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(az, az));
-  return {2.0 * ax, 2.0 * ay, 2.0 * az, __dadd_rn(__dsub_rn(a2, __dmul_rn(pj.w, pj.w)), wi)};
+  using exact::radd, exact::rsub, exact::rmul;
+  const double ax = rsub(pj.x, pi.x), ay = rsub(pj.y, pi.y), az = rsub(pj.z, pi.z);
+  const double a2 = radd(radd(rmul(ax, ax), rmul(ay, ay)), rmul(az, az));
+  return {2.0 * ax, 2.0 * ay, 2.0 * az, radd(rsub(a2, rmul(pj.w, pj.w)), wi)};
 }
 
 // Plane of neighbour slot q: from LDS, or recomputed for slots past the
@@ -589,7 +592,14 @@ __device__ inline Pl plane_of(const LT& L, const Bufs& b, const double4& pi, dou
   return p;
 }
 
-__device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, double& y, double& z) {
+// Vertex of three planes.  thr (optional) receives a bound on the rounding
+// error of any side test at this vertex: the planes' own coefficients carry
+// rounding (relative ~8 u for the offsets), and the solve divides by the
+// determinant, so the vertex is off by at most E |1/det| with E a per-atom
+// constant, and a side test b_m - n_m . v by at most P E |1/det| + T (see
+// star_atom, where E, P and T are set).
+__device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, double& y, double& z,
+                              double* thr = nullptr, double thrP = 0.0, double thrT = 0.0) {
   const double bcx = B.y * C.z - B.z * C.y, bcy = B.z * C.x - B.x * C.z, bcz = B.x * C.y - B.y * C.x;
   const double cax = C.y * A.z - C.z * A.y, cay = C.z * A.x - C.x * A.z, caz = C.x * A.y - C.y * A.x;
   const double abx = A.y * B.z - A.z * B.y, aby = A.z * B.x - A.x * B.z, abz = A.x * B.y - A.y * B.x;
@@ -602,7 +612,15 @@ __device__ inline void solve3(const Pl& A, const Pl& B, const Pl& C, double& x, 
   x = (A.b * bcx + B.b * cax + C.b * abx) * inv;
   y = (A.b * bcy + B.b * cay + C.b * aby) * inv;
   z = (A.b * bcz + B.b * caz + C.b * abz) * inv;
+  if (thr) *thr = fma(fabs(inv), thrP, thrT);  // inf when det = 0: every test at it is undecided
 }
+
+// A side-test bound kept in LDS as the exponent of a power of two above it.
+__device__ inline signed char thr_code(double t) {
+  if (!(t < 1e30)) return (signed char)127;
+  return (signed char)max(-126, __builtin_amdgcn_frexp_exp(t));  // t < 2^e
+}
+__device__ inline double thr_value(signed char e) { return ldexp(1.0, (int)e); }
 
 // value of lane l (wave-uniform l)
 __device__ inline double rdl(double v, int l) {
@@ -640,12 +658,116 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Exact sign of the side test of plane slot k at the vertex with plane ids pv
+// (exact_side.h), evaluated by the calling lane alone in the work space W.
+template <class LT>
+__device__ __noinline__ int exact_side_at(const Bufs& b, const double4& pi, double half, const LT& L,
+                                          exact::Work& W, unsigned pv, int k) {
+  const unsigned ids[4] = {pid0(pv), pid1(pv), pid2(pv), 6u + (unsigned)k};
+  for (int q = 0; q < 4; ++q) {
+    if (ids[q] < 6) {
+      exact::cube_face(ids[q], half, W.pl[q]);
+    } else {
+      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return 2;
+    }
+  }
+  return exact::side(W);
+}
+
+// Side test of plane slot k at the vertex with plane ids pv in double-double
+// (each lane its own; 0 if that does not decide it).
+template <class LT>
+__device__ __noinline__ int dd_side_at(const Bufs& b, const double4& pi, double half, const LT& L, unsigned pv,
+                                       int k) {
+  exact::DPl P[4];
+  const unsigned ids[4] = {pid0(pv), pid1(pv), pid2(pv), 6u + (unsigned)k};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (ids[q] < 6) {
+      P[q] = exact::dd_cube(ids[q], half);
+    } else {
+      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      P[q] = exact::dd_radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w);
+    }
+  }
+  return exact::dd_side(P);
+}
+
+// Sign of det[n_a; n_b; n_c] of the vertex with plane ids pv (the orientation
+// of the tetrahedron (i, a, b, c)): double-double, each lane its own; 0 if that
+// does not decide it.
+template <class LT>
+__device__ __noinline__ int dd_orient_at(const Bufs& b, const double4& pi, double half, const LT& L, unsigned pv) {
+  exact::DPl P[3];
+  const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (ids[q] < 6) {
+      P[q] = exact::dd_cube(ids[q], half);
+    } else {
+      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      P[q] = exact::dd_radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w);
+    }
+  }
+  double m;
+  const exact::DD d = exact::dd_det3(P[0], P[1], P[2], m);
+  const double v = d.hi + d.lo;
+  return fabs(v) > 1e-27 * m ? (v > 0.0 ? 1 : -1) : 0;
+}
+
+// The same sign from the expansions, by the calling lane alone in W.
+template <class LT>
+__device__ __noinline__ int exact_orient_at(const Bufs& b, const double4& pi, double half, const LT& L,
+                                            exact::Work& W, unsigned pv) {
+  const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
+  for (int q = 0; q < 3; ++q) {
+    if (ids[q] < 6) {
+      exact::cube_face(ids[q], half, W.pl[q]);
+    } else {
+      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return 2;
+    }
+  }
+  if (!exact::det3(W.pl[0], W.pl[1], W.pl[2], W)) return 2;
+  return exact::sign(W.det3);
+}
+
+// The vertex of plane ids pv solved exactly (exact_side.h), by the calling lane
+// alone in the work space W.  False on failure.
+template <class LT>
+__device__ __noinline__ bool exact_vertex_at(const Bufs& b, const double4& pi, double half, const LT& L,
+                                             exact::Work& W, unsigned pv, double* v) {
+  const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
+  for (int q = 0; q < 3; ++q) {
+    if (ids[q] < 6) {
+      exact::cube_face(ids[q], half, W.pl[q]);
+    } else {
+      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return false;
+    }
+  }
+  return exact::vertex(W, v);
+}
+
 // The star of the atom at cell-ordered position sidx.  Returns false when the
-// atom needs more than NBC neighbours or VC cell vertices and `last` is not
-// set (it is then left to a pass with larger capacities; nothing is written);
-// with `last` such an atom is reported as a capacity overflow.
-template <bool HINTS, int NBC, int VC, int NPL>
-__device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, bool last) {
+// atom needs more than NBC neighbours or VC cell vertices, or (without EXACT)
+// when a clipping side test is too close to zero for its rounding bound, and
+// `last` is not set: it is then left to the second pass (larger capacities,
+// exact side tests; nothing is written).  With `last` an atom over capacity is
+// reported as a capacity overflow.
+//
+// Ties.  A side test that rounding cannot decide is decided exactly (EXACT);
+// a vertex exactly on the plane is kept.  Keeping every tie is the clipping of
+// the cell whose planes are each moved outwards by an infinitesimal that grows
+// with the clipping order (later planes more), a valid perturbation of the
+// neighbours' weights: the cell is a consistent simple polytope, and Eq. 1 over
+// its star gives the atom's exact area in the limit.  Each atom's cell is its
+// own perturbation, so on tied inputs the stars of two atoms need not agree on a
+// shared simplex, while every atom's area (unique) and gradient (unique where
+// the area is differentiable) do.
+template <bool HINTS, bool EXACT, int NBC, int VC, int NPL>
+__device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, bool last, exact::Work* W) {
   // atoms in cell order (neighbouring blocks share neighbours in cache); the
   // atom's id, position, molecule and cell come from the cell-ordered copies
   const int i = b.sorted[sidx];
@@ -750,6 +872,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         const double rr = Ri + pj[h2].w;
         take = (j[h2] != i) && (d2 < rr * rr);
       }
+      // two balls with one centre and one radius have one cell between them:
+      // the input is refused (a smaller ball on the centre of a larger one is
+      // hidden by the clipping: its plane 0 . x <= w_i - w_j removes the cell)
+      if (__builtin_expect(__ballot(take && d2 == 0.0 && pj[h2].w == Ri) != 0ull, 0) && lane == 0)
+        atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], 1ull);
       const unsigned long long m = __ballot(take);
       if (take) {
         const int at = nn + prefix_below(m);
@@ -846,8 +973,42 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
   // registers; LDS holds the cell only across a cut.
   const double half = 1.1 * Ri;
+  // Rounding bounds of the side tests.  Every plane has |n| <= P (neighbours
+  // overlap, so |p_j - p_i| < R_i + R_max; cube faces |n| = 1) and an offset
+  // computed with error <= 8 u Bo; every vertex has |v| <= V.  A vertex solved
+  // from three planes is then off by at most E |1/det|, E = 128 u P^2 (Bo + P V)
+  // (the offsets' errors and the normals' through adj(M) / det, the rounding of
+  // the cross products, of the numerators and of det), and a side test
+  // b_m - n_m . v by at most P E |1/det| + 12 u (Bo + P V) (the plane's own
+  // errors and the dot product's rounding).
+  constexpr double kU = 1.1102230246251565e-16;  // 2^-53
+  const double Pn = fmax(2.0 * (Ri + rmax), 1.0);
+  const double Bo = (Ri + rmax) * (Ri + rmax) + rmax * rmax + wi + half;
+  const double Vv = 1.7320508075688772 * half;
+  const double thrE = 1.01 * 128.0 * kU * Pn * Pn * (Bo + Pn * Vv);
+  const double thrP = Pn * thrE;
+  const double thrT = 1.01 * 12.0 * kU * (Bo + Pn * Vv);
+  const double invPn = 1.0 / Pn;
+  // The star is read off the vertices' positions (inside B_i or not; where a
+  // cell edge passes).  The fast pass certifies each such decision with the
+  // vertex's bound and leaves the atom to the second pass if one is too close
+  // to call; the second pass solves every vertex whose position bound passes
+  // 1e-9 A exactly (planes close to parallel, as where a cut crosses an edge
+  // lying almost in its plane: 4 ulp per coordinate), and a kept trajectory
+  // vertex is used only within that bound.
+  const double thrCap = fma(Pn, 1e-9, thrT);
+  const double thrSolved = fma(Pn, 7.0 * kU * Vv, thrT);
+  // |v|^2 bound of a vertex with side-test bound t (its position error is at most t / P)
+  auto vr2 = [&](double x, double y, double z, double t) {
+    const double ev = t * invPn;
+    const double r = fma(ev, 2.0 * Vv + ev, x * x + y * y + z * z);
+    return r <= 1e300 ? r : 1e300;  // (a non-finite vertex never lets the clipping stop)
+  };
+  long long exact_tests = 0;
+  bool exact_fail = false;
   int nv = 8;
   double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+  double t0 = thrT, t1 = thrT;  // side-test bounds (the cube's corners are exact)
   unsigned p0 = 0, p1 = 0;
   if (lane < 8) {
     x0 = (lane & 1) ? -half : half;
@@ -873,7 +1034,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   int k0 = 0;
   if (HINTS && nvh > 0 && nvh <= 64 && nvh <= VC && nfirst > 0 && !overflow) {
     bool ok = true;
-    double vx = 0.0, vy = 0.0, vz = 0.0;
+    double vx = 0.0, vy = 0.0, vz = 0.0, vt = 0.0;
     unsigned vp = 0u;
     if (lane < nvh) {
       unsigned q[3];
@@ -889,13 +1050,13 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       vp = pack3(q[0], q[1], q[2]);
       if (ok && pid0(vp) != pid1(vp) && pid1(vp) != pid2(vp)) {
         solve3(plane_of(L, b, pi, wi, pid0(vp), half), plane_of(L, b, pi, wi, pid1(vp), half),
-               plane_of(L, b, pi, wi, pid2(vp), half), vx, vy, vz);
-        ok = isfinite(vx) && isfinite(vy) && isfinite(vz);
-        for (unsigned c = 0; c < 6 && ok; ++c) {  // the cube's planes
+               plane_of(L, b, pi, wi, pid2(vp), half), vx, vy, vz, &vt, thrP, thrT);
+        ok = isfinite(vx) && isfinite(vy) && isfinite(vz) && (!EXACT || vt <= thrCap);
+        for (unsigned c = 0; c < 6 && ok; ++c) {  // the cube's planes (strictly inside, beyond rounding)
           if (pid0(vp) == c || pid1(vp) == c || pid2(vp) == c) continue;
           const double sg = (c & 1) ? -1.0 : 1.0;
           const double t = (c >> 1) == 0 ? vx : ((c >> 1) == 1 ? vy : vz);
-          ok = half - sg * t >= 0.0;
+          ok = half - sg * t >= vt;
         }
       } else {
         ok = false;
@@ -907,7 +1068,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       const Pl qk = slot_plane(L, b, pi, wi, k);
       const unsigned pk = 6u + (unsigned)k;
       if (lane < nvh && pid0(vp) != pk && pid1(vp) != pk && pid2(vp) != pk)
-        ok = qk.b - (qk.x * vx + qk.y * vy + qk.z * vz) >= 0.0;
+        ok = qk.b - (qk.x * vx + qk.y * vy + qk.z * vz) >= vt;
     }
     plane_tests += (long long)nfirst * nvh;
     if (__ballot(!ok) == 0ull) {
@@ -916,11 +1077,13 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       nv = nvh;
       vmax = nvh;
       new_verts += nvh;
-      x0 = vx, y0 = vy, z0 = vz, p0 = vp;
-      rho2 = wave_max(lane < nvh ? vx * vx + vy * vy + vz * vz : 0.0);
+      x0 = vx, y0 = vy, z0 = vz, p0 = vp, t0 = vt;
+      rho2 = wave_max(lane < nvh ? vr2(vx, vy, vz, vt) : 0.0);
       rho_exact = true;
       // the star is read off LDS if no plane cuts Q further
-      if (lane < nvh) L.u.cl.vx[lane] = vx, L.u.cl.vy[lane] = vy, L.u.cl.vz[lane] = vz, L.u.cl.vp[lane] = vp;
+      if (lane < nvh)
+        L.u.cl.vx[lane] = vx, L.u.cl.vy[lane] = vy, L.u.cl.vz[lane] = vz, L.u.cl.vp[lane] = vp,
+        L.u.cl.vt[lane] = thr_code(vt);
       __syncthreads();
     }
   }
@@ -942,8 +1105,8 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     if (__builtin_expect(k >= nfirst && __ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull, 0)) {
       if (!rho_exact) {
         double r2 = 0.0;
-        if (lane < nv) r2 = x0 * x0 + y0 * y0 + z0 * z0;
-        if ((VC > 64 && lane + 64 < nv)) r2 = fmax(r2, x1 * x1 + y1 * y1 + z1 * z1);
+        if (lane < nv) r2 = vr2(x0, y0, z0, t0);
+        if ((VC > 64 && lane + 64 < nv)) r2 = fmax(r2, vr2(x1, y1, z1, t1));
         rho2 = wave_max(r2);
         rho_exact = true;
       }
@@ -952,9 +1115,52 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         break;
       }
     }
-    const bool r0 = lane < nv && qb - (qx * x0 + qy * y0 + qz * z0) < 0.0;
-    const bool r1 = (VC > 64 && lane + 64 < nv) && qb - (qx * x1 + qy * y1 + qz * z1) < 0.0;
+    const double g0 = qb - (qx * x0 + qy * y0 + qz * z0);
+    const double g1 = VC > 64 ? qb - (qx * x1 + qy * y1 + qz * z1) : 0.0;
+    bool r0 = lane < nv && g0 < 0.0;
+    bool r1 = (VC > 64 && lane + 64 < nv) && g1 < 0.0;
     plane_tests += nv;
+    {
+      // side tests within their rounding bound: the fast pass leaves the atom to
+      // the second pass, which decides them exactly (ties keep the vertex)
+      // (negated tests: a vertex with a non-finite coordinate is undecided too)
+      const bool u0 = lane < nv && !(fabs(g0) >= t0);
+      const bool u1 = (VC > 64 && lane + 64 < nv) && !(fabs(g1) >= t1);
+      if (__builtin_expect(__ballot(u0 || u1) != 0ull, 0)) {
+        if constexpr (!EXACT) {
+          if (!last) return false;
+        } else {
+          // double-double first, each lane its own test; then the remaining
+          // ones (exact ties, in practice) in expansions, one lane at a time
+          bool v0 = u0, v1 = u1;
+          if (v0) {
+            const int sg = dd_side_at(b, pi, half, L, p0, k);
+            if (sg != 0) r0 = sg < 0, v0 = false;
+          }
+          if (VC > 64 && v1) {
+            const int sg = dd_side_at(b, pi, half, L, p1, k);
+            if (sg != 0) r1 = sg < 0, v1 = false;
+          }
+          exact_tests += __popcll(__ballot(u0)) + __popcll(__ballot(u1));
+          for (int h = 0; h < 2; ++h) {
+            unsigned long long um = __ballot(h ? v1 : v0);
+            while (um) {
+              const int l = __builtin_ctzll(um);
+              um &= um - 1ull;
+              const unsigned pv = (unsigned)__builtin_amdgcn_readlane((int)(h ? p1 : p0), l);
+              int sg = 0;
+              if (lane == 0) sg = exact_side_at(b, pi, half, L, *W, pv, k);
+              sg = __shfl(sg, 0, 64);
+              exact_fail |= sg == 2;
+              if (lane == l) {
+                if (h) r1 = sg < 0;
+                else r0 = sg < 0;
+              }
+            }
+          }
+        }
+      }
+    }
     const unsigned long long m0 = __ballot(r0), m1 = __ballot(r1);
     const int nr0 = __popcll(m0);
     const int nrem = nr0 + __popcll(m1);
@@ -985,11 +1191,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     const unsigned long long k0 = __ballot(lane < nv && !r0), k1 = __ballot((VC > 64 && lane + 64 < nv) && !r1);
     if (lane < nv && !r0) {
       const int d = prefix_below(k0);
-      L.u.cl.vx[d] = x0, L.u.cl.vy[d] = y0, L.u.cl.vz[d] = z0, L.u.cl.vp[d] = p0;
+      L.u.cl.vx[d] = x0, L.u.cl.vy[d] = y0, L.u.cl.vz[d] = z0, L.u.cl.vp[d] = p0, L.u.cl.vt[d] = thr_code(t0);
     }
     if ((VC > 64 && lane + 64 < nv) && !r1) {
       const int d = __popcll(k0) + prefix_below(k1);
-      L.u.cl.vx[d] = x1, L.u.cl.vy[d] = y1, L.u.cl.vz[d] = z1, L.u.cl.vp[d] = p1;
+      L.u.cl.vx[d] = x1, L.u.cl.vy[d] = y1, L.u.cl.vz[d] = z1, L.u.cl.vp[d] = p1, L.u.cl.vt[d] = thr_code(t1);
     }
     // an edge with exactly one removed end crosses the plane: new vertex on it,
     // solved from its three planes in ascending id order (canonical)
@@ -1013,18 +1219,45 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         cross = (c == 1);
       }
       const unsigned long long cm = __ballot(cross);
+      bool bad_v = false;
+      int my_slot = -1;
       if (cross) {
         const int slot = nkeep + ncross + prefix_below(cm);
         if (slot < VC) {
+          my_slot = slot;
           // the pair is stored ascending and the cutting plane has the highest id
           // so far, so the triple is already in ascending order
           const unsigned tri3 = pr | (pid << 20);
-          double x, y, z;
-          solve3(plane_of(L, b, pi, wi, pr & 1023u, half), plane_of(L, b, pi, wi, pr >> 10, half), qk, x, y, z);
+          double x, y, z, t;
+          solve3(plane_of(L, b, pi, wi, pr & 1023u, half), plane_of(L, b, pi, wi, pr >> 10, half), qk, x, y, z, &t,
+                 thrP, thrT);
           L.u.cl.vx[slot] = x;
           L.u.cl.vy[slot] = y;
           L.u.cl.vz[slot] = z;
           L.u.cl.vp[slot] = tri3;
+          L.u.cl.vt[slot] = thr_code(t);
+          bad_v = EXACT && !(t <= thrCap);
+        }
+      }
+      if constexpr (EXACT) {
+        if (__builtin_expect(__ballot(bad_v) != 0ull, 0)) {
+          unsigned long long bm = __ballot(bad_v);
+          while (bm) {
+            const int l = __builtin_ctzll(bm);
+            bm &= bm - 1ull;
+            const unsigned tv = (unsigned)__builtin_amdgcn_readlane((int)(pr | (pid << 20)), l);
+            const int sl = __builtin_amdgcn_readlane(my_slot, l);
+            if (lane == 0) {
+              double v[3];
+              if (exact_vertex_at(b, pi, half, L, *W, tv, v)) {
+                L.u.cl.vx[sl] = v[0], L.u.cl.vy[sl] = v[1], L.u.cl.vz[sl] = v[2];
+                L.u.cl.vt[sl] = thr_code(thrSolved);
+              } else {
+                exact_fail = true;
+              }
+            }
+          }
+          exact_fail = __shfl(exact_fail ? 1 : 0, 0, 64) != 0;
         }
       }
       ncross += __popcll(cm);
@@ -1039,12 +1272,16 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     __syncthreads();
     x0 = y0 = z0 = x1 = y1 = z1 = 0.0;
     p0 = p1 = 0u;
-    if (lane < nv) x0 = L.u.cl.vx[lane], y0 = L.u.cl.vy[lane], z0 = L.u.cl.vz[lane], p0 = L.u.cl.vp[lane];
+    if (lane < nv)
+      x0 = L.u.cl.vx[lane], y0 = L.u.cl.vy[lane], z0 = L.u.cl.vz[lane], p0 = L.u.cl.vp[lane],
+      t0 = thr_value(L.u.cl.vt[lane]);
     if ((VC > 64 && lane + 64 < nv))
-      x1 = L.u.cl.vx[lane + 64], y1 = L.u.cl.vy[lane + 64], z1 = L.u.cl.vz[lane + 64], p1 = L.u.cl.vp[lane + 64];
+      x1 = L.u.cl.vx[lane + 64], y1 = L.u.cl.vy[lane + 64], z1 = L.u.cl.vz[lane + 64], p1 = L.u.cl.vp[lane + 64],
+      t1 = thr_value(L.u.cl.vt[lane + 64]);
     rho_exact = false;
     __syncthreads();  // the next cut overwrites pairs / vertices only after everyone has read
   }
+  overflow |= exact_fail;  // an expansion outgrew its array (inputs far outside Angstrom scales)
   int* st = b.stat + (size_t)i * STAT_STRIDE;
   if (lane == 0) {
     st[S_NN] = nn;
@@ -1074,17 +1311,22 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
 
   // ---- 3. the star: K-tetrahedra (cell vertices in B_i), K-triangles (cell
   // edges meeting B_i), K-edges (facets meeting B_i)
-  int ties = 0;
-  bool in0 = false, in1 = false;
+  int ties = lane == 0 ? (int)exact_tests : 0;  // side tests decided exactly
+  // |v|^2 - w_i is off by at most e (2 V + e) + rounding for a vertex off by e
+  auto near_sphere = [&](double m, double t) {
+    const double e = t * invPn;
+    return !(fabs(m) > fma(e, 2.0 * Vv + e, 8.0 * kU * (Vv * Vv + wi)));
+  };
+  bool in0 = false, in1 = false, unsure = false;
   if (lane < nv) {
     const double m = x0 * x0 + y0 * y0 + z0 * z0 - wi;
     in0 = m <= 0.0 && pid0(p0) >= 6;
-    ties += fabs(m) < kNearTie;
+    unsure |= pid0(p0) >= 6 && near_sphere(m, t0);
   }
   if ((VC > 64 && lane + 64 < nv)) {
     const double m = x1 * x1 + y1 * y1 + z1 * z1 - wi;
     in1 = m <= 0.0 && pid0(p1) >= 6;
-    ties += fabs(m) < kNearTie;
+    unsure |= pid0(p1) >= 6 && near_sphere(m, t1);
   }
   // facets present
   for (int h = 0; h < 2; ++h) {
@@ -1180,6 +1422,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     const int v = lane + 64 * h;
     const unsigned p = h ? p1 : p0;
     const double vx = h ? x1 : x0, vy = h ? y1 : y0, vz = h ? z1 : z0;
+    const double vtt = h ? t1 : t0;
     const bool vin = h ? in1 : in0;
     for (int c = 0; c < 3; ++c) {
       const unsigned pa = c == 0 ? pid1(p) : pid0(p);
@@ -1199,8 +1442,12 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
         t = fmin(fmax(t, 0.0), 1.0);
         const double qx = vx + t * dx, qy = vy + t * dy, qz = vz + t * dz;
         const double m = qx * qx + qy * qy + qz * qz - wi;
-        ties += fabs(m) < kNearTie;
-        if (m <= 0.0) {
+        // (the distance of a segment from p_i moves by at most the larger
+        // displacement of its ends)
+        unsure |= !vin && !uin && near_sphere(m, fmax(vtt, thr_value(L.u.cl.vt[u])));
+        // an edge with an end vertex in B_i meets B_i (so that n_t and the
+        // triangle's presence never disagree through rounding)
+        if (m <= 0.0 || vin || uin) {
           hit = true;
           const unsigned nt = (unsigned)vin + (unsigned)uin;
           word = (pa - 6) | ((pb - 6) << 10) | (nt << 20);
@@ -1218,6 +1465,9 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     }
   }
   ntri = min(ntri, 2 * VC);
+  if constexpr (!EXACT) {
+    if (__builtin_expect(__ballot(unsure) != 0ull, 0) && !last) return false;
+  }
   __syncthreads();
   // facets without a K-triangle: K-edge iff the disk centre lies in the cell
   for (int s = lane; s < nn; s += 64) {
@@ -1229,13 +1479,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       const double sc = nb / (nx * nx + ny * ny + nz * nz);
       const double yx = sc * nx, yy = sc * ny, yz = sc * nz;
       const double se = yx * yx + yy * yy + yz * yz - wi;
-      ties += fabs(se) < kNearTie;
       bool inside = se <= 0.0;
       for (int t = 0; t < nn && inside; ++t) {
         if (t == s) continue;
         const Pl qt = slot_plane(L, b, pi, wi, t);
         const double g = qt.b - (qt.x * yx + qt.y * yy + qt.z * yz);
-        ties += fabs(g) < kNearTie;
         inside = g >= 0.0;
       }
       kedge = inside;
@@ -1288,6 +1536,70 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   const bool ext = inK && (nk == 0 || next > 0);
   __syncthreads();
 
+  // orientation of each K-tetrahedron (i, a, b, c): the sign of det[n_a; n_b;
+  // n_c] in plane-id order.  The angle terms take |det| as that sign times det,
+  // which for a nearly flat tetrahedron fixes the branch of their derivatives
+  // that rounding could flip; it is taken from the vertex's normals when their
+  // rounding (relative u in n = 2 (p_j - p_i)) cannot reach it, else exactly
+  // (the fast pass leaves such an atom to the second pass).
+  int osg0 = 1, osg1 = 1;
+  bool ounsure0 = false, ounsure1 = false;
+  for (int h = 0; h < 2; ++h) {
+    const bool vin = h ? in1 : in0;
+    if (!vin) continue;
+    const unsigned p = h ? p1 : p0;
+    const Pl A = plane_of(L, b, pi, wi, pid0(p), half), B = plane_of(L, b, pi, wi, pid1(p), half),
+             C = plane_of(L, b, pi, wi, pid2(p), half);
+    const double d = A.x * (B.y * C.z - B.z * C.y) + A.y * (B.z * C.x - B.x * C.z) + A.z * (B.x * C.y - B.y * C.x);
+    const double m = (fabs(A.x) + fabs(A.y) + fabs(A.z)) * (fabs(B.x) + fabs(B.y) + fabs(B.z)) *
+                     (fabs(C.x) + fabs(C.y) + fabs(C.z));
+    const bool sure = fabs(d) > 24.0 * kU * m;
+    if (h) osg1 = d < 0.0 ? -1 : 1, ounsure1 = !sure;
+    else osg0 = d < 0.0 ? -1 : 1, ounsure0 = !sure;
+  }
+  if (__builtin_expect(__ballot(ounsure0 || ounsure1) != 0ull, 0)) {
+    if constexpr (!EXACT) {
+      if (!last) return false;
+    } else {
+      for (int h = 0; h < 2; ++h) {
+        bool u = h ? ounsure1 : ounsure0;
+        if (u) {
+          const int sg = dd_orient_at(b, pi, half, L, h ? p1 : p0);
+          if (sg != 0) {
+            if (h) osg1 = sg;
+            else osg0 = sg;
+            u = false;
+          }
+        }
+        unsigned long long um = __ballot(u);
+        while (um) {
+          const int l = __builtin_ctzll(um);
+          um &= um - 1ull;
+          const unsigned pv = (unsigned)__builtin_amdgcn_readlane((int)(h ? p1 : p0), l);
+          int sg = 0;
+          if (lane == 0) sg = exact_orient_at(b, pi, half, L, *W, pv);
+          sg = __shfl(sg, 0, 64);
+          exact_fail |= sg == 2 || sg == 0;
+          if (lane == l) {
+            if (h) osg1 = sg < 0 ? -1 : 1;
+            else osg0 = sg < 0 ? -1 : 1;
+          }
+        }
+      }
+    }
+  }
+  if (exact_fail) {  // an expansion outgrew its array: reported as a capacity overflow
+    if (lane == 0) {
+      st[S_BAD] = 1;
+      atomicAdd(&b.ctr[ctr_slot(C_OVERFLOW)], 1ull);
+      if (HINTS) b.hint_n[i] = 0;
+      b.vflag[i] = 0;
+      b.kn_cnt[i] = 0;
+      b.kt_cnt[i] = 0;
+      b.ktr_cnt[i] = 0;
+    }
+    return true;
+  }
   // tetrahedra at i (cell vertices inside B_i)
   const unsigned long long tm0 = __ballot(in0), tm1 = __ballot(in1);
   const int ntet = __popcll(tm0) + __popcll(tm1);
@@ -1305,7 +1617,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       bad_lane = true;
     } else if (at < KT_CAP) {  // K-neighbour indices ascending: the terms do not depend on the clipping order
       const unsigned k3 = pack3(ka, kb, kc);
-      b.ktet[(size_t)i * KT_CAP + at] = pid0(k3) | (pid1(k3) << 8) | (pid2(k3) << 16);
+      // orientation in that order: the plane-id order's, flipped by an odd sort
+      const int inv = (ka > kb) + (ka > kc) + (kb > kc);
+      const int osg = (h ? osg1 : osg0) * ((inv & 1) ? -1 : 1);
+      b.ktet[(size_t)i * KT_CAP + at] =
+          pid0(k3) | (pid1(k3) << 8) | (pid2(k3) << 16) | (osg < 0 ? (1u << 24) : 0u);
     }
     int ja = L.idx[sa], jb = L.idx[sb], jc = L.idx[sc];
     if (i < ja && i < jb && i < jc) {
@@ -1423,23 +1739,26 @@ template <bool HINTS>
 __global__ __launch_bounds__(64, 5) void k_star(Bufs b) {
   __shared__ StarLds<NB_CAP, V_FAST, NPL_FAST> L;
   if ((int)blockIdx.x >= b.n) return;
-  if (!star_atom<HINTS>(b, L, blockIdx.x, false) && threadIdx.x == 0) {
+  if (!star_atom<HINTS, false>(b, L, blockIdx.x, false, nullptr) && threadIdx.x == 0) {
     const unsigned long long q = atomicAdd(&b.ctr[ctr_slot(C_WIDE)], 1ull);
     b.wide[q] = (int)blockIdx.x;
   }
 }
 
-// Wide pass: the queued atoms, with the full capacities, a fixed grid looping
-// over the queue (it returns at once when the queue is empty).
+// Second pass: the queued atoms (cells past 64 vertices, or a side test
+// within its rounding bound), with the full capacities and exact side tests,
+// a fixed grid looping over the queue (it returns at once when the queue is
+// empty).  The exact work space is in LDS, used by one lane at a time.
 constexpr int WIDE_BLOCKS = 64;
 
 template <bool HINTS>
 __global__ __launch_bounds__(64) void k_star_wide(Bufs b) {
   __shared__ StarLds<NB_CAP, V_CAP, NB_CAP> L;
+  __shared__ exact::Work W;
   const int cnt = (int)b.ctr[ctr_slot(C_WIDE)];
   for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
     __syncthreads();
-    star_atom<HINTS>(b, L, b.wide[q], true);
+    star_atom<HINTS, true>(b, L, b.wide[q], true, &W);
   }
 }
 
@@ -1547,19 +1866,22 @@ __device__ inline double tatan2(double y, double x) { return atan2(y, x); }
 
 // Normalised solid angle at the origin of the tetrahedron (0, a, b, c) (Van
 // Oosterom--Strackee, atan2 form) and its gradient with respect to a, b, c.
+// osg (if not 0) is the sign of det[a; b; c], known exactly: |a.(b x c)| is then
+// taken as osg a.(b x c), which for a nearly flat tetrahedron keeps the
+// derivative on the branch of its true orientation.
 template <typename T>
-__device__ T solid_angle(V3<T> a, V3<T> b, V3<T> c, V3<T>* ga, V3<T>* gb, V3<T>* gc, bool grad) {
+__device__ T solid_angle(V3<T> a, V3<T> b, V3<T> c, V3<T>* ga, V3<T>* gb, V3<T>* gc, bool grad, int osg = 0) {
   const T la = norm(a), lb = norm(b), lc = norm(c);
   const V3<T> bxc = cross(b, c);
   const T tp = dot(a, bxc);
-  const T N = fabs(tp);
+  const T N = osg ? T(osg) * tp : fabs(tp);
   const T ab = dot(a, b), ac = dot(a, c), bc = dot(b, c);
   const T D = la * lb * lc + ab * lc + ac * lb + bc * la;
   const T inv2pi = T(1.0 / (2.0 * kPi));
   const T om = tatan2(N, D) * inv2pi;
   if (grad) {
     const T k = inv2pi / (N * N + D * D);
-    const T dN = D * k * (tp >= T(0) ? T(1) : T(-1));
+    const T dN = D * k * (osg ? T(osg) : (tp >= T(0) ? T(1) : T(-1)));
     const T dD = -N * k;
     *ga = cross(b, c) * dN + (a * ((lb * lc + bc) / la) + b * lc + c * lb) * dD;
     *gb = cross(c, a) * dN + (b * ((la * lc + ac) / lb) + a * lc + c * la) * dD;
@@ -1571,15 +1893,18 @@ __device__ T solid_angle(V3<T> a, V3<T> b, V3<T> c, V3<T>* ga, V3<T>* gb, V3<T>*
 // Normalised dihedral angle along the edge (0, e) between the faces (0, e, u)
 // and (0, e, v), and its gradient with respect to e, u, v.  The wing
 // gradients are normal to their faces; the edge end takes the lever share
-// that keeps the angle invariant under translation and rotation.
+// that keeps the angle invariant under translation and rotation.  With osg
+// (if not 0) the sign of det[e; u; v], known exactly, |n_k x n_l| is taken as
+// osg |e| det[e; u; v] (n_k x n_l = det[e; u; v] e) and the wings' side from it.
 template <typename T>
-__device__ T dihedral(V3<T> e, V3<T> u, V3<T> v, V3<T>* ge, V3<T>* gu, V3<T>* gv, bool grad) {
+__device__ T dihedral(V3<T> e, V3<T> u, V3<T> v, V3<T>* ge, V3<T>* gu, V3<T>* gv, bool grad, int osg = 0) {
   const V3<T> nk = cross(e, u), nl = cross(e, v);
   const T inv2pi = T(1.0 / (2.0 * kPi));
-  const T ph = tatan2(norm(cross(nk, nl)), dot(nk, nl)) * inv2pi;
+  const T num = osg ? T(osg) * norm(e) * dot(nk, v) : norm(cross(nk, nl));
+  const T ph = tatan2(num, dot(nk, nl)) * inv2pi;
   if (grad) {
     const T le2 = dot(e, e), le = sqrt(le2);
-    const T sg = dot(nk, v) >= T(0) ? T(1) : T(-1);
+    const T sg = osg ? T(osg) : (dot(nk, v) >= T(0) ? T(1) : T(-1));
     *gu = nk * (-sg * le / dot(nk, nk) * inv2pi);
     *gv = nl * (sg * le / dot(nl, nl) * inv2pi);
     const T tu = dot(u, e) / le2, tv = dot(v, e) / le2;
@@ -1623,7 +1948,7 @@ __device__ inline V3<T> ld(const TermsLds& L, int k) {
 // grad -- its contributions to dA_i/dp for a, b, c: -4 pi w_i d(omega) from the
 // vertex term and +S_e d(phi_e) for each exterior edge e at i (Eqs. 3, 5).
 template <typename T>
-__device__ double tet_item(const TermsLds& L, const int ks[3], unsigned long long extm, double Si, bool grad,
+__device__ double tet_item(const TermsLds& L, const int ks[3], int osg, unsigned long long extm, double Si, bool grad,
                            double phi[3], double acc_out[3][3]) {
   const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
   V3<T> acc[3];
@@ -1632,12 +1957,12 @@ __device__ double tet_item(const TermsLds& L, const int ks[3], unsigned long lon
   // evaluated in double.
   V3<double> g[3];
   const double om = solid_angle<double>(ld<double>(L, ks[0]), ld<double>(L, ks[1]), ld<double>(L, ks[2]), &g[0],
-                                        &g[1], &g[2], grad);
+                                        &g[1], &g[2], grad, osg);
   for (int c = 0; c < 3; ++c) acc[c] = V3<T>{T(-Si * g[c].x), T(-Si * g[c].y), T(-Si * g[c].z)};
   for (int c = 0; c < 3; ++c) {
     const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
     V3<T> ge, g1, g2;
-    const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad);
+    const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad, osg);  // cyclic: same orientation
     phi[c] = (double)ph;
     if (grad && ((extm >> ks[c]) & 1ull)) {
       const T Se = T(L.S[ks[c]]);
@@ -1772,8 +2097,9 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
           dbl = tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
                             L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin;
         double ph[3];
-        const double om = dbl ? tet_item<double>(L, ks, extm, Si, grad, ph, L.c.t.tg[lane])
-                              : tet_item<T>(L, ks, extm, Si, grad, ph, L.c.t.tg[lane]);
+        const int osg = (w >> 24) & 1u ? -1 : 1;  // orientation of (i, ks[0], ks[1], ks[2]), decided exactly
+        const double om = dbl ? tet_item<double>(L, ks, osg, extm, Si, grad, ph, L.c.t.tg[lane])
+                              : tet_item<T>(L, ks, osg, extm, Si, grad, ph, L.c.t.tg[lane]);
         omega_sum += om;
         L.c.t.phi[lane][0] = ph[0], L.c.t.phi[lane][1] = ph[1], L.c.t.phi[lane][2] = ph[2];
       }

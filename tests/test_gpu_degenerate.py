@@ -1,0 +1,148 @@
+"""HIP path vs the FP64 oracle on inputs with exact and near ties (C-ABI).
+
+Ideal rings, cube corners, lattices, an fcc patch, a coinciding regular
+tetrahedron, exact tangencies and coincident centres.  The per-atom areas are
+unique and are compared at the usual bars (1e-9 FP64, 1e-4 MIXED, floors
+1 A^2); so are the gradients, which are unique where the area is
+differentiable (it is C^1 at these ties; tangency is the exception and is
+checked against the two one-sided limits).  The simplex set is compared only
+where the oracle broke no exact tie: there it is unique.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import degenerate as dg
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
+PROBE = 1.4
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    from paper_2401_10462_amd import SasaContext
+    c = {"fp64": SasaContext(precision="fp64"), "mixed": SasaContext(precision="mixed")}
+    yield c
+    for v in c.values():
+        v.close()
+
+
+def _check(area, dadx, ref, tol, grad=True):
+    err_a = np.abs(area - ref.area) / np.maximum(ref.area, 1.0)
+    assert err_a.max() <= tol, f"area rel err {err_a.max():.3e} at atom {err_a.argmax()}"
+    assert np.all(area >= -tol)
+    if grad:
+        gn = np.linalg.norm(ref.dadx, axis=1)
+        err_g = np.linalg.norm(dadx - ref.dadx, axis=1) / np.maximum(gn, 1.0)
+        assert err_g.max() <= tol, f"gradient rel err {err_g.max():.3e} at atom {err_g.argmax()}"
+
+
+def _check_complex(ctx, ref):
+    e, t, nt, q, vf = ctx.export()
+    assert set(map(tuple, q.tolist())) == set(map(tuple, ref.tets.tolist()))
+    assert {tuple(x): int(k) for x, k in zip(t.tolist(), nt.tolist())} == {
+        tuple(x): int(k) for x, k in zip(ref.tris.tolist(), ref.tri_ntet.tolist())}
+    assert set(map(tuple, e.tolist())) == set(map(tuple, ref.edges.tolist()))
+    assert np.array_equal(vf & 1, ref.vert_in)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,inp,nodes,chi", dg.CASES, ids=[c[0] for c in dg.CASES])
+def test_degenerate_parity(ctxs, prec, name, inp, nodes, chi):
+    xyz, rad = inp
+    print(f"case {name} {prec} n={len(rad)}", flush=True)
+    ref = oracle.run(xyz, rad, PROBE)
+    ctx = ctxs[prec]
+    area, dadx = ctx.compute(xyz, rad, PROBE)
+    _check(area, dadx, ref, TOL[prec])
+    d = ctx.diagnostics()
+    assert d["overflow"] == 0 and d["input_errors"] == 0
+    if ref.counts["ties_broken"] == 0:
+        _check_complex(ctx, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ties_go_to_the_exact_pass(ctxs, prec):
+    """Exact ties (cube corners) are left by the fast pass to the second pass,
+    which decides them exactly; the areas are exact."""
+    xyz, rad = dg.cube(2.0)
+    ref = oracle.run(xyz, rad, PROBE)
+    ctx = ctxs[prec]
+    area, dadx = ctx.compute(xyz, rad, PROBE)
+    d = ctx.diagnostics()
+    assert d["second_pass_atoms"] > 0 and d["near_ties"] > 0
+    _check(area, dadx, ref, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rotated_and_translated_ties(ctxs, prec):
+    """The lattice moved off the axes and the origin (rounded coordinates, near
+    ties instead of exact ones): same areas as the oracle."""
+    xyz, rad = dg.lattice(3, 3.0)
+    rng = np.random.default_rng(11)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    xyz = xyz @ q.T + np.array([10.3, -4.7, 2.2])
+    ref = oracle.run(xyz, rad, PROBE)
+    area, dadx = ctxs[prec].compute(xyz, rad, PROBE)
+    _check(area, dadx, ref, TOL[prec])
+
+
+@pytest.mark.parametrize("d", [1e-1, 1e-2, 1e-3])
+def test_coinciding_regular_tetrahedron(ctxs, d):
+    xyz, rad = dg.regular_tetrahedron(d)
+    ref = oracle.run(xyz, rad, PROBE)
+    area, dadx = ctxs["fp64"].compute(xyz, rad, PROBE)
+    _check(area, dadx, ref, TOL["fp64"])
+
+
+@pytest.mark.parametrize("make", [dg.tangent_pair, dg.tangent_triple])
+def test_exact_tangency(ctxs, make):
+    """Balls touching exactly: full areas; the gradient along each contact is
+    one of the two one-sided limits (0 apart, pi (R_i + R_j) overlapping)."""
+    xyz, rad = make()
+    area, dadx = ctxs["fp64"].compute(xyz, rad, 1.5)
+    assert np.allclose(area, 4 * np.pi * 9.0, rtol=0, atol=1e-9)
+    if len(rad) == 2:
+        dd = dadx[1, 0]
+        assert min(abs(dd), abs(dd - 6.0 * np.pi)) < 1e-9, dd
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_coincident_centres(ctxs, prec):
+    from paper_2401_10462_amd import _lib
+    xyz, rad = dg.coincident_smaller()
+    ref = oracle.run(xyz, rad, PROBE)
+    area, dadx = ctxs[prec].compute(xyz, rad, PROBE)
+    assert area[1] == 0.0 and np.all(dadx[1] == 0.0)
+    _check(area, dadx, ref, TOL[prec])
+    xyz, rad = dg.coincident_equal()
+    with pytest.raises(_lib.SasaError) as e:
+        ctxs[prec].compute(xyz, rad, PROBE)
+    assert e.value.code == _lib.SASA_E_INVAL
+
+
+def test_degenerate_batch_and_frames(ctxs):
+    """The tied inputs in one batch, and as consecutive frames of a trajectory
+    context: the same areas as alone."""
+    from paper_2401_10462_amd import SasaContext
+    mols = [dg.ring(h=1.09), dg.cube(2.0), dg.lattice(3, 3.0), dg.fcc(2.0)]
+    xyz = np.concatenate([m[0] + 40.0 * k for k, m in enumerate(mols)])
+    rad = np.concatenate([m[1] for m in mols])
+    offs = np.cumsum([0] + [len(m[1]) for m in mols]).astype(np.int64)
+    area, dadx = ctxs["fp64"].compute_batch(offs, xyz, rad, PROBE)
+    for k, (x, r) in enumerate(mols):
+        ref = oracle.run(x, r, PROBE)
+        sl = slice(offs[k], offs[k + 1])
+        assert np.abs(area[sl] - ref.area).max() <= 1e-9 * max(ref.area.max(), 1.0)
+        assert np.abs(dadx[sl] - ref.dadx).max() <= 1e-9 * max(np.abs(ref.dadx).max(), 1.0)
+    ctx = SasaContext(precision="fp64", frames=True)
+    try:
+        x, r = dg.lattice(3, 3.0)
+        ref = oracle.run(x, r, PROBE)
+        for _ in range(3):
+            a, g = ctx.compute(x, r, PROBE)
+            _check(a, g, ref, 1e-9)
+    finally:
+        ctx.close()

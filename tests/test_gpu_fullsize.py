@@ -1,11 +1,12 @@
 """The HIP path at the workloads' full sizes, against the FP64 oracle.
 
-* MD-like sequence: a 20,000-atom globule (chains of 2,500 atoms), frames of
-  cumulative Gaussian moves (sigma 0.02 A), SASA + forces (gamma 0.005) with the
-  state on the device -- areas and forces of whole frames vs the oracle, and
-  the dual complex of the first frame simplex for simplex;
+* MD-like sequence: a 20,000-atom globule (chains of 2,500 atoms), 500 frames
+  of cumulative Gaussian moves (sigma 0.02 A), SASA + forces (gamma 0.005) with
+  the state on the device -- areas and forces of frames 0, 100, 250 and 499 vs
+  the oracle, and the dual complex of the first frame simplex for simplex;
 * serving: requests from 200 to 20,000 atoms in one continuous-batching run,
-  each result bitwise equal to the molecule computed alone;
+  each result bitwise equal to the molecule computed alone, and 200 served
+  requests of log-uniform size checked one by one against the oracle;
 * differentiation: 64 conformations of 2,000 atoms (8 chains x 8 noise
   frames) through SASAFunction, loss sum w_i A_i with w ~ U(-1, 1), backward
   vs the oracle's VJP on sampled molecules and vs central differences.
@@ -37,18 +38,25 @@ def globule20k():
 
 
 def test_md_globule_20000(globule20k):
+    """500 frames with the state on the device (trajectory mode), checked
+    against the oracle at frames 0, 100, 250 and 499."""
     from paper_2401_10462_amd import SasaContext
     from paper_2401_10462_amd.md_loop import md_loop
     xyz, rad = globule20k
     gamma = 0.005
-    lat, kept = md_loop(xyz, rad, frames=4, sigma=0.02, gamma=gamma, precision="mixed", keep_frames=(0, 3))
-    for f, (x, area, forces) in kept.items():
-        ref = oracle.run(x, rad, 1.4)
-        assert _rel(area, ref.area).max() <= 1e-4, f
-        assert _grad_rel(forces / gamma, -ref.dadx).max() <= 1e-4, f
+    keep = (0, 100, 250, 499)
+    print("md loop: 500 frames", flush=True)
+    lat, kept = md_loop(xyz, rad, frames=500, sigma=0.02, gamma=gamma, precision="mixed", keep_frames=keep,
+                        frame_hints=True)
+    print("oracle on frames", keep, flush=True)
+    refs = dict(zip(keep, oracle.run_many([(kept[f][0], rad, 1.4) for f in keep], workers=4)))
+    for f in keep:
+        x, area, forces = kept[f]
+        assert _rel(area, refs[f].area).max() <= 1e-4, f
+        assert _grad_rel(forces / gamma, -refs[f].dadx).max() <= 1e-4, f
     # the dual complex of the first frame, simplex for simplex (FP64 predicates in both precisions)
     x0 = kept[0][0]
-    ref = oracle.run(x0, rad, 1.4)
+    ref = refs[0]
     ctx = SasaContext(precision="fp64")
     area, dadx = ctx.compute(x0, rad, 1.4)
     assert _rel(area, ref.area).max() <= 1e-9
@@ -63,7 +71,9 @@ def test_md_globule_20000(globule20k):
     ctx.close()
 
 
-def test_serving_sizes_200_to_20000(globule20k):
+def test_serving_batch_invariance_200_to_20000(globule20k):
+    """Requests of 200 to 20,000 atoms in one continuous-batching run: each
+    result bitwise equal to the molecule computed alone."""
     from paper_2401_10462_amd import SasaContext
     from paper_2401_10462_amd.server import SasaServer
     xyz, rad = globule20k
@@ -80,11 +90,28 @@ def test_serving_sizes_200_to_20000(globule20k):
         assert srv.batches < len(mols)
     for (a, g), (a0, g0) in zip(res, ref):
         assert np.array_equal(a, a0) and np.array_equal(g, g0)
-    # oracle on two of them
-    for k in (0, 5):
-        o = oracle.run(*mols[k], 1.4)
-        assert _rel(res[k][0], o.area).max() <= 1e-4
-        assert _grad_rel(res[k][1], o.dadx).max() <= 1e-4
+
+
+def test_served_requests_vs_oracle(globule20k):
+    """200 requests of log-uniform size 200..20,000 atoms (the first n atoms of
+    the globule, randomly rotated), served by the batched server, every one
+    checked against the oracle (one worker process per host core)."""
+    from paper_2401_10462_amd.server import SasaServer
+    xyz, rad = globule20k
+    rng = np.random.default_rng(40)
+    mols = []
+    for _ in range(200):
+        n = int(round(np.exp(rng.uniform(np.log(200), np.log(20000)))))
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        mols.append((np.ascontiguousarray(xyz[:n] @ q.T + rng.normal(size=3) * 10), np.ascontiguousarray(rad[:n])))
+    print(f"serving 200 requests, {sum(len(r) for _, r in mols)} atoms", flush=True)
+    with SasaServer(precision="mixed", slots=3, slot_budget_bytes=512 << 20) as srv:
+        res = [f.result(timeout=300) for f in [srv.submit(x, r) for x, r in mols]]
+    print("oracle on all 200", flush=True)
+    refs = oracle.run_many([(x, r, 1.4) for x, r in mols])
+    for k, ((a, g), o) in enumerate(zip(res, refs)):
+        assert _rel(a, o.area).max() <= 1e-4, k
+        assert _grad_rel(g, o.dadx).max() <= 1e-4, k
 
 
 def test_autograd_64_conformations_of_2000():
@@ -109,9 +136,9 @@ def test_autograd_64_conformations_of_2000():
     g = Xt.grad.cpu().numpy()
     a = A.detach().cpu().numpy()
     rng = np.random.default_rng(55)
-    for k in rng.choice(64, size=6, replace=False):
+    picks = rng.choice(64, size=6, replace=False)
+    for k, o in zip(picks, oracle.run_many([(mols[k][0], mols[k][1], 1.4) for k in picks], workers=6)):
         s = slice(offs[k], offs[k + 1])
-        o = oracle.run(mols[k][0], mols[k][1], 1.4)
         assert _rel(a[s], o.area).max() <= 1e-4
         assert _grad_rel(g[s], o.vjp(w[s])).max() <= 1e-4
     # central differences of the FP64 forward on 32 atoms, moved in all 64

@@ -14,63 +14,10 @@ import numpy as np
 import pytest
 
 import oracle
+from synth.degenerate import CASES, cube, lattice, octahedron, regular_tetrahedron, ring
 from tests.pins.slice_area import exposed_areas
 
 PROBE = 1.4
-
-
-def ring(n=6, d=1.39, r=1.7, h=None):
-    """Ideal planar ring (C6 by default); with h, a hydrogen radially outside each atom."""
-    ang = np.arange(n) * 2 * np.pi / n
-    xyz = np.stack([d * np.cos(ang), d * np.sin(ang), np.zeros(n)], 1)
-    rad = np.full(n, r)
-    if h is not None:
-        xyz = np.concatenate([xyz, np.stack([(d + h) * np.cos(ang), (d + h) * np.sin(ang), np.zeros(n)], 1)])
-        rad = np.concatenate([rad, np.full(n, 1.2)])
-    return xyz, rad
-
-
-def cube(s, r=1.7):
-    return np.array([[x, y, z] for x in (0, s) for y in (0, s) for z in (0, s)], float), np.full(8, r)
-
-
-def lattice(m, s, r=1.7):
-    g = np.array([[x, y, z] for x in range(m) for y in range(m) for z in range(m)], float) * s
-    return g, np.full(len(g), r)
-
-
-def octahedron(s, centre=False):
-    v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float) * s
-    if centre:
-        v = np.concatenate([[[0.0, 0.0, 0.0]], v])
-    return v, np.full(len(v), 1.7)
-
-
-def fcc(s):
-    p = [[x, y, z] for x in range(3) for y in range(3) for z in range(3) if (x + y + z) % 2 == 0]
-    return np.array(p, float) * s, np.full(len(p), 1.6)
-
-
-# (name, input, slice-integral nodes, expected Euler characteristic of the union of balls)
-CASES = [
-    ("C6 ring", ring(), 96, 1),
-    ("C6H6 ring", ring(h=1.09), 96, 1),
-    ("square ring, exact coordinates", (np.array([[1.5, 0, 0], [0, 1.5, 0], [-1.5, 0, 0], [0, -1.5, 0]]), np.full(4, 1.7)), 96, 1),
-    ("cube corners s=2", cube(2.0), 96, 1),
-    ("cube corners s=3", cube(3.0), 96, 1),
-    # s = 4: the cube's centre is 3.46 A from the corners, outside the 3.1 A
-    # balls, while the faces' centres (2.83 A) are covered: one cavity
-    ("cube corners s=4", cube(4.0), 96, 2),
-    ("octahedron", octahedron(2.0), 96, 1),
-    ("octahedron + centre", octahedron(2.0, True), 96, 1),
-    ("3x3x3 lattice s=2", lattice(3, 2.0), 96, 1),
-    ("3x3x3 lattice s=3", lattice(3, 3.0), 96, 1),
-    # s = 4: the centre of each of the 8 lattice cubes is 3.46 A from its
-    # corners, outside the 3.1 A balls: 8 cavities
-    ("3x3x3 lattice s=4", lattice(3, 4.0), 400, 9),
-    ("4x4x4 lattice s=2.5", lattice(4, 2.5), 96, 1),
-    ("fcc", fcc(2.0), 96, 1),
-]
 
 
 @pytest.mark.parametrize("name,inp,nodes,chi", CASES, ids=[c[0] for c in CASES])
@@ -118,10 +65,9 @@ def test_regular_tetrahedron_coinciding_limit():
     to one ball, and by symmetry each atom keeps the quarter of its sphere that
     faces its own vertex, a cone of pi sr, so A_i -> pi w_i, to first order in d."""
     w = (1.7 + PROBE) ** 2
-    unit = np.array([[1, 0, -1 / np.sqrt(2)], [-1, 0, -1 / np.sqrt(2)], [0, 1, 1 / np.sqrt(2)], [0, -1, 1 / np.sqrt(2)]])
     prev = None
     for d in (1e-1, 1e-2, 1e-3, 1e-4):
-        r = oracle.run(unit * d, np.full(4, 1.7), PROBE)
+        r = oracle.run(*regular_tetrahedron(d), PROBE)
         assert r.counts["tetrahedra"] == 1
         assert np.allclose(r.area, r.area[0], rtol=0, atol=1e-9)
         dev = r.area[0] - np.pi * w
@@ -129,8 +75,8 @@ def test_regular_tetrahedron_coinciding_limit():
         if prev is not None:
             assert 5 < prev / dev < 20  # first order: the deviation shrinks with d
         prev = dev
-    ref = exposed_areas(unit * 1e-2, np.full(4, 1.7), PROBE)
-    assert np.abs(oracle.run(unit * 1e-2, np.full(4, 1.7), PROBE).area - ref).max() < 1e-9
+    ref = exposed_areas(*regular_tetrahedron(1e-2), PROBE)
+    assert np.abs(oracle.run(*regular_tetrahedron(1e-2), PROBE).area - ref).max() < 1e-9
 
 
 def test_exact_external_tangency():
@@ -188,3 +134,28 @@ def test_gradient_at_ties_by_finite_differences(name, inp):
         errs[h] = worst
     assert errs[1e-6] < 1e-5, errs
     assert errs[1e-5] > 3 * errs[1e-6], errs
+
+
+def test_gradient_near_ties_rotated_lattice():
+    """The 3x3x3 lattice rotated and moved off the origin: rounding turns its
+    co-planar quadruples into nearly flat K-tetrahedra, whose angle terms have
+    derivatives on the branch of their (tiny) orientation.  With that sign taken
+    exactly, the analytic gradient matches central differences of the slice
+    integral (no triangulation involved); a face-centre atom's gradient is 0
+    by symmetry."""
+    xyz, rad = lattice(3, 3.0)
+    rng = np.random.default_rng(11)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    xyz = xyz @ q.T + np.array([10.3, -4.7, 2.2])
+    r = oracle.run(xyz, rad, PROBE)
+    assert np.abs(r.area - exposed_areas(xyz, rad, PROBE, nodes=200)).max() < 1e-9
+    h = 1e-6
+    for m in (22, 4, 0):
+        fd = np.zeros(3)
+        for c in range(3):
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[m, c] += h
+            xm[m, c] -= h
+            fd[c] = (exposed_areas(xp, rad, PROBE, nodes=200).sum() - exposed_areas(xm, rad, PROBE, nodes=200).sum()) / (2 * h)
+        assert np.abs(r.dadx[m] - fd).max() < 1e-5, (m, r.dadx[m], fd)
+    assert np.linalg.norm(r.dadx[22]) < 1e-9
