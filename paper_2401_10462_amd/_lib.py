@@ -74,6 +74,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2401_10462_amd/build.py "
                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    from . import build as _build
+    if os.path.abspath(LIB_PATH) == os.path.abspath(_build.LIB) and _build.stale():
+        raise ImportError(f"{LIB_PATH} was built from other sources than the ones in this tree: rebuild it "
+                          "with paper_2401_10462_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.sasa_create.argtypes = [ctypes.POINTER(sasa_options), ctypes.POINTER(P)]

@@ -1,4 +1,5 @@
 """Build the HIP library (gfx950) into paper_2401_10462_amd/libsasa_hip.so."""
+import hashlib
 import os
 import subprocess
 
@@ -7,7 +8,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsasa_hip.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "volume.hip", "sorted_extract.hip", "api.hip")]
-HEADERS = [os.path.join(CSRC, "sasa_internal.h"), os.path.join(INCLUDE, "sasa.h")]
+HEADERS = [os.path.join(CSRC, "sasa_internal.h"), os.path.join(CSRC, "exact_side.h"), os.path.join(INCLUDE, "sasa.h")]
+# SHA-256 of the sources and flags the library was built from (written beside it)
+HASH = LIB + ".srchash"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -23,11 +26,23 @@ FLAGS = [
 ]
 
 
+def source_hash():
+    """Digest of every source and header and of the compiler flags."""
+    h = hashlib.sha256()
+    for p in SOURCES + HEADERS:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(f for f in FLAGS if not os.path.isabs(f)).encode())  # (the tree may move)
+    return h.hexdigest()
+
+
 def stale():
-    if not os.path.exists(LIB):
+    """True if the library is missing or was built from other sources."""
+    if not os.path.exists(LIB) or not os.path.exists(HASH):
         return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
+    with open(HASH) as f:
+        return f.read().strip() != source_hash()
 
 
 def build(force=True, verbose=False):
@@ -42,6 +57,8 @@ def build(force=True, verbose=False):
     if verbose:
         print(res.stderr)
     os.replace(tmp, LIB)
+    with open(HASH, "w") as f:
+        f.write(source_hash() + "\n")
     return LIB
 
 

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -78,6 +79,20 @@ int fail(Ctx* c, int code, const std::string& msg) {
     }                                                                                   \
   } while (0)
 
+// Allocation failure injection for the tests of the capacity bookkeeping:
+// with SASA_TEST_FAIL_ALLOC=k in the environment, the k-th buffer allocation
+// from then on (counted per process) reports out-of-memory without calling
+// the allocator.
+bool injected_alloc_failure() {
+  static long counter = 0;
+  const char* v = std::getenv("SASA_TEST_FAIL_ALLOC");
+  if (!v || !*v) {
+    counter = 0;
+    return false;
+  }
+  return ++counter == std::atol(v);
+}
+
 template <typename T>
 hipError_t grow(T** p, size_t count) {
   if (*p) {
@@ -85,13 +100,20 @@ hipError_t grow(T** p, size_t count) {
     *p = nullptr;
     if (e != hipSuccess) return e;
   }
+  if (count && injected_alloc_failure()) return hipErrorOutOfMemory;
   return count ? hipMalloc((void**)p, count * sizeof(T)) : hipSuccess;
 }
 
+// Each group of buffers records its capacity only once all of them exist: a
+// grow frees a buffer before allocating its replacement, so the capacity is
+// zeroed first, and an allocation that fails part-way leaves 0 behind and the
+// next call grows the whole group again (never writing through a freed or
+// missing buffer).
 int ensure(Ctx* c, int64_t n, int nmol) {
   Bufs& b = c->b;
   if (n > c->cap_n) {
     const int64_t cap = std::max<int64_t>(n, c->cap_n + c->cap_n / 2);
+    c->cap_n = 0;
     HIP_TRY(c, grow(&b.pos, cap));
     HIP_TRY(c, grow(&b.mol, cap));
     HIP_TRY(c, grow(&b.cellid, cap));
@@ -125,6 +147,7 @@ int ensure(Ctx* c, int64_t n, int nmol) {
   const int64_t cells = cell_capacity(n);
   if (cells > c->cap_cells) {
     const int64_t cap = std::max<int64_t>(cells, c->cap_cells + c->cap_cells / 2);
+    c->cap_cells = 0;
     HIP_TRY(c, grow(&b.cnt, cap));
     HIP_TRY(c, grow(&b.start, (size_t)cap + 1));
     HIP_TRY(c, grow(&b.scan_tmp, (size_t)scan_blocks((unsigned)cap) + 1));
@@ -133,6 +156,7 @@ int ensure(Ctx* c, int64_t n, int nmol) {
   b.cell_cap = (int)cells;
   if (nmol + 1 > c->cap_mol) {
     const int cap = std::max(nmol + 1, 2 * c->cap_mol);
+    c->cap_mol = 0;
     HIP_TRY(c, grow(&c->off_d, cap));
     HIP_TRY(c, grow(&b.mol_box, (size_t)cap * 6));
     HIP_TRY(c, grow(&b.mol_geo, cap));
@@ -542,6 +566,7 @@ int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t 
   const int64_t nfaces = 4 * cnt[3], cap_free = cnt[6];
   if (nfaces > c->sf_cap_faces || cap_free > c->sf_cap_free) {
     const int64_t nf = std::max<int64_t>(nfaces, 1), nz = std::max<int64_t>(cap_free, 1);
+    c->sf_cap_faces = c->sf_cap_free = -1;  // set again once every buffer exists
     HIP_TRY(c, grow(&w.faces, nf));
     HIP_TRY(c, grow(&w.sorted, nf));
     HIP_TRY(c, grow(&w.uniq, nf));
@@ -553,6 +578,7 @@ int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t 
     if (!w.cursors) HIP_TRY(c, grow(&w.cursors, 2));
     const size_t tb = sorted_faces_temp_bytes(nf);
     if (tb > w.temp_bytes) {
+      w.temp_bytes = 0;
       HIP_TRY(c, grow((char**)&w.temp, tb));
       w.temp_bytes = tb;
     }
@@ -629,15 +655,18 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   HIP_TRY(c, hipSetDevice(c->device));
   Bufs& B = c->b;
   if (cnt[1] > c->ex_cap_e) {
+    c->ex_cap_e = 0;
     HIP_TRY(c, grow(&B.ex_edges, (size_t)cnt[1] * 2));
     c->ex_cap_e = cnt[1];
   }
   if (cnt[2] > c->ex_cap_t) {
+    c->ex_cap_t = 0;
     HIP_TRY(c, grow(&B.ex_tris, (size_t)cnt[2] * 3));
     HIP_TRY(c, grow(&B.ex_ntet, (size_t)cnt[2]));
     c->ex_cap_t = cnt[2];
   }
   if (cnt[3] > c->ex_cap_q) {
+    c->ex_cap_q = 0;
     HIP_TRY(c, grow(&B.ex_tets, (size_t)cnt[3] * 4));
     c->ex_cap_q = cnt[3];
   }

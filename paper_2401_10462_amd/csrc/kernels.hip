@@ -1861,6 +1861,11 @@ __device__ inline T norm(V3<T> a) {
   return sqrt(dot(a, a));
 }
 
+template <typename T>
+__device__ inline V3<double> dbl3(V3<T> a) {
+  return {(double)a.x, (double)a.y, (double)a.z};
+}
+
 __device__ inline float tatan2(float y, float x) { return atan2f(y, x); }
 __device__ inline double tatan2(double y, double x) { return atan2(y, x); }
 
@@ -1951,32 +1956,27 @@ template <typename T>
 __device__ double tet_item(const TermsLds& L, const int ks[3], int osg, unsigned long long extm, double Si, bool grad,
                            double phi[3], double acc_out[3][3]) {
   const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
-  V3<T> acc[3];
   // The vertex term 4 pi w_i omega is the largest single term and cancels
   // against its neighbours' for nearly buried atoms: its solid angle is always
-  // evaluated in double.
-  V3<double> g[3];
+  // evaluated in double, and every contribution is summed in double.
+  V3<double> g[3], acc[3];
   const double om = solid_angle<double>(ld<double>(L, ks[0]), ld<double>(L, ks[1]), ld<double>(L, ks[2]), &g[0],
                                         &g[1], &g[2], grad, osg);
-  for (int c = 0; c < 3; ++c) acc[c] = V3<T>{T(-Si * g[c].x), T(-Si * g[c].y), T(-Si * g[c].z)};
+  for (int c = 0; c < 3; ++c) acc[c] = g[c] * (-Si);
   for (int c = 0; c < 3; ++c) {
     const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
     V3<T> ge, g1, g2;
     const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad, osg);  // cyclic: same orientation
     phi[c] = (double)ph;
     if (grad && ((extm >> ks[c]) & 1ull)) {
-      const T Se = T(L.S[ks[c]]);
-      acc[c] = acc[c] + ge * Se;
-      acc[o1] = acc[o1] + g1 * Se;
-      acc[o2] = acc[o2] + g2 * Se;
+      const double Se = L.S[ks[c]];
+      acc[c] = acc[c] + dbl3(ge) * Se;
+      acc[o1] = acc[o1] + dbl3(g1) * Se;
+      acc[o2] = acc[o2] + dbl3(g2) * Se;
     }
   }
   if (grad)
-    for (int c = 0; c < 3; ++c) {
-      acc_out[c][0] = (double)acc[c].x;
-      acc_out[c][1] = (double)acc[c].y;
-      acc_out[c][2] = (double)acc[c].z;
-    }
+    for (int c = 0; c < 3; ++c) acc_out[c][0] = acc[c].x, acc_out[c][1] = acc[c].y, acc_out[c][2] = acc[c].z;
   return om;
 }
 
@@ -1990,32 +1990,35 @@ __device__ double tri_item(const TermsLds& L, int ka, int kb, double X0, double 
                            double Si, bool grad, double G[2][3]) {
   const V3<T> X = {T(X0), T(X1), T(X2)};
   const V3<T> A = ld<T>(L, ka), B = ld<T>(L, kb);
-  const T Rt = T(Ri);
-  V3<T> gSa, gSb, g1e, g1u, g1v, g2e, g2u, g2v, gwa, gwb, gwx;
-  const T Sa = cap_area<T>(A, Rt, T(L.pR[ka]), &gSa, grad);
-  const T Sb = cap_area<T>(B, Rt, T(L.pR[kb]), &gSb, grad);
+  V3<T> g1e, g1u, g1v, g2e, g2u, g2v;
+  // caps in double: they multiply the angles' derivatives, and a buried atom's
+  // area is the small difference of many of them
+  V3<double> gSa, gSb;
+  const double Sa = cap_area<double>(ld<double>(L, ka), Ri, L.pR[ka], &gSa, grad);
+  const double Sb = cap_area<double>(ld<double>(L, kb), Ri, L.pR[kb], &gSb, grad);
   const T ph1 = dihedral<T>(A, B, X, &g1e, &g1u, &g1v, grad);  // along (i,a)
   const T ph2 = dihedral<T>(B, A, X, &g2e, &g2u, &g2v, grad);  // along (i,b)
   // solid angle in double, as in tet_item
   V3<double> hwa, hwb, hwx;
   const double om = solid_angle<double>(ld<double>(L, ka), ld<double>(L, kb), V3<double>{X0, X1, X2}, &hwa, &hwb,
                                         &hwx, grad);
-  const double St = 2.0 * ((double)(ph1 * Sa) + (double)(ph2 * Sb) - om * Si);
+  const double p1 = (double)ph1, p2 = (double)ph2;
+  const double St = 2.0 * (p1 * Sa + p2 * Sb - om * Si);
   if (grad) {
-    gwa = V3<T>{T(Si * hwa.x), T(Si * hwa.y), T(Si * hwa.z)};
-    gwb = V3<T>{T(Si * hwb.x), T(Si * hwb.y), T(Si * hwb.z)};
-    gwx = V3<T>{T(Si * hwx.x), T(Si * hwx.y), T(Si * hwx.z)};
-    V3<T> dA = g1e * Sa + gSa * ph1 + g2u * Sb - gwa;
-    V3<T> dB = g1u * Sa + g2e * Sb + gSb * ph2 - gwb;
-    const V3<T> dX = g1v * Sa + g2v * Sb - gwx;
-    const V3<T> r0 = X, r1 = X - A, r2 = X - B;
-    const V3<T> c0 = cross(r1, r2), c1 = cross(r2, r0), c2 = cross(r0, r1);
-    const T idet = T(1) / dot(r0, c0);
-    const T l1 = dot(c1, dX) * idet, l2 = dot(c2, dX) * idet;
+    // the angles' derivatives in T; the caps, the sums, the solid angle's
+    // share and the chain rule through x in double (M^-T amplifies rounding)
+    V3<double> dA = dbl3(g1e) * Sa + gSa * p1 + dbl3(g2u) * Sb - hwa * Si;
+    V3<double> dB = dbl3(g1u) * Sa + dbl3(g2e) * Sb + gSb * p2 - hwb * Si;
+    const V3<double> dX = dbl3(g1v) * Sa + dbl3(g2v) * Sb - hwx * Si;
+    const V3<double> Xd = {X0, X1, X2};
+    const V3<double> r0 = Xd, r1 = Xd - ld<double>(L, ka), r2 = Xd - ld<double>(L, kb);
+    const V3<double> c0 = cross(r1, r2), c1 = cross(r2, r0), c2 = cross(r0, r1);
+    const double idet = 1.0 / dot(r0, c0);
+    const double l1 = dot(c1, dX) * idet, l2 = dot(c2, dX) * idet;
     dA = dA + r1 * l1;
     dB = dB + r2 * l2;
-    G[0][0] = 2.0 * (double)dA.x, G[0][1] = 2.0 * (double)dA.y, G[0][2] = 2.0 * (double)dA.z;
-    G[1][0] = 2.0 * (double)dB.x, G[1][1] = 2.0 * (double)dB.y, G[1][2] = 2.0 * (double)dB.z;
+    G[0][0] = 2.0 * dA.x, G[0][1] = 2.0 * dA.y, G[0][2] = 2.0 * dA.z;
+    G[1][0] = 2.0 * dB.x, G[1][1] = 2.0 * dB.y, G[1][2] = 2.0 * dB.z;
   }
   return St;
 }
@@ -2029,9 +2032,13 @@ __device__ inline double tet_quality(double ax, double ay, double az, double bx,
   return fabs(tp) / l;
 }
 
-// In MIXED precision, items below these qualities are evaluated in double.
-constexpr double kTetQualityMin = 0.05;
-constexpr double kTripleDepthMin = 0.02;  // -s_t / w_i: triple points close to the centres' plane
+// In MIXED precision, items below these qualities are evaluated in double:
+// a float dihedral derivative is off by about u_f S / (|u| sin^2 theta) for a
+// wing at angle theta to the edge, and the quality bounds sin theta from below
+// (0.2 keeps the largest gradient error of the drifted 20,000-atom MD frames
+// near 5e-5 of the 1e-4 bar; 0.05 reached 1.3e-4).
+constexpr double kTetQualityMin = 0.2;
+constexpr double kTripleDepthMin = 0.1;  // -s_t / w_i: triple points close to the centres' plane
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
@@ -2066,15 +2073,16 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   for (int t = lane; t < nt; t += 64) L.tet[t] = b.ktet[(size_t)i * KT_CAP + t];
   for (int t = lane; t < nr; t += 64) L.tri[t] = b.ktri[(size_t)i * KTR_CAP + t];
   __syncthreads();
-  const T Rt = T(Ri);
   const double Si = 4.0 * kPi * wi;
-  // edges: cap areas
-  V3<T> gS = {T(0), T(0), T(0)};
+  // edges: cap areas, in double in both precisions (they multiply the
+  // dihedral angles and their derivatives, and a buried atom's area is the
+  // small difference of many of them)
+  V3<double> gS = {0.0, 0.0, 0.0};
   double Sk = 0.0;
   const int k = lane;  // one K-neighbour per lane (KN_CAP = 64)
   const bool kext = k < nk && ((extm >> k) & 1ull);
   if (kext) {
-    Sk = (double)cap_area<T>(ld<T>(L, k), Rt, T(L.pR[k]), &gS, grad);
+    Sk = cap_area<double>(ld<double>(L, k), Ri, L.pR[k], &gS, grad);
     L.S[k] = Sk;
   }
   __syncthreads();
@@ -2123,9 +2131,9 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   if (kext) {
     const double Phi = 1.0 - phi_sum;
     area_part -= Phi * Sk;
-    gx -= Phi * (double)gS.x;
-    gy -= Phi * (double)gS.y;
-    gz -= Phi * (double)gS.z;
+    gx -= Phi * gS.x;
+    gy -= Phi * gS.y;
+    gz -= Phi * gS.z;
   }
   // exterior triangles: Eq. 6 through the triple point, in chunks of 64
   for (int c0 = 0; c0 < nr; c0 += 64) {

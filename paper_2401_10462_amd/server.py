@@ -28,14 +28,21 @@ from .context import SasaContext
 
 
 class Request:
-    __slots__ = ("xyz", "radii", "future", "arrival", "t_admit", "t_done", "n")
+    __slots__ = ("xyz", "radii", "future", "arrival", "t_admit", "t_done", "n", "solo")
 
     def __init__(self, xyz, radii, arrival):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         self.radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
         if self.xyz.shape[0] != self.radii.shape[0]:
             raise ValueError("xyz and radii disagree on the atom count")
+        # checked here so that a bad request is refused alone, before it can
+        # share a batch with others
+        if not np.all(np.isfinite(self.xyz)):
+            raise ValueError("non-finite coordinate")
+        if not np.all(np.isfinite(self.radii) & (self.radii > 0)):
+            raise ValueError("radii must be finite and > 0")
         self.n = self.radii.shape[0]
+        self.solo = False  # set when a batch that held it failed: it then runs alone
         self.future = Future()
         self.arrival = arrival
         self.t_admit = None
@@ -132,6 +139,8 @@ class SasaServer:
     def stop(self, drain=True):
         if drain:
             while not (self._inbox.empty() and not self._q and all(not s.reqs for s in self._slots)):
+                if self._thread is None or not self._thread.is_alive():
+                    break
                 time.sleep(1e-3)
         self._stop.set()
         self._wake.set()
@@ -148,10 +157,15 @@ class SasaServer:
 
     # ----------------------------------------------------------- scheduler
     def _admit(self):
-        """Requests for one batch: FIFO while the footprint fits the slot budget."""
+        """Requests for one batch: FIFO while the footprint fits the slot budget
+        (a request whose batch failed before runs alone)."""
         batch, atoms = [], 0
         while self._q:
             r = self._q[0]
+            if r.solo or (batch and batch[0].solo):
+                if not batch:
+                    batch.append(self._q.popleft())
+                break
             need = _lib.sasa_footprint(atoms + r.n)
             if batch and (need > self.budget or (self.max_req and len(batch) >= self.max_req)):
                 break
@@ -161,7 +175,32 @@ class SasaServer:
                 break
         return batch
 
+    def _fail_or_split(self, reqs, err):
+        """A failed batch of several requests goes back to the front of the
+        queue one request at a time (only an offending request then fails); a
+        request that fails alone gets the error."""
+        if len(reqs) > 1:
+            for r in reversed(reqs):
+                r.solo = True
+                self._q.appendleft(r)
+        else:
+            for r in reqs:
+                r.future.set_exception(err)
+            self.errors.append(err)
+
     def _loop(self):
+        try:
+            self._serve()
+        except BaseException as e:  # never leave a caller waiting on a dead scheduler
+            pending = list(self._q) + [r for s in self._slots for r in s.reqs]
+            while not self._inbox.empty():
+                pending.append(self._inbox.get())
+            for r in pending:
+                if not r.future.done():
+                    r.future.set_exception(e)
+            self.errors.append(e)
+
+    def _serve(self):
         if self._cuda:
             torch.cuda.set_device(self.device)
         while not self._stop.is_set():
@@ -178,11 +217,9 @@ class SasaServer:
                         self.completed.extend(reqs)  # recorded before any caller is woken
                         for r, res in zip(reqs, results):
                             r.future.set_result(res)
-                    except Exception as e:  # deliver the error to every request of the batch
-                        for r in s.reqs:
-                            r.future.set_exception(e)
-                        self.errors.append(e)
-                        s.reqs = []
+                    except Exception as e:
+                        reqs, s.reqs = s.reqs, []
+                        self._fail_or_split(reqs, e)
                     progressed = True
             for s in self._slots:
                 if not s.reqs and self._q:
@@ -190,7 +227,11 @@ class SasaServer:
                     now = time.perf_counter()
                     for r in batch:
                         r.t_admit = now
-                    s.launch(batch)
+                    try:
+                        s.launch(batch)
+                    except Exception as e:  # e.g. no device memory for a request run alone
+                        s.reqs = []
+                        self._fail_or_split(batch, e)
                     self.batches += 1
                     progressed = True
             if not progressed:

@@ -52,6 +52,10 @@ def test_md_globule_20000(globule20k):
     refs = dict(zip(keep, oracle.run_many([(kept[f][0], rad, 1.4) for f in keep], workers=4)))
     for f in keep:
         x, area, forces = kept[f]
+        print(f"frame {f}: area err {_rel(area, refs[f].area).max():.2e}, "
+              f"force err {_grad_rel(forces / gamma, -refs[f].dadx).max():.2e}", flush=True)
+    for f in keep:
+        x, area, forces = kept[f]
         assert _rel(area, refs[f].area).max() <= 1e-4, f
         assert _grad_rel(forces / gamma, -refs[f].dadx).max() <= 1e-4, f
     # the dual complex of the first frame, simplex for simplex (FP64 predicates in both precisions)
@@ -109,6 +113,9 @@ def test_served_requests_vs_oracle(globule20k):
         res = [f.result(timeout=300) for f in [srv.submit(x, r) for x, r in mols]]
     print("oracle on all 200", flush=True)
     refs = oracle.run_many([(x, r, 1.4) for x, r in mols])
+    ea = max(_rel(a, o.area).max() for (a, g), o in zip(res, refs))
+    eg = max(_grad_rel(g, o.dadx).max() for (a, g), o in zip(res, refs))
+    print(f"largest error over the 200 requests: area {ea:.2e}, gradient {eg:.2e}", flush=True)
     for k, ((a, g), o) in enumerate(zip(res, refs)):
         assert _rel(a, o.area).max() <= 1e-4, k
         assert _grad_rel(g, o.dadx).max() <= 1e-4, k
