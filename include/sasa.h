@@ -256,6 +256,27 @@ int sasa_footprint(int64_t n, int64_t* bytes);
 /* Fixed per-atom kernel capacities: [0] overlapping neighbours, [1] cell vertices. */
 void sasa_capacity(int64_t caps[2]);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sasa_compute
+ * of one molecule of at most SASA_NOALLOC_MAX_ATOMS atoms, all work space in
+ * one fixed 16 MiB array of the library's device code (each GPU the library
+ * runs on holds it until the process ends).  No context; nothing is kept, so
+ * there is no sasa_backward or export afterwards.
+ *   device      HIP ordinal (made current for the call, restored after)
+ *   xyz, radii  device pointers, as in sasa_compute
+ *   area        n doubles out (device) or NULL;  dA_dx n*3 doubles out (device) or NULL
+ *   precision   SASA_FP64 or SASA_MIXED;  hip_stream: the caller's stream (NULL: default)
+ * Synchronous: waits for the stream and returns SASA_E_INVAL (as sasa_compute,
+ * also for n > SASA_NOALLOC_MAX_ATOMS), SASA_E_CAPACITY or SASA_E_DEVICE.  It
+ * calls no allocator.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.
+ */
+#define SASA_NOALLOC_MAX_ATOMS 4096
+int sasa_compute_noalloc(int device, int64_t n, const double* xyz, const double* radii, double probe,
+                         double* area, double* dA_dx, int precision, void* hip_stream);
+
 const char* sasa_strerror(int32_t code);
 const char* sasa_last_error(void* ctx);
 

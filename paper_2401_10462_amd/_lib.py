@@ -31,6 +31,7 @@ EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
     "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export",
     "sasa_diagnostics", "sasa_status", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
+    "sasa_compute_noalloc",
 )
 
 
@@ -97,6 +98,7 @@ def load():
     L.sasa_footprint.argtypes = [I64, P]
     L.sasa_footprint.restype = ctypes.c_int
     L.sasa_capacity.argtypes = [P]
+    L.sasa_compute_noalloc.argtypes = [I32, I64, P, P, D, P, P, I32, P]
     L.sasa_capacity.restype = None
     L.sasa_strerror.argtypes = [I32]
     L.sasa_strerror.restype = ctypes.c_char_p
@@ -113,7 +115,7 @@ def load():
 def check(rc, ctx=None):
     if rc != SASA_OK:
         L = load()
-        msg = L.sasa_last_error(ctx).decode() if ctx is not None else L.sasa_strerror(rc).decode()
+        msg = L.sasa_last_error(ctx).decode()  # (a NULL context: the thread's last message)
         raise SasaError(rc, msg or L.sasa_strerror(rc).decode())
     return rc
 
@@ -166,6 +168,18 @@ def sasa_compute(ctx, n, xyz, radii, probe, area, dA_dx, mem=None, stream=None):
     stream = stream_of(arrs) if stream is None else stream
     return check(load().sasa_compute(ctx, int(n), ptr(xyz), ptr(radii), float(probe), ptr(area), ptr(dA_dx),
                                      mem, stream), ctx)
+
+
+SASA_NOALLOC_MAX_ATOMS = 4096
+
+
+def sasa_compute_noalloc(device, n, xyz, radii, probe, area, dA_dx, precision=SASA_FP64, stream=None):
+    """One molecule of at most SASA_NOALLOC_MAX_ATOMS atoms on device buffers, with
+    the library's fixed work space (no device allocation)."""
+    arrs = (xyz, radii, area, dA_dx)
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_compute_noalloc(int(device), int(n), ptr(xyz), ptr(radii), float(probe), ptr(area),
+                                             ptr(dA_dx), int(precision), stream), None)
 
 
 def sasa_compute_batch(ctx, offsets, xyz, radii, probe, area, dA_dx, mem=None, stream=None):

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -758,3 +759,152 @@ const char* sasa_last_error(void* ctx) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ no allocation
+// sasa_compute_noalloc's work space: one fixed array in the library's device
+// code (allocated on each GPU when the code is loaded there, held until the
+// process ends).  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// ever handed to kernels.
+namespace {
+constexpr size_t kNoAllocBytes = (size_t)16 << 20;  // 16 MiB: SASA_NOALLOC_MAX_ATOMS atoms with room to spare
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kMaxDevices] = {};
+
+// Consecutive 256-byte-aligned arrays carved from a base address (with a null
+// base it only counts the bytes).
+struct Carve {
+  unsigned char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// The buffers of a one-molecule compute of n atoms; returns the bytes used.
+size_t noalloc_layout(unsigned char* base, int64_t n, Bufs& b, double** area_ws, unsigned long long** status) {
+  Carve c{base};
+  const size_t N = (size_t)n;
+  const int64_t cells = cell_capacity(n);
+  b.pos = c.take<double4>(N);
+  b.mol = c.take<int>(N);
+  b.cellid = c.take<int>(N);
+  b.offsets = c.take<int64_t>(2);  // (not read by the one-block cell list)
+  b.mol_box = c.take<unsigned long long>(6);
+  b.mol_geo = c.take<double4>(1);
+  b.mol_dim = c.take<int4>(1);
+  b.cnt = c.take<int>((size_t)cells);
+  b.start = c.take<int>((size_t)cells + 1);
+  b.scan_tmp = c.take<int>((size_t)scan_blocks((unsigned)cells) + 1);
+  b.sorted = c.take<int>(N);
+  b.spos = c.take<double4>(N);
+  b.smc = c.take<int2>(N);
+  b.vflag = c.take<uint8_t>(N);
+  b.kn_cnt = c.take<int>(N);
+  b.knbr = c.take<int>(N * KN_CAP);
+  b.kn_ext = c.take<unsigned long long>(N);
+  b.kt_cnt = c.take<int>(N);
+  b.ktet = c.take<unsigned>(N * KT_CAP);
+  b.ktr_cnt = c.take<int>(N);
+  b.ktri = c.take<unsigned>(N * KTR_CAP);
+  b.stat = c.take<int>(N * STAT_STRIDE);
+  b.wide = c.take<int>(N);
+  b.rows = c.take<double>(N * ROW * 3);
+  b.ctr = c.take<unsigned long long>((size_t)C_COUNT * CTR_STRIDE);
+  *area_ws = c.take<double>(N);
+  *status = c.take<unsigned long long>(3);
+  return c.off;
+}
+
+}  // namespace
+
+extern "C" int sasa_compute_noalloc(int device, int64_t n, const double* xyz, const double* radii, double probe,
+                                    double* area, double* dA_dx, int precision, void* hip_stream) {
+  if (n < 0) return fail(nullptr, SASA_E_INVAL, "n < 0");
+  if (n > SASA_NOALLOC_MAX_ATOMS)
+    return fail(nullptr, SASA_E_INVAL, "n exceeds SASA_NOALLOC_MAX_ATOMS (the fixed work space of this entry point)");
+  if (n > 0 && (!xyz || !radii)) return fail(nullptr, SASA_E_INVAL, "xyz / radii must not be NULL");
+  if (!(probe >= 0.0) || !std::isfinite(probe)) return fail(nullptr, SASA_E_INVAL, "probe must be finite and >= 0");
+  if (precision != SASA_FP64 && precision != SASA_MIXED)
+    return fail(nullptr, SASA_E_INVAL, "precision must be SASA_FP64 or SASA_MIXED");
+  if (device < 0 || device >= kMaxDevices) return fail(nullptr, SASA_E_INVAL, "bad device ordinal");
+  if (n == 0) return SASA_OK;
+  int prev = 0;
+  HIP_TRY(nullptr, hipGetDevice(&prev));
+  if (prev != device) HIP_TRY(nullptr, hipSetDevice(device));
+  int rc = SASA_OK;
+  do {
+    unsigned char* base = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(g_noalloc_mu);
+      if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+          rc = fail(nullptr, SASA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+          break;
+        }
+        g_noalloc_ptr[device] = (unsigned char*)p;
+      }
+      base = g_noalloc_ptr[device];
+    }
+    Bufs b;
+    double* area_ws = nullptr;
+    unsigned long long* status = nullptr;
+    if (noalloc_layout(nullptr, n, b, &area_ws, &status) > kNoAllocBytes) {
+      rc = fail(nullptr, SASA_E_INVAL, "n does not fit the fixed work space");
+      break;
+    }
+    noalloc_layout(base, n, b, &area_ws, &status);
+    b.n = (int)n;
+    b.nmol = 1;
+    b.cell_cap = (int)cell_capacity(n);
+    b.xyz = xyz;
+    b.radii = radii;
+    b.probe = probe;
+    b.area = area ? area : area_ws;
+    b.status = status;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // k_cells_one clears the counters (everything else is written before it
+    // is read); the last call's contents are never used
+    launch_cells_one(b, s);
+    launch_star(b, s);
+    launch_star_wide(b, s);
+    launch_terms(b, precision, dA_dx != nullptr, s);
+    if (dA_dx) launch_gather(b, nullptr, dA_dx, 1.0, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      rc = fail(nullptr, SASA_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+      break;
+    }
+    unsigned long long st[3] = {0, 0, 0};
+    e = hipMemcpyAsync(st, status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = fail(nullptr, SASA_E_DEVICE, std::string("status read: ") + hipGetErrorString(e));
+      break;
+    }
+    if (st[2] != 1ull) {
+      rc = fail(nullptr, SASA_E_DEVICE, "the call's status words were not written");
+    } else if (st[0]) {
+      rc = fail(nullptr, SASA_E_INVAL,
+                "NaN/Inf coordinate, radius <= 0, or two atoms with the same centre and radius in the input");
+    } else if (st[1]) {
+      rc = fail(nullptr, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
+    }
+  } while (false);
+  if (prev != device) hipSetDevice(prev);
+  return rc;
+}
