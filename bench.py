@@ -222,12 +222,19 @@ def measured_traffic():
     return rec["bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
 
 
-def cpu_baseline(xyz, rad, budget, area=None, dadx=None):
+def cpu_baseline(xyz, rad, budget, area=None, dadx=None, all_cores=True):
     """FP64 oracle on the host: whole molecule, repeated up to the time budget.
 
-    The timed leg also yields the oracle's result for this molecule, so the
-    error of the GPU result just measured is reported beside it (per atom,
-    relative to max(|ref|, 1 A^2) or max(|ref|, 1 A^2/A)).
+    The oracle is the plain brute-force reference of the tests (every candidate
+    simplex of each atom's overlapping neighbours decided from its definition,
+    O(n k^3), with dual-number Jacobians), built -O3 for x86-64-v3: a baseline
+    of that code, not of a tuned CPU implementation of the method.  The timed
+    leg also yields the oracle's result for this molecule, so the error of the
+    GPU result just measured is reported beside it (per atom, relative to
+    max(|ref|, 1 A^2) or max(|ref|, 1 A^2/A)).  The all-core leg runs one
+    worker process per host core (at most 16, the host share of one GPU) on as
+    many distinct conformations of the molecule (Gaussian moves, sigma 0.02 A):
+    molecules are independent, so that is the fair multi-core form.
     """
     import oracle
     oracle.lib()
@@ -241,12 +248,23 @@ def cpu_baseline(xyz, rad, budget, area=None, dadx=None):
         if el > budget or runs >= 8:
             break
     out = {"value": runs * len(rad) / el, "unit": "atoms/s", "cores": 1, "kind": "oracle",
-           "sample": f"{runs} full run(s) of the {len(rad)}-atom molecule (SASA + dA/dx, FP64, one thread)",
+           "sample": f"{runs} full run(s) of the {len(rad)}-atom molecule (SASA + dA/dx, FP64, one thread; "
+                     "brute-force oracle)",
            "seconds": el, "host_cpus": os.cpu_count()}
     if area is not None:
         out["max_rel_err_area"] = float((np.abs(area - ref.area) / np.maximum(ref.area, 1.0)).max())
         gn = np.linalg.norm(ref.dadx, axis=1)
         out["max_rel_err_grad"] = float((np.linalg.norm(dadx - ref.dadx, axis=1) / np.maximum(gn, 1.0)).max())
+    if all_cores:
+        from synth.globule import md_frames
+        P = max(1, min(16, os.cpu_count() or 1))
+        confs = [(x, rad, 1.4) for x in md_frames(xyz, 77, P)]
+        ta = time.perf_counter()
+        oracle.run_many(confs, workers=P)
+        ea = time.perf_counter() - ta
+        out["all_cores"] = {"value": P * len(rad) / ea, "unit": "atoms/s", "cores": P, "seconds": ea,
+                            "sample": f"{P} distinct conformations of the {len(rad)}-atom molecule, one worker "
+                                      "process per core (process start included)"}
     return out
 
 
@@ -453,6 +471,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gpu_over_cpu": (value / cpu["value"]) if cpu else None,
+        "gpu_over_cpu_all_cores": (value / cpu["all_cores"]["value"]) if cpu and "all_cores" in cpu else None,
         "diagnostics": {k: diag[k] for k in ("max_neighbours", "max_cell_vertices", "near_ties", "lost_pairs",
                                              "overflow", "plane_tests", "new_vertices", "candidates",
                                              "planes_used", "max_planes_used", "atoms_over_64_planes",
