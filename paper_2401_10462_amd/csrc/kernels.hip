@@ -631,6 +631,9 @@ __device__ inline double rdl(double v, int l) {
 }
 __device__ inline int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// The clipping's security-radius test is made at every this many slots.
+constexpr int kSecurityStride = 16;
+
 // Lowers the ranking key of a neighbour that was a facet in the previous frame
 // (plane distances are a few Angstrom; the shifted keys keep their order to
 // well below 1e-9 A, and exact ties fall back to the atom id).
@@ -849,14 +852,14 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     for (int h2 = 0; h2 < 4; ++h2) {
       const int f = base + 64 * h2 + lane;
       j[h2] = -1;
-      if (f < total) {
-        int d = 0;
+      // its row: the last of lanes 0..31 whose first flat index is <= f (the
+      // starts ascend; lanes 25..31 start at total), by binary search
+      int r = 0;
 #pragma unroll
-        for (int r = 0; r < 25; ++r) {
-          const int sr = __builtin_amdgcn_readlane(row_s, r);
-          const int dr = __builtin_amdgcn_readlane(row_d, r);
-          if (sr <= f) d = dr;
-        }
+      for (int step = 16; step >= 1; step >>= 1)
+        if (__shfl(row_s, r + step, 64) <= f) r += step;
+      const int d = __shfl(row_d, r, 64);
+      if (f < total) {
         const int k = f + d;
         j[h2] = b.sorted[k];
         pj[h2] = b.spos[k];
@@ -1017,6 +1020,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     p0 = ((lane & 1) ? 1u : 0u) | (((lane & 2) ? 3u : 2u) << 10) | (((lane & 4) ? 5u : 4u) << 20);
   }
   double rho2 = 3.0 * half * half;  // bound on |v|^2 over the cell (exact when rho_exact)
+  double rs2 = rho2 * (1.0 + 1e-6) + 1e-12;  // the same with the security test's margin
   bool rho_exact = true;
   bool empty = false;
   int vmax = 8;
@@ -1079,6 +1083,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       new_verts += nvh;
       x0 = vx, y0 = vy, z0 = vz, p0 = vp, t0 = vt;
       rho2 = wave_max(lane < nvh ? vr2(vx, vy, vz, vt) : 0.0);
+      rs2 = rho2 * (1.0 + 1e-6) + 1e-12;
       rho_exact = true;
       // the star is read off LDS if no plane cuts Q further
       if (lane < nvh)
@@ -1098,21 +1103,26 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     // nearer after this one.  A neighbour at the same centre (n = 0)
     // has no plane and never ends the loop.  rho^2 is kept as an upper bound
     // (a cut never moves a vertex away from p_i) and made exact only when the
-    // bound would end the loop.
+    // bound would end the loop.  The test is made at every kSecurityStride-th
+    // slot only: the loop then ends at most that many planes late (planes that
+    // cut nothing), and the planes in between are spared it.
     // (k >= nfirst: the rest is in plane order.  The plane and rho^2 are the
     // same in every lane; voting on the tests makes their branches scalar.)
-    const double qn2 = qx * qx + qy * qy + qz * qz;
-    if (__builtin_expect(k >= nfirst && __ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull, 0)) {
-      if (!rho_exact) {
-        double r2 = 0.0;
-        if (lane < nv) r2 = vr2(x0, y0, z0, t0);
-        if ((VC > 64 && lane + 64 < nv)) r2 = fmax(r2, vr2(x1, y1, z1, t1));
-        rho2 = wave_max(r2);
-        rho_exact = true;
-      }
-      if (__ballot(qb * qb >= (rho2 * (1.0 + 1e-6) + 1e-12) * qn2) != 0ull) {
-        kstop = k;
-        break;
+    if (__builtin_expect(k >= nfirst && k % kSecurityStride == 0, 0)) {
+      const double qn2 = qx * qx + qy * qy + qz * qz;
+      if (__ballot(qn2 > 0.0 && qb >= 0.0 && qb * qb >= rs2 * qn2) != 0ull) {
+        if (!rho_exact) {
+          double r2 = 0.0;
+          if (lane < nv) r2 = vr2(x0, y0, z0, t0);
+          if ((VC > 64 && lane + 64 < nv)) r2 = fmax(r2, vr2(x1, y1, z1, t1));
+          rho2 = wave_max(r2);
+          rs2 = rho2 * (1.0 + 1e-6) + 1e-12;
+          rho_exact = true;
+        }
+        if (__ballot(qb * qb >= rs2 * qn2) != 0ull) {
+          kstop = k;
+          break;
+        }
       }
     }
     const double g0 = qb - (qx * x0 + qy * y0 + qz * z0);
