@@ -1,7 +1,7 @@
 // kernels.hip -- HIP kernels (gfx950, wave64) of the exact analytic SASA path.
 //
 // Pipeline for one batch of molecules (each molecule is one segment of atoms):
-//   k_cells_one one molecule of up to 65,536 atoms: the whole cell-list stage
+//   k_cells_one one molecule of up to 8,192 atoms: the whole cell-list stage
 //               below in one block (weights, box, grid, counts, scan, scatter)
 //   k_prep      weights R_i = r_i + probe, molecule ids, input checks, R_max and
 //               each molecule's bounding box
@@ -300,11 +300,13 @@ __global__ void k_scatter(Bufs b) {
 constexpr int ONE_T = 1024;
 constexpr int ONE_LDS_CELLS = 32768;
 
-// PER > 0: every atom of the call stays in the registers of one thread
-// (n <= PER * ONE_T); PER == 0: the atoms are re-read from memory per phase.
+// Every atom of the call stays in the registers of one thread (n <= PER *
+// ONE_T); larger molecules take the multi-kernel cell list, which spreads over
+// the whole GPU.
 template <int PER>
 __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
-  constexpr int R = PER > 0 ? PER : 1;
+  static_assert(PER > 0, "atoms in registers");
+  constexpr int R = PER;
   __shared__ int lcnt[ONE_LDS_CELLS];
   __shared__ double red[ONE_T / 64][7];
   __shared__ int scan_lds[ONE_T];
@@ -337,31 +339,25 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     v[3] = fmax(v[3], x), v[4] = fmax(v[4], y), v[5] = fmax(v[5], z);
     v[6] = fmax(v[6], r);
   };
-  constexpr int U = 8;  // atoms per thread in flight together when they do not stay in registers
-  if (PER > 0) {
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int i = t + k * ONE_T;
-      if (i < b.n) load(i, rx[k], ry[k], rz[k], rr[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int i = t + k * ONE_T;
-      if (i < b.n) weigh(i, rx[k], ry[k], rz[k], rr[k]);
-    }
-  } else {
-    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
-      double x[U], y[U], z[U], r[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) load(i0 + u * ONE_T, x[u], y[u], z[u], r[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) weigh(i0 + u * ONE_T, x[u], y[u], z[u], r[u]);
-    }
+  for (int k = 0; k < R; ++k) {
+    const int i = t + k * ONE_T;
+    if (i < b.n) load(i, rx[k], ry[k], rz[k], rr[k]);
   }
-  for (int q = 0; q < 7; ++q) v[q] = q < 3 ? wave_min_d(v[q]) : wave_max_d(v[q]);
-  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t + k * ONE_T;
+    if (i < b.n) weigh(i, rx[k], ry[k], rz[k], rr[k]);
+  }
+  // (the seven reductions step together: six dependent exchanges in all)
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const double o = __shfl_xor(v[q], off, 64);
+      v[q] = q < 3 ? fmin(v[q], o) : fmax(v[q], o);
+    }
+    bad += __shfl_xor(bad, off, 64);
+  }
   if (lane == 0)
     for (int q = 0; q < 7; ++q) red[t >> 6][q] = v[q];
   __syncthreads();  // also orders the counter clearing before the stores below
@@ -394,32 +390,13 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   auto cell_of = [&](double x, double y, double z) {
     return (cell_index(z, gz, inv_s, dz) * dy + cell_index(y, gy, inv_s, dy)) * dx + cell_index(x, gx, inv_s, dx);
   };
-  if (PER > 0) {
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int i = t + k * ONE_T;
-      if (i < b.n) {
-        rc[k] = cell_of(rx[k], ry[k], rz[k]);
-        b.cellid[i] = rc[k];
-        atomicAdd(&cnt[rc[k]], 1);
-      }
-    }
-  } else {
-    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
-      double x[U] = {}, y[U] = {}, z[U] = {};
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) {
-          const double* q = &b.pos[i0 + u * ONE_T].x;
-          x[u] = q[0], y[u] = q[1], z[u] = q[2];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) {
-          const int c = cell_of(x[u], y[u], z[u]);
-          b.cellid[i0 + u * ONE_T] = c;
-          atomicAdd(&cnt[c], 1);
-        }
+  for (int k = 0; k < R; ++k) {
+    const int i = t + k * ONE_T;
+    if (i < b.n) {
+      rc[k] = cell_of(rx[k], ry[k], rz[k]);
+      b.cellid[i] = rc[k];
+      atomicAdd(&cnt[rc[k]], 1);
     }
   }
   __syncthreads();
@@ -449,36 +426,21 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     for (int c = t; c < cells; c += ONE_T) b.start[c] = lcnt[c];
     __syncthreads();
   }
-  if (PER > 0) {
+  // every slot first (the cursor atomics then are all in flight together),
+  // then the stores
+  int slot[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int i = t + k * ONE_T;
-      if (i < b.n) {
-        const int slot = atomicAdd(&cnt[rc[k]], 1);
-        b.sorted[slot] = i;
-        b.spos[slot] = make_double4(rx[k], ry[k], rz[k], rr[k]);
-        b.smc[slot] = make_int2(0, rc[k]);
-      }
-    }
-  } else {
-    for (int i0 = t; i0 < b.n; i0 += U * ONE_T) {
-      double x[U] = {}, y[U] = {}, z[U] = {}, w[U] = {};
-      int c[U] = {};
+  for (int k = 0; k < R; ++k) {
+    const int i = t + k * ONE_T;
+    if (i < b.n) slot[k] = atomicAdd(&cnt[rc[k]], 1);
+  }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) {
-          const double* q = &b.pos[i0 + u * ONE_T].x;
-          x[u] = q[0], y[u] = q[1], z[u] = q[2], w[u] = q[3];
-          c[u] = b.cellid[i0 + u * ONE_T];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * ONE_T < b.n) {
-          const int slot = atomicAdd(&cnt[c[u]], 1);
-          b.sorted[slot] = i0 + u * ONE_T;
-          b.spos[slot] = make_double4(x[u], y[u], z[u], w[u]);
-          b.smc[slot] = make_int2(0, c[u]);
-        }
+  for (int k = 0; k < R; ++k) {
+    const int i = t + k * ONE_T;
+    if (i < b.n) {
+      b.sorted[slot[k]] = i;
+      b.spos[slot[k]] = make_double4(rx[k], ry[k], rz[k], rr[k]);
+      b.smc[slot[k]] = make_int2(0, rc[k]);
     }
   }
 }
@@ -2316,8 +2278,8 @@ void launch_scatter(const Bufs& b, hipStream_t s) {
 }
 void launch_cells_one(const Bufs& b, hipStream_t s) {
   if (!b.n) return;
-  if (b.n <= 8 * ONE_T) k_cells_one<8><<<1, ONE_T, 0, s>>>(b);
-  else k_cells_one<0><<<1, ONE_T, 0, s>>>(b);
+  static_assert(ONE_BLOCK_MAX_ATOMS <= 8 * ONE_T, "one block holds its atoms in registers");
+  k_cells_one<8><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
   if (!b.n) return;

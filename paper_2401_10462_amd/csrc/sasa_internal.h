@@ -150,7 +150,7 @@ void launch_cells_one(const Bufs& b, hipStream_t s);
 void launch_star(const Bufs& b, hipStream_t s);        // fast pass over all atoms
 void launch_star_wide(const Bufs& b, hipStream_t s);   // atoms the fast pass queued
 // Largest single molecule whose cell list is built by one block.
-constexpr int64_t ONE_BLOCK_MAX_ATOMS = 65536;
+constexpr int64_t ONE_BLOCK_MAX_ATOMS = 8192;
 void launch_stats(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
