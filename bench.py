@@ -95,8 +95,8 @@ def serving(args, precision):
                 st = poisson_run(srv, reqs, rate, seed=int(rate))
                 st["batches"] = srv.batches - 1
             row[name] = st
+            print(json.dumps({"serving_rate": rate, name: st}), file=sys.stderr, flush=True)
         res["rates"].append(row)
-        print(json.dumps({"serving_rate": rate, "batched": row["batched"], "plain": row["plain"]}), file=sys.stderr)
     return res
 
 
@@ -106,14 +106,19 @@ def md(args, precision):
     from synth.globule import globule_complex
     xyz, rad = globule_complex(args.md_atoms, 3)
     out = {"atoms": len(rad), "frames": args.frames, "gamma": 0.005, "sigma": 0.02}
-    # trajectory mode (cells clipped first by the previous frame's facets), then
-    # the same frames with every cell clipped from scratch
-    for key, hints in (("hinted", True), ("cold", False)):
+    # md_loop's default (every cell clipped from scratch), then the same frames
+    # in trajectory mode (each cell kept from the previous frame when it still
+    # verifies, else clipped with the previous frame's facets first)
+    from paper_2401_10462_amd import SasaContext
+    for key, hints in (("cold", False), ("hinted", True)):
         md_loop(xyz, rad, frames=min(args.warmup, 5), precision=precision, frame_hints=hints)
-        lat, _ = md_loop(xyz, rad, frames=args.frames, precision=precision, frame_hints=hints)
+        ctx = SasaContext(precision=precision, max_atoms=len(rad), frames=hints)
+        lat, _ = md_loop(xyz, rad, frames=args.frames, precision=precision, ctx=ctx, frame_hints=hints)
         lat = np.array(lat)
         out[key] = {"frames_per_s": 1e3 / lat.mean(), "atoms_per_s": len(rad) * 1e3 / lat.mean(),
-                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "cells_kept_last_frame": int(ctx.diagnostics()["reused_cells"])}
+        ctx.close()
     return out
 
 

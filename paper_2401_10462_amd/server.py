@@ -60,25 +60,38 @@ class _Slot:
         self.host_out = None
         self.area = None
         self.grad = None
+        # pinned staging for a full slot, allocated once (a pinned allocation
+        # of a new size can stall the device for milliseconds); a batch reuses
+        # it only after the previous one has been finished
+        self.cap = max(int(max_atoms), 1)
+        self._pin = self._pinned(self.cap)
+
+    @staticmethod
+    def _pinned(n):
+        return {"xyz": torch.empty((n, 3), dtype=torch.float64, pin_memory=True),
+                "rad": torch.empty(n, dtype=torch.float64, pin_memory=True),
+                "area": torch.empty(n, dtype=torch.float64, pin_memory=True),
+                "grad": torch.empty((n, 3), dtype=torch.float64, pin_memory=True)}
 
     def launch(self, reqs):
         self.reqs = reqs
         n = sum(r.n for r in reqs)
         offs = np.zeros(len(reqs) + 1, np.int64)
         offs[1:] = np.cumsum([r.n for r in reqs])
-        xyz = torch.from_numpy(np.concatenate([r.xyz for r in reqs])).pin_memory()
-        rad = torch.from_numpy(np.concatenate([r.radii for r in reqs])).pin_memory()
+        pin = self._pin if n <= self.cap else self._pinned(n)  # (a request above the budget, run alone)
+        xyz, rad = pin["xyz"][:n], pin["rad"][:n]
+        np.concatenate([r.xyz for r in reqs], out=xyz.numpy())
+        np.concatenate([r.radii for r in reqs], out=rad.numpy())
         with torch.cuda.stream(self.stream):
             X = xyz.to(self.device, non_blocking=True)
             R = rad.to(self.device, non_blocking=True)
             area, grad = self.ctx.compute_batch(offs, X, R, self.probe, grad=True)
-            self.host_out = (torch.empty(n, dtype=torch.float64, pin_memory=True),
-                             torch.empty((n, 3), dtype=torch.float64, pin_memory=True))
+            self.host_out = (pin["area"][:n], pin["grad"][:n])
             self.host_out[0].copy_(area, non_blocking=True)
             self.host_out[1].copy_(grad, non_blocking=True)
             self.event.record(self.stream)
         # keep the staging alive until the event completes
-        self._keep = (xyz, rad, X, R, area, grad, offs)
+        self._keep = (pin, X, R, area, grad, offs)
 
     def done(self):
         return self.event.query()
