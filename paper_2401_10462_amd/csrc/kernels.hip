@@ -484,7 +484,7 @@ struct StarLds {
     unsigned w[NBC / 4];   // the same four to a word (atomic OR)
   } sf;
   signed char kidx[NBC];  // slot -> K-neighbour index or -1
-  union {
+  union alignas(16) {
     struct {  // candidates in arrival order (neighbour search and ranking only)
       double key[NBC];  // signed distance of the radical plane from p_i
       int id[NBC];
@@ -899,25 +899,35 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     nfirst = __popcll(__ballot(ft0 >= 0)) + __popcll(__ballot(ft1 >= 0)) + __popcll(__ballot(ft2 >= 0));
   }
   const unsigned long long ok0 = order_key(ck0, ci0), ok1 = order_key(ck1, ci1), ok2 = order_key(ck2, ci2);
+  // The keys go to LDS (each lane overwrites the arrival slots it has just
+  // read), padded to an even count with a key above every candidate's; each
+  // lane then counts the keys below its own, two keys per (broadcast) read.
+  unsigned long long* okey = reinterpret_cast<unsigned long long*>(L.u.app.key);
+  if (lane < nn) okey[lane] = ok0;
+  if (lane + 64 < nn) okey[lane + 64] = ok1;
+  if (lane + 128 < nn) okey[lane + 128] = ok2;
+  if (lane == 0 && (nn & 1)) okey[nn] = ~0ull;
+  __syncthreads();
+  const ulonglong2* okp = reinterpret_cast<const ulonglong2*>(okey);
+  const int npair = (nn + 1) >> 1;
   int rk0 = 0, rk1 = 0, rk2 = 0;
-  for (int hb = 0; hb < nsets; ++hb) {
-    const unsigned long long kk = hb == 0 ? ok0 : (hb == 1 ? ok1 : ok2);
-    const int lim = min(64, nn - 64 * hb);
-    if (nsets == 1) {
-      for (int t = 0; t < lim; ++t) rk0 += rdl64(kk, t) < ok0;
-    } else if (nsets == 2) {
-      for (int t = 0; t < lim; ++t) {
-        const unsigned long long kt = rdl64(kk, t);
-        rk0 += kt < ok0;
-        rk1 += kt < ok1;
-      }
-    } else {
-      for (int t = 0; t < lim; ++t) {
-        const unsigned long long kt = rdl64(kk, t);
-        rk0 += kt < ok0;
-        rk1 += kt < ok1;
-        rk2 += kt < ok2;
-      }
+  if (nsets == 1) {
+    for (int t = 0; t < npair; ++t) {
+      const ulonglong2 kt = okp[t];
+      rk0 += (kt.x < ok0) + (kt.y < ok0);
+    }
+  } else if (nsets == 2) {
+    for (int t = 0; t < npair; ++t) {
+      const ulonglong2 kt = okp[t];
+      rk0 += (kt.x < ok0) + (kt.y < ok0);
+      rk1 += (kt.x < ok1) + (kt.y < ok1);
+    }
+  } else {
+    for (int t = 0; t < npair; ++t) {
+      const ulonglong2 kt = okp[t];
+      rk0 += (kt.x < ok0) + (kt.y < ok0);
+      rk1 += (kt.x < ok1) + (kt.y < ok1);
+      rk2 += (kt.x < ok2) + (kt.y < ok2);
     }
   }
   for (int hb = 0; hb < 3; ++hb) {
