@@ -85,7 +85,10 @@ def serving(args, precision):
     sizes = np.round(np.exp(rng.uniform(np.log(200), np.log(20000), size=nreq))).astype(int)
     reqs = pool_molecules(sizes)
     rates = [float(x) for x in args.rates.split(",")]
-    res = {"requests_per_rate": nreq, "mean_atoms": float(sizes.mean()), "rates": []}
+    res = {"requests_per_rate": nreq, "mean_atoms": float(sizes.mean()),
+           "molecules": "first n atoms of 7 pooled structures (200 to 20,000 atoms; above 2,500 atoms complexes of "
+                        "globules of up to 2,500 heavy atoms), randomly rotated",
+           "rates": []}
     for rate in rates:
         row = {"rate_req_s": rate}
         for name, kw in (("batched", dict(slots=3, slot_budget_bytes=1 << 30)),
@@ -105,7 +108,8 @@ def md(args, precision):
     from paper_2401_10462_amd.md_loop import md_loop
     from synth.globule import globule_complex
     xyz, rad = globule_complex(args.md_atoms, 3)
-    out = {"atoms": len(rad), "frames": args.frames, "gamma": 0.005, "sigma": 0.02}
+    out = {"atoms": len(rad), "frames": args.frames, "gamma": 0.005, "sigma": 0.02,
+           "structure": f"complex of {-(-len(rad) // 2500)} globules of up to 2,500 heavy atoms (seed 3)"}
     # md_loop's default (every cell clipped from scratch), then the same frames
     # in trajectory mode (each cell kept from the previous frame when it still
     # verifies, else clipped with the previous frame's facets first)

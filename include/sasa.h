@@ -80,7 +80,9 @@ enum {
 typedef struct {
   int32_t device;       /* HIP device ordinal */
   int32_t precision;    /* sasa_precision */
-  int64_t max_atoms;    /* optional size hint for the first allocation (0: grow on demand) */
+  int64_t max_atoms;    /* optional size hint for the first allocation (0: grow on demand); the buffers are
+                           sized for max_atoms atoms in up to min(max_atoms, 8192) molecules per call, so
+                           calls within that size never reallocate (which would wait for the device) */
   uint32_t flags;       /* SASA_FLAG_* */
   uint32_t reserved;
 } sasa_options;

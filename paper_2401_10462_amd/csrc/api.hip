@@ -110,6 +110,8 @@ hipError_t grow(T** p, size_t count) {
 // zeroed first, and an allocation that fails part-way leaves 0 behind and the
 // next call grows the whole group again (never writing through a freed or
 // missing buffer).
+constexpr int64_t kPresizedMolecules = 8192;
+
 int ensure(Ctx* c, int64_t n, int nmol) {
   Bufs& b = c->b;
   if (n > c->cap_n) {
@@ -404,7 +406,10 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
         return fail(nullptr, SASA_E_DEVICE, "hipEventCreate failed");
       }
   if (opt && opt->max_atoms > 0) {
-    int rc = ensure(c, opt->max_atoms, 1);
+    // the per-molecule arrays too, for batches of up to min(max_atoms, 8,192)
+    // molecules: growing them later frees pinned and device memory, which
+    // waits for the device (tens of milliseconds inside a serving loop)
+    int rc = ensure(c, opt->max_atoms, (int)std::min<int64_t>(opt->max_atoms, kPresizedMolecules));
     if (rc) {
       sasa_destroy(c);
       return rc;

@@ -15,6 +15,7 @@ served as soon as a slot and memory free up.
 molecule per launch sequence, first in first out.
 """
 import collections
+import gc
 import queue
 import threading
 import time
@@ -116,10 +117,20 @@ class SasaServer:
 
     slot_budget_bytes: HBM footprint one slot may use (admission limit); a
     request larger than the budget is run alone.
+    freeze_gc: move the objects that exist when the server starts out of the
+    garbage collector's reach (``gc.freeze``).  A full collection walks every
+    tracked object of the process (a few hundred thousand once torch is
+    imported) and, holding the interpreter lock, stalls the scheduler thread for
+    about 70 ms: the one-in-a-hundred latencies of a stream.  Objects frozen
+    here are never collected, so a process that creates and drops many servers
+    may prefer to leave it off.
     """
 
     def __init__(self, device=0, precision="mixed", slots=3, slot_budget_bytes=2 << 30, probe=1.4,
-                 max_requests_per_batch=None, slot_factory=None):
+                 max_requests_per_batch=None, slot_factory=None, freeze_gc=True):
+        if freeze_gc:
+            gc.collect()
+            gc.freeze()
         self.device = device
         self.budget = slot_budget_bytes
         self.max_req = max_requests_per_batch
