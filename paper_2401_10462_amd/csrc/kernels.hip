@@ -494,7 +494,7 @@ struct StarLds {
       unsigned vp[VC];
       signed char vt[VC];  // side-test bound of each vertex (thr_code)
       union {
-        unsigned pairs[3 * VC];  // edges of the removed vertices of one cut
+        alignas(16) unsigned pairs[3 * VC];  // edges of the removed vertices of one cut
         struct {                 // cell edges by plane pair: code << 7 | first end, second end
           unsigned key[EH_SIZE];
           unsigned char second[EH_SIZE];
@@ -611,11 +611,6 @@ __device__ inline unsigned long long order_key(double key, int id) {
   const unsigned u = __float_as_uint((float)key);
   const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
   return ((unsigned long long)o << 32) | (unsigned)id;
-}
-__device__ inline unsigned long long rdl64(unsigned long long v, int l) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
-  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ inline double wave_max(double v) {
@@ -864,8 +859,8 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   __syncthreads();
   // ---- slots in clipping order: nearest plane first, ties by atom id.  Lane
   // s holds candidates s, s + 64, s + 128 in registers, ranks each against all
-  // others (read with readlane) and writes its plane at its rank; the
-  // candidates' positions are fetched while the ranks are counted.
+  // others (their order keys read back from LDS) and writes its plane at its
+  // rank; the candidates' positions are fetched while the ranks are counted.
   const int nsets = (nn + 63) >> 6;
   double ck0 = 0.0, ck1 = 0.0, ck2 = 0.0;
   int ci0 = -1, ci1 = -1, ci2 = -1;
@@ -1166,6 +1161,9 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       L.u.cl.w.pairs[3 * rk + 1] = pid0(p1) | (pid2(p1) << 10);
       L.u.cl.w.pairs[3 * rk + 2] = pid0(p1) | (pid1(p1) << 10);
     }
+    // padded to a multiple of four with a code no plane pair has (nrem < nv
+    // <= VC, so the pad stays inside the array)
+    if (lane < 3 && 3 * nrem + lane < ((3 * nrem + 3) & ~3)) L.u.cl.w.pairs[3 * nrem + lane] = 0xffffffffu;
     __syncthreads();
     const int nkeep = nv - nrem;
     // kept vertices move to their compacted slots (old LDS contents are dead:
@@ -1181,25 +1179,21 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
     }
     // an edge with exactly one removed end crosses the plane: new vertex on it,
     // solved from its three planes in ascending id order (canonical)
-    // (up to 64 edges, lane e holds edge e and counts its copies with
-    // readlane; more edges take the LDS loop)
+    // (lane e holds edge e and counts its copies, four pairs per broadcast
+    // read of the list)
     const int ne = 3 * nrem;
+    const int nq = (ne + 3) >> 2;
+    const uint4* pq = reinterpret_cast<const uint4*>(L.u.cl.w.pairs);
     int ncross = 0;
     for (int base = 0; base < ne; base += 64) {
       const int e = base + lane;
-      bool cross = false;
-      unsigned pr = 0;
-      if (ne <= 64) {
-        pr = e < ne ? L.u.cl.w.pairs[e] : 0xffffffffu;
-        int c = 0;
-        for (int t = 0; t < ne; ++t) c += (unsigned)__builtin_amdgcn_readlane((int)pr, t) == pr;
-        cross = e < ne && c == 1;
-      } else if (e < ne) {
-        pr = L.u.cl.w.pairs[e];
-        int c = 0;
-        for (int t = 0; t < ne; ++t) c += (L.u.cl.w.pairs[t] == pr);
-        cross = (c == 1);
+      const unsigned pr = e < ne ? L.u.cl.w.pairs[e] : 0xfffffffeu;  // (no pair and not the pad)
+      int c = 0;
+      for (int t = 0; t < nq; ++t) {
+        const uint4 q = pq[t];
+        c += (q.x == pr) + (q.y == pr) + (q.z == pr) + (q.w == pr);
       }
+      const bool cross = e < ne && c == 1;
       const unsigned long long cm = __ballot(cross);
       bool bad_v = false;
       int my_slot = -1;
