@@ -620,15 +620,18 @@ __device__ inline double wave_max(double v) {
 
 // Exact sign of the side test of plane slot k at the vertex with plane ids pv
 // (exact_side.h), evaluated by the calling lane alone in the work space W.
+// (These helpers take the positions array, not the whole buffer set: a
+// non-inlined function taking the kernel's argument block by reference would
+// make every block copy that block to scratch memory on entry.)
 template <class LT>
-__device__ __noinline__ int exact_side_at(const Bufs& b, const double4& pi, double half, const LT& L,
+__device__ __noinline__ int exact_side_at(const double4* pos, const double4& pi, double half, const LT& L,
                                           exact::Work& W, unsigned pv, int k) {
   const unsigned ids[4] = {pid0(pv), pid1(pv), pid2(pv), 6u + (unsigned)k};
   for (int q = 0; q < 4; ++q) {
     if (ids[q] < 6) {
       exact::cube_face(ids[q], half, W.pl[q]);
     } else {
-      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      const double4 pj = pos[L.idx[ids[q] - 6]];
       if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return 2;
     }
   }
@@ -638,7 +641,7 @@ __device__ __noinline__ int exact_side_at(const Bufs& b, const double4& pi, doub
 // Side test of plane slot k at the vertex with plane ids pv in double-double
 // (each lane its own; 0 if that does not decide it).
 template <class LT>
-__device__ __noinline__ int dd_side_at(const Bufs& b, const double4& pi, double half, const LT& L, unsigned pv,
+__device__ __noinline__ int dd_side_at(const double4* pos, const double4& pi, double half, const LT& L, unsigned pv,
                                        int k) {
   exact::DPl P[4];
   const unsigned ids[4] = {pid0(pv), pid1(pv), pid2(pv), 6u + (unsigned)k};
@@ -647,7 +650,7 @@ __device__ __noinline__ int dd_side_at(const Bufs& b, const double4& pi, double 
     if (ids[q] < 6) {
       P[q] = exact::dd_cube(ids[q], half);
     } else {
-      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      const double4 pj = pos[L.idx[ids[q] - 6]];
       P[q] = exact::dd_radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w);
     }
   }
@@ -658,7 +661,7 @@ __device__ __noinline__ int dd_side_at(const Bufs& b, const double4& pi, double 
 // of the tetrahedron (i, a, b, c)): double-double, each lane its own; 0 if that
 // does not decide it.
 template <class LT>
-__device__ __noinline__ int dd_orient_at(const Bufs& b, const double4& pi, double half, const LT& L, unsigned pv) {
+__device__ __noinline__ int dd_orient_at(const double4* pos, const double4& pi, double half, const LT& L, unsigned pv) {
   exact::DPl P[3];
   const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
 #pragma unroll
@@ -666,7 +669,7 @@ __device__ __noinline__ int dd_orient_at(const Bufs& b, const double4& pi, doubl
     if (ids[q] < 6) {
       P[q] = exact::dd_cube(ids[q], half);
     } else {
-      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      const double4 pj = pos[L.idx[ids[q] - 6]];
       P[q] = exact::dd_radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w);
     }
   }
@@ -678,14 +681,14 @@ __device__ __noinline__ int dd_orient_at(const Bufs& b, const double4& pi, doubl
 
 // The same sign from the expansions, by the calling lane alone in W.
 template <class LT>
-__device__ __noinline__ int exact_orient_at(const Bufs& b, const double4& pi, double half, const LT& L,
+__device__ __noinline__ int exact_orient_at(const double4* pos, const double4& pi, double half, const LT& L,
                                             exact::Work& W, unsigned pv) {
   const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
   for (int q = 0; q < 3; ++q) {
     if (ids[q] < 6) {
       exact::cube_face(ids[q], half, W.pl[q]);
     } else {
-      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      const double4 pj = pos[L.idx[ids[q] - 6]];
       if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return 2;
     }
   }
@@ -696,14 +699,14 @@ __device__ __noinline__ int exact_orient_at(const Bufs& b, const double4& pi, do
 // The vertex of plane ids pv solved exactly (exact_side.h), by the calling lane
 // alone in the work space W.  False on failure.
 template <class LT>
-__device__ __noinline__ bool exact_vertex_at(const Bufs& b, const double4& pi, double half, const LT& L,
+__device__ __noinline__ bool exact_vertex_at(const double4* pos, const double4& pi, double half, const LT& L,
                                              exact::Work& W, unsigned pv, double* v) {
   const unsigned ids[3] = {pid0(pv), pid1(pv), pid2(pv)};
   for (int q = 0; q < 3; ++q) {
     if (ids[q] < 6) {
       exact::cube_face(ids[q], half, W.pl[q]);
     } else {
-      const double4 pj = b.pos[L.idx[ids[q] - 6]];
+      const double4 pj = pos[L.idx[ids[q] - 6]];
       if (!exact::radical(pi.x, pi.y, pi.z, pi.w, pj.x, pj.y, pj.z, pj.w, W.pl[q], W)) return false;
     }
   }
@@ -1111,11 +1114,11 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
           // ones (exact ties, in practice) in expansions, one lane at a time
           bool v0 = u0, v1 = u1;
           if (v0) {
-            const int sg = dd_side_at(b, pi, half, L, p0, k);
+            const int sg = dd_side_at(b.pos, pi, half, L, p0, k);
             if (sg != 0) r0 = sg < 0, v0 = false;
           }
           if (VC > 64 && v1) {
-            const int sg = dd_side_at(b, pi, half, L, p1, k);
+            const int sg = dd_side_at(b.pos, pi, half, L, p1, k);
             if (sg != 0) r1 = sg < 0, v1 = false;
           }
           exact_tests += __popcll(__ballot(u0)) + __popcll(__ballot(u1));
@@ -1126,7 +1129,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
               um &= um - 1ull;
               const unsigned pv = (unsigned)__builtin_amdgcn_readlane((int)(h ? p1 : p0), l);
               int sg = 0;
-              if (lane == 0) sg = exact_side_at(b, pi, half, L, *W, pv, k);
+              if (lane == 0) sg = exact_side_at(b.pos, pi, half, L, *W, pv, k);
               sg = __shfl(sg, 0, 64);
               exact_fail |= sg == 2;
               if (lane == l) {
@@ -1225,7 +1228,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
             const int sl = __builtin_amdgcn_readlane(my_slot, l);
             if (lane == 0) {
               double v[3];
-              if (exact_vertex_at(b, pi, half, L, *W, tv, v)) {
+              if (exact_vertex_at(b.pos, pi, half, L, *W, tv, v)) {
                 L.u.cl.vx[sl] = v[0], L.u.cl.vy[sl] = v[1], L.u.cl.vz[sl] = v[2];
                 L.u.cl.vt[sl] = thr_code(thrSolved);
               } else {
@@ -1540,7 +1543,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
       for (int h = 0; h < 2; ++h) {
         bool u = h ? ounsure1 : ounsure0;
         if (u) {
-          const int sg = dd_orient_at(b, pi, half, L, h ? p1 : p0);
+          const int sg = dd_orient_at(b.pos, pi, half, L, h ? p1 : p0);
           if (sg != 0) {
             if (h) osg1 = sg;
             else osg0 = sg;
@@ -1553,7 +1556,7 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
           um &= um - 1ull;
           const unsigned pv = (unsigned)__builtin_amdgcn_readlane((int)(h ? p1 : p0), l);
           int sg = 0;
-          if (lane == 0) sg = exact_orient_at(b, pi, half, L, *W, pv);
+          if (lane == 0) sg = exact_orient_at(b.pos, pi, half, L, *W, pv);
           sg = __shfl(sg, 0, 64);
           exact_fail |= sg == 2 || sg == 0;
           if (lane == l) {
