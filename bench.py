@@ -386,12 +386,16 @@ def main():
     volume = {"ms_per_call": 1e3 * tv / kv, "atoms_per_s": n * kv / tv, "calls": kv,
               "volume_A3": float(vol.sum().item()), "vjp_ms_per_call": 1e3 * tb / kv}
 
-    # ---- the paper's sorted-face extraction of the same complex (A/B against
-    # the classification the star kernel does per atom)
+    # ---- the paper's sorted extraction of the same complex (A/B against the
+    # classification the star kernel does per atom): triangles, then also the
+    # edges and vertices
     ctx.compute(X, R, 1.4)
     ctx.triangles_by_sort()
     sort_ms = [ctx.triangles_by_sort()[2] for _ in range(5)]
+    ev = [ctx.edges_vertices_by_sort() for _ in range(3)]
     sorted_extraction = {"ms": float(np.median(sort_ms)), "triangles": int(ctx.counts()["triangles"]),
+                         "with_edges_vertices_ms": float(np.median([r[4] for r in ev])),
+                         "edges": int(len(ev[-1][0])), "vertices": int(len(ev[-1][2])),
                          "star_kernel_ms": stage["star"] / args.steps}
 
     # ---- dominant kernel roofline (VALU-bound FP64 clipping): k_star alone

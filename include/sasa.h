@@ -15,8 +15,9 @@
  *   - the volumes of the same cells, the molecular-volume gradient and the
  *     per-atom volume VJP (sasa_volume, sasa_volume_backward; the
  *     Discussion's extension to volumes);
- *   - the paper's sort-based extraction of unique triangles, for comparison
- *     (sasa_triangles_by_sort).
+ *   - the paper's sort-based extraction of unique triangles, edges and
+ *     vertices, for comparison (sasa_triangles_by_sort,
+ *     sasa_edges_vertices_by_sort).
  *
  * Units: lengths in Angstrom, areas in A^2, volumes in A^3, gradients in A^2/A.
  *
@@ -192,6 +193,36 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]);
  */
 int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms);
+
+/*
+ * The other half of that extraction (GPU section, extraction of exterior
+ * simplices): the unique K-edges and K-vertices of the last compute and their
+ * exterior flags, found by the same lexicographic sorts one dimension down.
+ * Every unique triangle (sasa_triangles_by_sort) lists its three edges with its
+ * exterior flag (n_t <= 1), and every K-edge is listed once more from the star
+ * of its lower atom; the candidates are radix-sorted and each run's flags
+ * combined: an edge is exterior iff it lies on an exterior triangle or on
+ * none.  Every unique edge then lists its two atoms with its flag, every atom
+ * in K once more, and a vertex is exterior iff it has an exterior edge or none.
+ * For comparison with the star kernel's per-atom classification.
+ *   edges      2*edge_capacity int32 out (host): ascending atom ids per edge,
+ *              in lexicographic order
+ *   edge_ext   edge_capacity uint8 out (host): 1 if the edge is exterior
+ *   edge_count out: number of K-edges (= sasa_complex_counts()[1])
+ *   verts      vert_capacity int32 out (host): the atoms in K, ascending
+ *   vert_ext   vert_capacity uint8 out (host): 1 if the vertex is exterior
+ *   vert_count out: number of K-vertices (= sasa_complex_counts()[0])
+ *   ms         out (may be NULL): GPU time of the whole extraction (triangles,
+ *              edges and vertices) on the null stream
+ * With all four output arrays NULL only the counts (and ms) are returned; give
+ * all four or none.  Allocates its work buffers on first use.
+ * SASA_E_CAPACITY if a count exceeds its capacity, SASA_E_INVAL for 2^21 atoms
+ * or more, SASA_E_STATE without a kept compute, SASA_E_DEVICE if the sorted
+ * counts disagree with the complex's counters.
+ */
+int sasa_edges_vertices_by_sort(void* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
+                                int64_t* edge_count, int32_t* verts, uint8_t* vert_ext, int64_t vert_capacity,
+                                int64_t* vert_count, float* ms);
 
 /*
  * Copy the kept complex to host arrays sized by sasa_complex_counts: each

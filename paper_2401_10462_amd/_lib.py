@@ -31,7 +31,7 @@ EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
     "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export",
     "sasa_diagnostics", "sasa_status", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
-    "sasa_compute_noalloc",
+    "sasa_compute_noalloc", "sasa_edges_vertices_by_sort",
 )
 
 
@@ -91,6 +91,7 @@ def load():
     L.sasa_volume.argtypes = [P, P, P, I32, P]
     L.sasa_volume_backward.argtypes = [P, P, P, I32, P]
     L.sasa_triangles_by_sort.argtypes = [P, P, P, I64, P, P]
+    L.sasa_edges_vertices_by_sort.argtypes = [P, P, P, I64, P, P, P, I64, P, P]
     L.sasa_complex_counts.argtypes = [P, P]
     L.sasa_complex_export.argtypes = [P, P, P, P, P, P]
     L.sasa_diagnostics.argtypes = [P, ctypes.POINTER(sasa_diag), I64]
@@ -231,6 +232,23 @@ def sasa_triangles_by_sort(ctx):
     check(L.sasa_triangles_by_sort(ctx, ctypes.c_void_p(tris.ctypes.data), ctypes.c_void_p(nt.ctypes.data),
                                    int(m.value), ctypes.byref(m), ctypes.byref(ms)), ctx)
     return tris[:m.value], nt[:m.value], float(ms.value)
+
+
+def sasa_edges_vertices_by_sort(ctx):
+    L = load()
+    ne, nv = ctypes.c_int64(0), ctypes.c_int64(0)
+    ms = ctypes.c_float(0.0)
+    check(L.sasa_edges_vertices_by_sort(ctx, None, None, 0, ctypes.byref(ne), None, None, 0, ctypes.byref(nv),
+                                        ctypes.byref(ms)), ctx)
+    e = np.zeros((max(ne.value, 1), 2), np.int32)
+    ee = np.zeros(max(ne.value, 1), np.uint8)
+    v = np.zeros(max(nv.value, 1), np.int32)
+    ve = np.zeros(max(nv.value, 1), np.uint8)
+    check(L.sasa_edges_vertices_by_sort(ctx, ctypes.c_void_p(e.ctypes.data), ctypes.c_void_p(ee.ctypes.data),
+                                        int(ne.value), ctypes.byref(ne), ctypes.c_void_p(v.ctypes.data),
+                                        ctypes.c_void_p(ve.ctypes.data), int(nv.value), ctypes.byref(nv),
+                                        ctypes.byref(ms)), ctx)
+    return e[:ne.value], ee[:ne.value].astype(bool), v[:nv.value], ve[:nv.value].astype(bool), float(ms.value)
 
 
 def sasa_complex_counts(ctx):

@@ -85,6 +85,11 @@ class SasaContext:
         """The kept complex's triangles and n_t by the sorted-face extraction, and its GPU time (ms)."""
         return _lib.sasa_triangles_by_sort(self._h)
 
+    def edges_vertices_by_sort(self):
+        """The kept complex's unique edges and vertices with exterior flags by sorted extraction, and its GPU time (ms):
+        (edges (m, 2), edge_ext (m,), verts (k,), vert_ext (k,), ms)."""
+        return _lib.sasa_edges_vertices_by_sort(self._h)
+
     def counts(self):
         c = _lib.sasa_complex_counts(self._h)
         keys = ("vertices", "edges", "triangles", "tetrahedra", "ext_vertices", "ext_edges", "ext_triangles", "atoms")

@@ -56,6 +56,7 @@ struct Ctx {
   int64_t fac_atoms = -1;  // atom count of the call that wrote the facet hints (-1: none)
   SortedFaces sf;           // buffers of the sorted-face extraction (grown on demand)
   int64_t sf_cap_faces = -1, sf_cap_free = -1;
+  SortedEV se, sv;          // the same for unique edges and vertices
   sasa_diag diag{};
   std::string err;
 };
@@ -433,6 +434,12 @@ void sasa_destroy(void* ctx) {
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
     if (p) (void)hipFree(p);
+  for (SortedEV* w : {&c->se, &c->sv}) {
+    void* ev[] = {w->keys, w->vals, w->skeys, w->svals, w->uniq, w->agg, w->nuniq, w->cursor, w->out_ids, w->out_ext,
+                  w->temp};
+    for (void* p : ev)
+      if (p) (void)hipFree(p);
+  }
   if (c->off_h) (void)hipHostFree(c->off_h);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -627,6 +634,118 @@ int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t 
     HIP_TRY(c, hipMemcpy(tri_ntet, w.ntet, (size_t)m, hipMemcpyDeviceToHost));
   }
   return SASA_OK;
+}
+
+namespace {
+// Work buffers of one sorted edge / vertex extraction for n candidates (a
+// failed allocation leaves cap at -1, so the next call grows them all again).
+int ensure_ev(Ctx* c, SortedEV& w, int64_t n) {
+  n = std::max<int64_t>(n, 1);
+  if (n <= w.cap) return SASA_OK;
+  w.cap = -1;
+  HIP_TRY(c, grow(&w.keys, n));
+  HIP_TRY(c, grow(&w.vals, n));
+  HIP_TRY(c, grow(&w.skeys, n));
+  HIP_TRY(c, grow(&w.svals, n));
+  HIP_TRY(c, grow(&w.uniq, n));
+  HIP_TRY(c, grow(&w.agg, n));
+  HIP_TRY(c, grow(&w.out_ids, 2 * n));
+  HIP_TRY(c, grow(&w.out_ext, n));
+  if (!w.nuniq) HIP_TRY(c, grow(&w.nuniq, 1));
+  if (!w.cursor) HIP_TRY(c, grow(&w.cursor, 1));
+  const size_t tb = sorted_ev_temp_bytes(n);
+  if (tb > w.temp_bytes) {
+    w.temp_bytes = 0;
+    HIP_TRY(c, grow((char**)&w.temp, tb));
+    w.temp_bytes = tb;
+  }
+  w.cap = n;
+  return SASA_OK;
+}
+}  // namespace
+
+int sasa_edges_vertices_by_sort(void* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
+                                int64_t* edge_count, int32_t* verts, uint8_t* vert_ext, int64_t vert_capacity,
+                                int64_t* vert_count, float* ms) {
+  auto* c = (Ctx*)ctx;
+  if (!c || !edge_count || !vert_count) return fail(c, SASA_E_INVAL, "NULL argument");
+  int64_t m = 0;
+  float t_tri = 0.0f;
+  int rc = sasa_triangles_by_sort(ctx, nullptr, nullptr, 0, &m, &t_tri);  // unique triangles, kept on the device
+  if (rc) return rc;
+  int64_t cnt[8];
+  rc = sasa_complex_counts(ctx, cnt);
+  if (rc) return rc;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int64_t ne_cand = 3 * m + cnt[1];
+  rc = ensure_ev(c, c->se, ne_cand);
+  if (rc) return rc;
+  Bufs b = c->b;
+  b.n = (int)c->n;
+  b.nmol = std::max(c->nmol, 1);
+  hipStream_t s = nullptr;
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  for (auto& ev : e) HIP_TRY(c, hipEventCreate(&ev));
+  auto done = [&](int code) {
+    for (auto& ev : e)
+      if (ev) (void)hipEventDestroy(ev);
+    return code;
+  };
+  // edges
+  launch_zero(c->se.cursor, sizeof(unsigned long long), s);
+  launch_zero(c->se.nuniq, sizeof(unsigned), s);
+  HIP_TRY(c, hipEventRecord(e[0], s));
+  hipError_t le = launch_sorted_edges(b, c->sf.tris, c->sf.ntet, m, ne_cand, c->se, s);
+  if (le != hipSuccess) return done(fail(c, SASA_E_DEVICE, hipGetErrorString(le)));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  unsigned ue = 0;
+  unsigned long long cur = 0;
+  HIP_TRY(c, hipMemcpy(&ue, c->se.nuniq, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&cur, c->se.cursor, sizeof(cur), hipMemcpyDeviceToHost));
+  if ((int64_t)cur != cnt[1] || (int64_t)ue != cnt[1])
+    return done(fail(c, SASA_E_DEVICE, "sorted extraction: edge count differs from the complex's counters"));
+  launch_ev_unpack(c->se, ue, 2, s);
+  // vertices, from the unique edges
+  const int64_t nv_cand = 2 * (int64_t)ue + cnt[0];
+  rc = ensure_ev(c, c->sv, nv_cand);
+  if (rc) return done(rc);
+  launch_zero(c->sv.cursor, sizeof(unsigned long long), s);
+  launch_zero(c->sv.nuniq, sizeof(unsigned), s);
+  HIP_TRY(c, hipEventRecord(e[1], s));
+  // (the vertex candidates from edges read the edge step's unique count first)
+  HIP_TRY(c, hipMemcpyAsync(c->sv.nuniq, c->se.nuniq, sizeof(unsigned), hipMemcpyDeviceToDevice, s));
+  le = launch_sorted_vertices(b, c->se.uniq, c->se.agg, ue, nv_cand, c->sv, s);
+  if (le != hipSuccess) return done(fail(c, SASA_E_DEVICE, hipGetErrorString(le)));
+  HIP_TRY(c, hipEventRecord(e[2], s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  unsigned uv = 0;
+  HIP_TRY(c, hipMemcpy(&uv, c->sv.nuniq, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&cur, c->sv.cursor, sizeof(cur), hipMemcpyDeviceToHost));
+  if ((int64_t)cur != cnt[0] || (int64_t)uv != cnt[0])
+    return done(fail(c, SASA_E_DEVICE, "sorted extraction: vertex count differs from the complex's counters"));
+  launch_ev_unpack(c->sv, uv, 1, s);
+  HIP_TRY(c, hipStreamSynchronize(s));
+  float t_e = 0.0f, t_v = 0.0f;
+  HIP_TRY(c, hipEventElapsedTime(&t_e, e[0], e[1]));
+  HIP_TRY(c, hipEventElapsedTime(&t_v, e[1], e[2]));
+  *edge_count = ue;
+  *vert_count = uv;
+  if (ms) *ms = t_tri + t_e + t_v;
+  if (edges || edge_ext || verts || vert_ext) {
+    if (!edges || !edge_ext || !verts || !vert_ext)
+      return done(fail(c, SASA_E_INVAL, "sorted extraction: give all four output arrays or none"));
+    if ((int64_t)ue > edge_capacity || (int64_t)uv > vert_capacity)
+      return done(fail(c, SASA_E_CAPACITY, "sorted extraction: output capacity too small"));
+    if (ue) {
+      HIP_TRY(c, hipMemcpy(edges, c->se.out_ids, (size_t)ue * 2 * sizeof(int), hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy(edge_ext, c->se.out_ext, (size_t)ue, hipMemcpyDeviceToHost));
+    }
+    if (uv) {
+      HIP_TRY(c, hipMemcpy(verts, c->sv.out_ids, (size_t)uv * sizeof(int), hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy(vert_ext, c->sv.out_ext, (size_t)uv, hipMemcpyDeviceToHost));
+    }
+  }
+  return done(SASA_OK);
 }
 
 int sasa_complex_counts(void* ctx, int64_t counts[8]) {

@@ -180,6 +180,34 @@ struct SortedFaces {
 };
 size_t sorted_faces_temp_bytes(int64_t nfaces);
 hipError_t launch_sorted_faces(const Bufs& b, const SortedFaces& w, hipStream_t s);
+
+// Buffers of the sorted extraction of unique edges and vertices (grown on demand).
+struct SortedEV {
+  unsigned long long* keys = nullptr;   // candidates: edge (a << 21 | b) or vertex id
+  unsigned* vals = nullptr;             // bit 0: on a triangle (edge) / an edge (vertex); bit 1: an exterior one
+  unsigned long long* skeys = nullptr;  // sorted
+  unsigned* svals = nullptr;
+  unsigned long long* uniq = nullptr;  // unique keys
+  unsigned* agg = nullptr;             // OR of the values of each key
+  unsigned* nuniq = nullptr;           // 1
+  unsigned long long* cursor = nullptr;  // 1
+  int* out_ids = nullptr;                // 2 per edge / 1 per vertex
+  uint8_t* out_ext = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  long long cap = -1;  // candidate capacity of every array above
+};
+size_t sorted_ev_temp_bytes(int64_t n);
+// Unique edges: candidates from the m unique triangles (3 each) and from the
+// stars (each K-edge once, by its lower atom), sorted and reduced.
+hipError_t launch_sorted_edges(const Bufs& b, const int* tris, const uint8_t* ntet, long long m, long long ncand,
+                               const SortedEV& w, hipStream_t s);
+// Unique vertices: candidates from the ue unique edges (2 each) and from the
+// stars (every atom in K), sorted and reduced.
+hipError_t launch_sorted_vertices(const Bufs& b, const unsigned long long* edges, const unsigned* eagg, long long ue,
+                                  long long ncand, const SortedEV& w, hipStream_t s);
+// Unique keys and their OR-ed values to ids and exterior flags (edges: 2 ids).
+void launch_ev_unpack(const SortedEV& w, long long count, int ids_per_key, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int scan_blocks(unsigned hb);
 // Grid cells a batch of n atoms may use: a molecule of m > 0 atoms gets at most

@@ -1,5 +1,6 @@
-// sorted_extract.hip -- the paper's GPU extraction of unique triangles, as an
-// A/B against the per-atom classification of the star kernel.
+// sorted_extract.hip -- the paper's GPU extraction of unique triangles, edges
+// and vertices, as an A/B against the per-atom classification of the star
+// kernel.
 //
 // The paper (GPU section, extraction of exterior simplices) starts from the
 // global list of tetrahedra, lists all four faces of every tetrahedron, sorts
@@ -15,8 +16,10 @@
 // vertices inside the ball.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce_by_key.hpp>
 #include <rocprim/device/device_run_length_encode.hpp>
 
 #include "sasa_internal.h"
@@ -105,7 +108,141 @@ __global__ void k_unpack(const unsigned long long* uniq, const unsigned* counts,
   ntet[q] = q < nu ? (uint8_t)counts[q] : (uint8_t)0;
 }
 
+// Edges and vertices, the same way one dimension down (GPU section, extraction
+// of exterior simplices: unique simplices by lexicographic sorts of the
+// candidates, then classification).  Every unique triangle lists its three
+// edges with its exterior flag (n_t <= 1); every K-edge is also listed once
+// from the star of its lower atom with no flag, so that an edge on no triangle
+// still appears.  Sorting by the edge and OR-ing the flags of each run gives,
+// per unique edge, whether it lies on a triangle and on an exterior one; it is
+// exterior iff on an exterior triangle or on none (the classification rule
+// read from the paper's text).  Vertices: every unique edge lists its two atoms
+// with its exterior flag, every atom in K is listed once with none, and a
+// vertex is exterior iff it has an exterior edge or no edge.
+constexpr unsigned EV_ON = 1u, EV_EXT = 2u;
+
+__device__ inline unsigned long long edge_key(unsigned a, unsigned b) {
+  return a < b ? ((unsigned long long)a << 21) | b : ((unsigned long long)b << 21) | a;
+}
+
+__global__ void k_edges_from_tris(const int* tris, const uint8_t* ntet, long long m, unsigned long long* keys,
+                                  unsigned* vals) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const unsigned a = (unsigned)tris[3 * q], b = (unsigned)tris[3 * q + 1], c = (unsigned)tris[3 * q + 2];
+  const unsigned v = EV_ON | (ntet[q] <= 1 ? EV_EXT : 0u);
+  keys[3 * q] = edge_key(a, b), keys[3 * q + 1] = edge_key(a, c), keys[3 * q + 2] = edge_key(b, c);
+  vals[3 * q] = vals[3 * q + 1] = vals[3 * q + 2] = v;
+}
+
+// One thread per atom: its K-edges to higher atoms, after the triangles' 3m
+// candidates (slots by wave-aggregated reservation; the sort makes the order
+// immaterial).
+__global__ __launch_bounds__(64) void k_edges_from_stars(Bufs b, long long base, long long cap,
+                                                         unsigned long long* cursor, unsigned long long* keys,
+                                                         unsigned* vals) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  int nk = 0, own = 0;
+  const int* nb = nullptr;
+  if (i < b.n && (b.vflag[i] & VF_IN)) {
+    nk = min(b.kn_cnt[i], KN_CAP);
+    nb = b.knbr + (size_t)i * KN_CAP;
+    for (int k = 0; k < nk; ++k) own += i < nb[k];
+  }
+  unsigned long long p = base + reserve(cursor, own);
+  for (int k = 0; k < nk; ++k) {
+    if (!(i < nb[k])) continue;
+    if ((long long)p < cap) keys[p] = edge_key((unsigned)i, (unsigned)nb[k]), vals[p] = 0u;
+    ++p;
+  }
+}
+
+__global__ void k_vertices_from_edges(const unsigned long long* edges, const unsigned* eagg, const unsigned* nue,
+                                      unsigned long long* keys, unsigned* vals) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)*nue) return;
+  const unsigned long long e = edges[q];
+  const unsigned f = eagg[q];
+  const bool ext = !(f & EV_ON) || (f & EV_EXT);
+  const unsigned v = EV_ON | (ext ? EV_EXT : 0u);
+  keys[2 * q] = e >> 21, keys[2 * q + 1] = e & 0x1fffffull;
+  vals[2 * q] = vals[2 * q + 1] = v;
+}
+
+__global__ __launch_bounds__(64) void k_vertices_from_stars(Bufs b, const unsigned* nue, long long cap,
+                                                            unsigned long long* cursor, unsigned long long* keys,
+                                                            unsigned* vals) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int own = (i < b.n && (b.vflag[i] & VF_IN)) ? 1 : 0;
+  const unsigned long long p = 2ull * *nue + reserve(cursor, own);
+  if (own && (long long)p < cap) keys[p] = (unsigned long long)i, vals[p] = 0u;
+}
+
+// Unique keys to ids and exterior flags.
+__global__ void k_ev_unpack(const unsigned long long* uniq, const unsigned* agg, long long count, int ids_per_key,
+                            int* ids, uint8_t* ext) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const unsigned long long k = uniq[q];
+  if (ids_per_key == 2) ids[2 * q] = (int)(k >> 21), ids[2 * q + 1] = (int)(k & 0x1fffffull);
+  else ids[q] = (int)k;
+  const unsigned f = agg[q];
+  ext[q] = (!(f & EV_ON) || (f & EV_EXT)) ? 1 : 0;
+}
+
+struct BitOr {
+  __host__ __device__ unsigned operator()(unsigned a, unsigned b) const { return a | b; }
+};
+
+hipError_t sort_and_reduce(const SortedEV& w, long long ncand, unsigned end_bit, hipStream_t s) {
+  if (ncand <= 0) return hipSuccess;
+  size_t bytes = w.temp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(w.temp, bytes, w.keys, w.skeys, w.vals, w.svals, (size_t)ncand, 0u,
+                                           end_bit, s);
+  if (e != hipSuccess) return e;
+  bytes = w.temp_bytes;
+  return rocprim::reduce_by_key(w.temp, bytes, w.skeys, w.svals, (size_t)ncand, w.uniq, w.agg, w.nuniq, BitOr(),
+                                rocprim::equal_to<unsigned long long>(), s);
+}
+
 }  // namespace
+
+size_t sorted_ev_temp_bytes(int64_t n) {
+  size_t a = 0, c = 0;
+  const unsigned long long* k = nullptr;
+  unsigned long long* o = nullptr;
+  const unsigned* v = nullptr;
+  unsigned* u = nullptr;
+  size_t a2 = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, a, k, o, v, u, (size_t)n, 0u, 42u);
+  (void)rocprim::radix_sort_pairs(nullptr, a2, k, o, v, u, (size_t)n, 0u, 21u);
+  (void)rocprim::reduce_by_key(nullptr, c, k, v, (size_t)n, o, u, u, BitOr(), rocprim::equal_to<unsigned long long>());
+  return std::max(std::max(a, a2), c);
+}
+
+hipError_t launch_sorted_edges(const Bufs& b, const int* tris, const uint8_t* ntet, long long m, long long ncand,
+                               const SortedEV& w, hipStream_t s) {
+  if (m > 0) k_edges_from_tris<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(tris, ntet, m, w.keys, w.vals);
+  if (b.n) k_edges_from_stars<<<(b.n + 63) / 64, 64, 0, s>>>(b, 3 * m, w.cap, w.cursor, w.keys, w.vals);
+  hipError_t e = sort_and_reduce(w, ncand, 42u, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_sorted_vertices(const Bufs& b, const unsigned long long* edges, const unsigned* eagg, long long ue,
+                                  long long ncand, const SortedEV& w, hipStream_t s) {
+  if (ue > 0) k_vertices_from_edges<<<(unsigned)((ue + 255) / 256), 256, 0, s>>>(edges, eagg, w.nuniq, w.keys, w.vals);
+  if (b.n) k_vertices_from_stars<<<(b.n + 63) / 64, 64, 0, s>>>(b, w.nuniq, w.cap, w.cursor, w.keys, w.vals);
+  hipError_t e = sort_and_reduce(w, ncand, 21u, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+void launch_ev_unpack(const SortedEV& w, long long count, int ids_per_key, hipStream_t s) {
+  if (count > 0)
+    k_ev_unpack<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(w.uniq, w.agg, count, ids_per_key, w.out_ids,
+                                                                w.out_ext);
+}
 
 size_t sorted_faces_temp_bytes(int64_t nfaces) {
   size_t a = 0, c = 0;
