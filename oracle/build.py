@@ -29,5 +29,21 @@ def build(force=True, march_native=False):
     return LIB
 
 
+SAN_LIB = os.path.join(HERE, "libsasa_oracle_san.so")
+
+
+def build_sanitized():
+    """The same sources with AddressSanitizer and UndefinedBehaviorSanitizer
+    (-O1, frame pointers, every undefined-behaviour report fatal) into
+    oracle/libsasa_oracle_san.so, for runs in a process that preloads the
+    sanitizer runtime (tests/test_oracle_sanitizers.py)."""
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-std=c++17", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off"]
+    tmp = SAN_LIB + ".tmp"
+    subprocess.run(["g++", *flags, *SOURCES, "-o", tmp], check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(force=True, march_native="--native" in sys.argv))

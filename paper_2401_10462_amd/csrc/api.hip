@@ -1029,6 +1029,6 @@ extern "C" int sasa_compute_noalloc(int device, int64_t n, const double* xyz, co
       rc = fail(nullptr, SASA_E_CAPACITY, "an atom exceeds the per-atom neighbour / cell-vertex / star capacity");
     }
   } while (false);
-  if (prev != device) hipSetDevice(prev);
+  if (prev != device) (void)hipSetDevice(prev);
   return rc;
 }
