@@ -5,8 +5,9 @@ The library is built a second time with both sanitizers on its host code only
 the sanitizer runtime.  Without a GPU the child drives every host path that
 needs none: the capacity and footprint queries, the error strings, every entry
 point's argument checks and the failing context creation; any report ends the
-child.  (The same build can be loaded on a GPU machine to run the device paths
-with checked host code.)
+child.  (In a process that uses the GPU the sanitizer runtime's interceptor of
+the HSA memory-pool allocation refuses the runtime's first device allocation,
+so the device paths are not run this way.)
 """
 import glob
 import os
