@@ -47,8 +47,10 @@ def parse():
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--batch", type=int, default=32, help="molecules in the batched form (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU leg (0: skip)")
-    p.add_argument("--workload", default="globule", choices=["globule", "serving", "md", "gbsa", "small", "autograd"],
+    p.add_argument("--workload", default="globule",
+                   choices=["globule", "serving", "md", "local", "gbsa", "small", "autograd"],
                    help="globule: the headline line; serving: Poisson stream sweep; md: MD-like frames; "
+                        "local: frames of local moves, cold against incremental calls; "
                         "gbsa: Langevin harness with SASA forces through autograd; small: one 300-heavy-atom "
                         "globule in FP64; autograd: 64 conformations of 2,000 atoms, forward + backward")
     p.add_argument("--serve-requests", type=int, default=600, help="requests per arrival rate (serving)")
@@ -123,6 +125,59 @@ def md(args, precision):
                     "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                     "cells_kept_last_frame": int(ctx.diagnostics()["reused_cells"])}
         ctx.close()
+    return out
+
+
+def local_moves(args, precision):
+    """Config: the MD complex, each frame moving the atoms within 5 A of a random atom (a side-chain-like
+    trial move), SASA + forces every frame; a cold context against an incremental one."""
+    import torch
+    from paper_2401_10462_amd import SasaContext
+    from synth.globule import globule_complex
+    xyz, rad = globule_complex(args.md_atoms, 3)
+    n = len(rad)
+    rng = np.random.default_rng(17)
+    frames = args.frames
+    # the moves are drawn up front (groups picked on the starting structure)
+    moves = []
+    for _ in range(frames + args.warmup):
+        c = xyz[rng.integers(n)]
+        sel = np.nonzero(np.linalg.norm(xyz - c, axis=1) < 5.0)[0]
+        moves.append((sel, rng.normal(0.0, 0.3, size=(len(sel), 3))))
+    dev = torch.device("cuda:0")
+    R = torch.tensor(rad, device=dev)
+    moves = [(torch.tensor(i, device=dev), torch.tensor(d, device=dev)) for i, d in moves]
+    out = {"atoms": n, "frames": frames, "gamma": 0.005, "moved_per_frame": float(np.mean([len(i) for i, _ in moves])),
+           "structure": f"complex of {-(-n // 2500)} globules of up to 2,500 heavy atoms (seed 3)",
+           "move": "atoms within 5 A of a random atom, each displaced by N(0, 0.3^2) A per coordinate"}
+    last = {}
+    for key, inc in (("cold", False), ("incremental", True)):
+        ctx = SasaContext(precision=precision, max_atoms=n, incremental=inc)
+        X = torch.tensor(xyz, device=dev)
+        for idx, d in moves[:args.warmup]:
+            X.index_add_(0, idx, d)
+            ctx.forces(X, R, 0.005, 1.4)
+        torch.cuda.synchronize()
+        lat, kept = [], []
+        for idx, d in moves[args.warmup:]:
+            t = time.perf_counter()
+            X.index_add_(0, idx, d)
+            a, f = ctx.forces(X, R, 0.005, 1.4)
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t))
+            if inc and len(kept) < 20:
+                kept.append(ctx.diagnostics()["skipped_atoms"] / n)
+        lat = np.array(lat)
+        out[key] = {"frames_per_s": 1e3 / lat.mean(), "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99))}
+        if inc:
+            out[key]["stars_kept"] = float(np.mean(kept))
+        last[key] = (a.cpu().numpy(), f.cpu().numpy())
+        ctx.close()
+    # the same trajectory both ways: the last frame's results agree bit for bit
+    out["last_frame_equal"] = bool(np.array_equal(last["cold"][0], last["incremental"][0])
+                                   and np.array_equal(last["cold"][1], last["incremental"][1]))
+    out["speedup"] = out["incremental"]["frames_per_s"] / out["cold"]["frames_per_s"]
     return out
 
 
@@ -311,6 +366,9 @@ def main():
         return
     if args.workload == "md":
         print(json.dumps({"workload": "md", "precision": args.precision, **md(args, args.precision)}))
+        return
+    if args.workload == "local":
+        print(json.dumps({"workload": "local", "precision": args.precision, **local_moves(args, args.precision)}))
         return
 
     xyz, rad = globule(args.heavy, args.seed, hydrogens=True)

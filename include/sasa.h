@@ -66,7 +66,7 @@ enum {
   SASA_FLAG_ASYNC = 1u, /* device-pointer calls return without synchronising the stream; capacity
                            overflow and input errors are then reported by the next sasa_diagnostics */
   SASA_FLAG_TIMING = 2u, /* record HIP events around every stage of a call (stage times in sasa_diag) */
-  SASA_FLAG_FRAMES = 4u  /* consecutive calls are frames of one trajectory (same atoms, small moves).
+  SASA_FLAG_FRAMES = 4u, /* consecutive calls are frames of one trajectory (same atoms, small moves).
                             The context keeps each atom's power cell (facet neighbours and vertices
                             as plane triples) from the previous call of the same atom count.  A kept
                             cell whose vertices, solved afresh, lie inside every neighbour plane
@@ -76,6 +76,19 @@ enum {
                             order of the terms; near-degenerate decisions aside, which sasa_diag
                             counts); a call with another atom count starts without.  Costs 516
                             bytes of device memory per atom. */
+  SASA_FLAG_INCREMENTAL = 8u /* consecutive one-molecule calls (sasa_compute, sasa_compute_forces) of
+                                the same atom count and probe rebuild only the stars of atoms whose
+                                star can have changed: an atom that moved (position or radius,
+                                compared bit for bit) and every atom overlapping such an atom at its
+                                old or its new place.  The other atoms keep the star, the area and,
+                                when this call and the previous one both ask for the gradient, the
+                                gradient blocks of the previous call; the gradient sums are always
+                                redone.  Every result equals that of a context without the flag bit
+                                for bit (a star depends only on the atom and its overlapping
+                                neighbours; with SASA_FLAG_FRAMES too, up to the summation order
+                                of the terms, as for that flag alone).  When more than a quarter of the atoms moved, every
+                                star is rebuilt.  A batch, a failed call or another atom count or
+                                probe starts afresh.  Costs 77 bytes of device memory per atom. */
 };
 
 typedef struct {
@@ -269,6 +282,9 @@ typedef struct {
   int64_t reused_cells;       /* SASA_FLAG_FRAMES: atoms whose previous-frame cell was verified and kept */
   int64_t second_pass_atoms;  /* atoms the fast star pass left to the second pass (cells past 64
                                  vertices, or a side test within its rounding bound) */
+  int64_t moved_atoms;        /* SASA_FLAG_INCREMENTAL: atoms whose position or radius changed since
+                                 the previous call (all atoms when the call started afresh) */
+  int64_t skipped_atoms;      /* SASA_FLAG_INCREMENTAL: atoms whose star was kept from the previous call */
 } sasa_diag;
 int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
 

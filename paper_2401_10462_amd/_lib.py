@@ -25,6 +25,7 @@ SASA_MEM_DEVICE = 1
 SASA_FLAG_ASYNC = 1
 SASA_FLAG_TIMING = 2
 SASA_FLAG_FRAMES = 4
+SASA_FLAG_INCREMENTAL = 8
 
 # every entry point of include/sasa.h
 EXPORTS = (
@@ -54,7 +55,7 @@ class sasa_diag(ctypes.Structure):
                                              "ms_gather")] + [
         (name, ctypes.c_int64) for name in ("plane_tests", "new_vertices", "candidates", "planes_used",
                                             "max_planes_used", "atoms_over_64_planes", "reused_cells",
-                                            "second_pass_atoms")]
+                                            "second_pass_atoms", "moved_atoms", "skipped_atoms")]
 
 
 _lib = None

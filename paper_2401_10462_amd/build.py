@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsasa_hip.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "volume.hip", "sorted_extract.hip", "api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "volume.hip", "sorted_extract.hip", "incremental.hip", "api.hip")]
 HEADERS = [os.path.join(CSRC, "sasa_internal.h"), os.path.join(CSRC, "exact_side.h"), os.path.join(INCLUDE, "sasa.h")]
 # SHA-256 of the sources and flags the library was built from (written beside it)
 HASH = LIB + ".srchash"

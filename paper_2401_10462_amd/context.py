@@ -12,14 +12,18 @@ class SasaContext:
     frames: consecutive calls are frames of one trajectory; each atom's cell is
     clipped first by the previous frame's facet neighbours (same results,
     fewer cuts).
+    incremental: consecutive one-molecule calls rebuild only the stars that
+    the atoms moved since the previous call can reach (the same results; for
+    moves of a few atoms in a large molecule).
     """
 
-    def __init__(self, device=0, precision="fp64", max_atoms=0, async_calls=False, timing=False, frames=False):
+    def __init__(self, device=0, precision="fp64", max_atoms=0, async_calls=False, timing=False, frames=False,
+                 incremental=False):
         prec = {"fp64": _lib.SASA_FP64, "mixed": _lib.SASA_MIXED}[precision]
         self.precision = precision
         self.device = device
         flags = ((_lib.SASA_FLAG_ASYNC if async_calls else 0) | (_lib.SASA_FLAG_TIMING if timing else 0)
-                 | (_lib.SASA_FLAG_FRAMES if frames else 0))
+                 | (_lib.SASA_FLAG_FRAMES if frames else 0) | (_lib.SASA_FLAG_INCREMENTAL if incremental else 0))
         self._h = _lib.sasa_create(device, prec, max_atoms, flags)
         self._n, self._like_last = 0, np.zeros(0)
 

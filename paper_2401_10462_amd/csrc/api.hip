@@ -57,6 +57,16 @@ struct Ctx {
   SortedFaces sf;           // buffers of the sorted-face extraction (grown on demand)
   int64_t sf_cap_faces = -1, sf_cap_free = -1;
   SortedEV se, sv;          // the same for unique edges and vertices
+  // SASA_FLAG_INCREMENTAL: buffers (capacity-sized) and whether the last call
+  // left stars, areas (and, with inc_grad, gradient blocks) of every atom that
+  // the next call of the same system may keep
+  double4* prev_d = nullptr;
+  int* mv_id_d = nullptr;
+  double4* mv_old_d = nullptr;
+  uint8_t* dirty_d = nullptr;
+  double* area_keep_d = nullptr;
+  bool inc_valid = false;
+  bool inc_grad = false;
   sasa_diag diag{};
   std::string err;
 };
@@ -145,6 +155,14 @@ int ensure(Ctx* c, int64_t n, int nmol) {
       HIP_TRY(c, grow(&b.vtx, cap * FAC_CAP));
       HIP_TRY(c, grow(&b.hint_n, cap));
     }
+    c->inc_valid = false;
+    if (c->flags & SASA_FLAG_INCREMENTAL) {
+      HIP_TRY(c, grow(&c->prev_d, cap));
+      HIP_TRY(c, grow(&c->mv_id_d, cap));
+      HIP_TRY(c, grow(&c->mv_old_d, cap));
+      HIP_TRY(c, grow(&c->dirty_d, cap));
+      HIP_TRY(c, grow(&c->area_keep_d, cap));
+    }
     c->fac_atoms = -1;
     c->cap_n = cap;
   }
@@ -196,6 +214,7 @@ void read_times(Ctx* c) {
 }
 
 int check_errors(Ctx* c, unsigned long long bad_input, unsigned long long overflow) {
+  if (bad_input || overflow) c->inc_valid = false;
   if (bad_input) {
     c->kept = false;
     return fail(c, SASA_E_INVAL,
@@ -242,6 +261,8 @@ int read_counters(Ctx* c, hipStream_t s, bool full = true) {
   c->diag.atoms_over_64_planes = (int64_t)h[ctr_slot(C_PLANES_GT64)];
   c->diag.reused_cells = (int64_t)h[ctr_slot(C_REUSED)];
   c->diag.second_pass_atoms = (int64_t)h[ctr_slot(C_WIDE)];
+  c->diag.moved_atoms = (int64_t)h[ctr_slot(C_MOVED)];
+  c->diag.skipped_atoms = (int64_t)h[ctr_slot(C_SKIPPED)];
   read_times(c);
   return check_errors(c, h[ctr_slot(C_BAD_INPUT)], h[ctr_slot(C_OVERFLOW)]);
 }
@@ -282,6 +303,11 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   }
   c->kept = false;
   c->stats_due = false;  // the buffers may be reallocated below
+  // an incremental call keeps what the previous call of the same system left
+  // (checked before anything of this call can fail; set again once it is enqueued)
+  const bool inc = (c->flags & SASA_FLAG_INCREMENTAL) && nmol == 1 && n > 0;
+  bool inc_keep = inc && c->inc_valid && c->n == n && c->nmol == 1 && c->probe == probe;
+  c->inc_valid = false;
   if (mem == SASA_MEM_HOST && n > 0 && !host_inputs_ok(n, xyz, radii))
     return fail(c, SASA_E_INVAL, "NaN/Inf coordinate or radius <= 0 in the input");
   int rc = ensure(c, n, nmol);
@@ -333,12 +359,29 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
     launch_scan(b, s);
     launch_scatter(b, s);
   }
+  if (inc) {
+    // atoms that moved since the previous call, and the stars they can reach
+    b.prev = c->prev_d;
+    b.mv_id = c->mv_id_d;
+    b.mv_old = c->mv_old_d;
+    b.dirty = c->dirty_d;
+    b.area_keep = c->area_keep_d;
+    launch_moved(b, inc_keep, s);
+    if (inc_keep) launch_mark(b, s);
+    else b.dirty = nullptr;  // every star is rebuilt
+  }
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   launch_star(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
   launch_star_wide(b, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
-  launch_terms(b, c->precision, dA_dx != nullptr, s);
+  {
+    // kept stars keep their area, and their gradient blocks when the previous
+    // call wrote them too (the context's precision never changes)
+    Bufs bt = b;
+    if (c->inc_grad != (dA_dx != nullptr)) bt.dirty = nullptr;
+    launch_terms(bt, c->precision, dA_dx != nullptr, s);
+  }
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[4], s));
   if (dA_dx) launch_gather(b, nullptr, out, scale, s);
   if (timing) HIP_TRY(c, hipEventRecord(c->ev[5], s));
@@ -356,6 +399,8 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   c->diag.n_mol = nmol;
   const bool async = (c->flags & SASA_FLAG_ASYNC) && mem == SASA_MEM_DEVICE;
   c->kept = true;
+  c->inc_valid = inc;  // cleared again if the call reports an error
+  c->inc_grad = dA_dx != nullptr;
   c->last_stream = s;
   if (async) {
     c->pending = true;
@@ -430,7 +475,8 @@ void sasa_destroy(void* ctx) {
                  b.mol_box, b.mol_geo, b.mol_dim, b.vflag, b.stat, b.wide, b.kn_cnt, b.knbr, b.kn_ext, b.kt_cnt, b.ktet, b.ktr_cnt,
                  b.ktri, b.rows,  b.ctr,      b.ex_edges, b.ex_tris, b.ex_ntet, b.ex_tets, b.fac, b.vtx, b.hint_n,
                  c->sf.faces, c->sf.sorted, c->sf.uniq, c->sf.counts, c->sf.nruns, c->sf.free_tris, c->sf.cursors,
-                 c->sf.tris, c->sf.ntet, c->sf.temp, c->xyz_d,
+                 c->sf.tris, c->sf.ntet, c->sf.temp, c->xyz_d, c->prev_d, c->mv_id_d, c->mv_old_d, c->dirty_d,
+                 c->area_keep_d,
                  c->rad_d, c->area_d, c->out_d, c->u_d, c->off_d};
   for (void* p : dev)
     if (p) (void)hipFree(p);

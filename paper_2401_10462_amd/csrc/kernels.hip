@@ -1718,6 +1718,24 @@ template <bool HINTS>
 __global__ __launch_bounds__(64, 5) void k_star(Bufs b) {
   __shared__ StarLds<NB_CAP, V_FAST, NPL_FAST> L;
   if ((int)blockIdx.x >= b.n) return;
+  if (b.dirty) {
+    // incremental call: an atom whose star cannot have changed keeps it (and
+    // its record's sizes and simplex counts); the work counts become zero
+    const int i = b.sorted[blockIdx.x];
+    if (!b.dirty[i]) {
+      if (threadIdx.x == 0) {
+        int* st = b.stat + (size_t)i * STAT_STRIDE;
+        st[S_VMAX] = 0;
+        st[S_CAND] = 0;
+        st[S_TESTS] = 0;
+        st[S_NEWV] = 0;
+        st[S_TIES] = 0;
+        st[S_BAD] = 4;
+        st[S_KSTOP] = 0;
+      }
+      return;
+    }
+  }
   if (!star_atom<HINTS, false>(b, L, blockIdx.x, false, nullptr) && threadIdx.x == 0) {
     const unsigned long long q = atomicAdd(&b.ctr[ctr_slot(C_WIDE)], 1ull);
     b.wide[q] = (int)blockIdx.x;
@@ -1773,7 +1791,8 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
   constexpr int S_KMAX = 15;  // spare slot: the largest S_KSTOP of the block
   constexpr int S_KGT = 16;   // extra slot: atoms that visited more than 64 planes
   constexpr int S_REUSE = 17;  // extra slot: atoms that kept their previous-frame cell
-  constexpr int NV = 18;
+  constexpr int S_SKIP = 18;   // extra slot: atoms that kept their previous call's star
+  constexpr int NV = 19;
   __shared__ int part[STATS_T / 64][NV];
   const int a = blockIdx.x * STATS_T + threadIdx.x;
   int v[NV];
@@ -1788,7 +1807,8 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
   }
   v[S_KMAX] = v[S_KSTOP];
   v[S_KGT] = v[S_KSTOP] > 64 ? 1 : 0;
-  v[S_REUSE] = v[S_BAD] >> 1;
+  v[S_REUSE] = (v[S_BAD] >> 1) & 1;
+  v[S_SKIP] = (v[S_BAD] >> 2) & 1;
   v[S_BAD] &= 1;
   auto is_max = [](int q) { return q == S_NN || q == S_VMAX || q == S_KMAX; };
   for (int q = 0; q < NV; ++q)
@@ -1804,7 +1824,11 @@ __global__ __launch_bounds__(STATS_T) void k_stats(Bufs b) {
     const int q = threadIdx.x;
     long long t = part[0][q];
     for (int w = 1; w < STATS_T / 64; ++w) t = is_max(q) ? max(t, (long long)part[w][q]) : t + part[w][q];
-    const int ctr = q == S_KMAX ? C_MAX_PLANES : q == S_KGT ? C_PLANES_GT64 : q == S_REUSE ? C_REUSED : stat_counter(q);
+    const int ctr = q == S_KMAX   ? C_MAX_PLANES
+                    : q == S_KGT  ? C_PLANES_GT64
+                    : q == S_REUSE ? C_REUSED
+                    : q == S_SKIP ? C_SKIPPED
+                                  : stat_counter(q);
     if (is_max(q)) atomicMax(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
     else if (t) atomicAdd(&b.ctr[ctr_slot(ctr)], (unsigned long long)t);
   }
@@ -2032,9 +2056,16 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   }
   const int i = b.sorted[blockIdx.x];  // cell order, as in k_star
   const int lane = threadIdx.x;
+  if (b.dirty && !b.dirty[i]) {  // incremental call: star kept, so are its area and blocks
+    if (lane == 0) b.area[i] = b.area_keep[i];
+    return;
+  }
   const uint8_t vf = b.vflag[i];
   if (!(vf & VF_EXT)) {
-    if (lane == 0) b.area[i] = 0.0;
+    if (lane == 0) {
+      b.area[i] = 0.0;
+      if (b.area_keep) b.area_keep[i] = 0.0;
+    }
     return;
   }
   const bool grad = with_grad != 0;
@@ -2170,7 +2201,11 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
     os += __shfl_xor(os, off, 64);
     ap += __shfl_xor(ap, off, 64);
   }
-  if (lane == 0) b.area[i] = (1.0 - os) * Si + ap;
+  if (lane == 0) {
+    const double a = (1.0 - os) * Si + ap;
+    b.area[i] = a;
+    if (b.area_keep) b.area_keep[i] = a;
+  }
   if (!grad) return;
   // gradient block of K-neighbour k: edge + tetrahedra + triangles containing k
   if (k < nk) {

@@ -49,6 +49,8 @@ enum Counter {
   C_PLANES_GT64,   // atoms whose clipping visited more than 64 planes
   C_WIDE,          // atoms queued for the star kernel's wide pass
   C_REUSED,        // atoms whose previous-frame cell was verified and kept
+  C_MOVED,         // incremental calls: atoms moved since the previous call (queue cursor)
+  C_SKIPPED,       // ... atoms whose star was kept
   C_COUNT
 };
 // Counters sit 128 bytes apart, so that atomics on different counters never
@@ -67,7 +69,8 @@ enum Stat {
   S_TESTS,    // (vertex, plane) side tests
   S_NEWV,     // vertices created
   S_TIES,     // near-degenerate decisions
-  S_BAD,      // capacity exceeded or broken star (bit 0); previous-frame cell kept (bit 1)
+  S_BAD,      // capacity exceeded or broken star (bit 0); previous-frame cell kept (bit 1);
+              // star kept from the previous call (bit 2)
   S_VERT,     // atom is a vertex of K
   S_EXTV,     // ... an exterior one
   S_TET,      // owned simplices (lowest index)
@@ -124,6 +127,15 @@ struct Bufs {
   int* fac = nullptr;
   unsigned* vtx = nullptr;
   int* hint_n = nullptr;
+  // incremental calls (null otherwise): each atom's weighted point in the
+  // previous call (x, y, z, R), the moved atoms (ids and previous points, in
+  // queue order), the atoms whose star is rebuilt (1) or kept (0; read by the
+  // star and terms kernels only when set), and each atom's last area
+  double4* prev = nullptr;
+  int* mv_id = nullptr;
+  double4* mv_old = nullptr;
+  uint8_t* dirty = nullptr;
+  double* area_keep = nullptr;
   // results
   double* area = nullptr;
   double* rows = nullptr;    // n * ROW * 3
@@ -152,6 +164,13 @@ void launch_star_wide(const Bufs& b, hipStream_t s);   // atoms the fast pass qu
 // Largest single molecule whose cell list is built by one block.
 constexpr int64_t ONE_BLOCK_MAX_ATOMS = 8192;
 void launch_stats(const Bufs& b, hipStream_t s);
+// Incremental calls (incremental.hip), after the cell list: atoms whose point
+// changed since the previous call (b.prev updated; with `mark`, dirty[i] set
+// to whether atom i moved and the moved atoms queued), then every atom that
+// overlaps a queued atom at its old or new point marked too (all atoms when
+// more than a quarter moved).
+void launch_moved(const Bufs& b, bool mark, hipStream_t s);
+void launch_mark(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
 // Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64).

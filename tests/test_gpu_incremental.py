@@ -1,0 +1,188 @@
+"""Incremental calls (SASA_FLAG_INCREMENTAL): only the stars that moved atoms
+can reach are rebuilt; every other atom keeps its star, area and gradient
+blocks from the previous call.
+
+A star is decided by the atom's weighted point and those of the atoms whose
+balls overlap its ball (no other radical plane meets the ball), so every
+result of an incremental call must equal a cold context's bit for bit, over
+local moves, a radius change, moves far outside the previous grid, calls with
+and without the gradient, and after whatever starts afresh (a batch, a probe
+or size change, a failed call).  The mode must also do what it is for: most
+stars kept when a small group moves, none when most atoms move.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth.globule import globule
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(**kw):
+    from paper_2401_10462_amd import SasaContext
+    return SasaContext(**kw)
+
+
+def _equal(a, b, what):
+    (a1, g1), (a2, g2) = a, b
+    assert np.array_equal(a1, a2), f"{what}: areas differ (max {np.abs(a1 - a2).max():.3e})"
+    if g1 is not None or g2 is not None:
+        assert np.array_equal(g1, g2), f"{what}: gradients differ (max {np.abs(g1 - g2).max():.3e})"
+
+
+def _local_move(xyz, rng, radius=4.0, sigma=0.3):
+    """Atoms within `radius` of a random atom, each displaced by N(0, sigma^2) A (a side-chain-like move)."""
+    c = xyz[rng.integers(len(xyz))]
+    sel = np.nonzero(np.linalg.norm(xyz - c, axis=1) < radius)[0]
+    out = xyz.copy()
+    out[sel] += rng.normal(0.0, sigma, size=(len(sel), 3))
+    return out, len(sel)
+
+
+def _tiled(copies):
+    """`copies` globules of 2,000 atoms side by side (touching): one molecule."""
+    xyz, rad = globule(1000, 5, hydrogens=True)
+    xyz = xyz - xyz.mean(axis=0)
+    X = np.vstack([xyz + [30.0 * k, 0.0, 0.0] for k in range(copies)])
+    return X, np.tile(rad, copies)
+
+
+@pytest.mark.parametrize("prec,copies", [("fp64", 1), ("mixed", 1), ("fp64", 5)])
+def test_incremental_equals_cold(prec, copies):
+    """Frames of local moves (one-block and multi-kernel cell list) against a cold context."""
+    xyz, rad = _tiled(copies)
+    n = len(rad)
+    print(f"incremental {n} atoms {prec}", flush=True)
+    inc, cold = _ctx(precision=prec, incremental=True), _ctx(precision=prec)
+    rng = np.random.default_rng(21)
+
+    def step(X, R, what, grad=True, probe=1.4):
+        ri = inc.compute(X, R, probe, grad=grad)
+        di = inc.diagnostics()
+        rc = cold.compute(X, R, probe, grad=grad)
+        dc = cold.diagnostics()
+        _equal(ri, rc, what)
+        assert di["overflow"] == 0 and dc["skipped_atoms"] == 0 and dc["moved_atoms"] == 0
+        assert inc.counts() == cold.counts(), what  # the kept records still sum to the complex
+        return di
+
+    d = step(xyz, rad, "first call")
+    assert d["moved_atoms"] == n and d["skipped_atoms"] == 0
+    d = step(xyz, rad, "same coordinates")
+    assert d["moved_atoms"] == 0 and d["skipped_atoms"] == n
+    X = xyz
+    kept = []
+    for f in range(4):
+        X, moved = _local_move(X, rng)
+        d = step(X, rad, f"local move {f}")
+        assert d["moved_atoms"] == moved
+        assert d["skipped_atoms"] <= n - moved
+        kept.append(d["skipped_atoms"] / n)
+    print(f"kept stars per local move: {[round(k, 3) for k in kept]}", flush=True)
+    assert min(kept) > (0.6 if copies == 1 else 0.9)
+    # one radius changes
+    R = rad.copy()
+    R[n // 2] *= 1.1
+    d = step(X, R, "radius change")
+    assert d["moved_atoms"] == 1 and d["skipped_atoms"] > 0
+    # areas only, then the gradient again (the blocks of kept stars are stale then)
+    d = step(X, R, "areas only", grad=False)
+    assert d["skipped_atoms"] == n
+    X2, _ = _local_move(X, rng)
+    step(X2, R, "gradient after areas only")
+    X = X2
+    # a group moved far outside the previous grid, and back
+    sel = np.arange(0, n, max(1, n // 12))[:12]
+    Xf = X.copy()
+    Xf[sel] += [60.0, -45.0, 80.0]
+    d = step(Xf, R, "moved far away")
+    assert d["moved_atoms"] == len(sel)
+    d = step(X, R, "moved back")
+    assert d["moved_atoms"] == len(sel)
+    # most atoms move: every star is rebuilt
+    Xj = X + rng.normal(0.0, 0.01, size=X.shape)
+    d = step(Xj, R, "all atoms jittered")
+    assert d["skipped_atoms"] == 0
+    # another probe starts afresh
+    d = step(Xj, R, "probe change", probe=1.2)
+    assert d["skipped_atoms"] == 0 and d["moved_atoms"] == n
+    d = step(Xj, R, "same again", probe=1.2)
+    assert d["skipped_atoms"] == n
+    # the last frame against the oracle at the precision's bar
+    if copies == 1:
+        a, g = inc.compute(Xj, R, 1.2)
+        ref = oracle.run(Xj, R, 1.2)
+        tol = 1e-9 if prec == "fp64" else 1e-4
+        assert (np.abs(a - ref.area) / np.maximum(ref.area, 1.0)).max() <= tol
+        assert (np.linalg.norm(g - ref.dadx, axis=1) / np.maximum(np.linalg.norm(ref.dadx, axis=1), 1.0)).max() <= tol
+    inc.close()
+    cold.close()
+
+
+def test_incremental_restarts():
+    """A batch, a size change and a failed call in between: the next call starts afresh."""
+    import torch
+    xyz, rad = globule(1000, 5, hydrogens=True)
+    n = len(rad)
+    print(f"incremental restarts {n} atoms", flush=True)
+    inc, cold = _ctx(precision="fp64", incremental=True), _ctx(precision="fp64")
+    rng = np.random.default_rng(4)
+    inc.compute(xyz, rad, 1.4)
+    # a batch of two molecules: no star is kept, nor afterwards
+    offs = np.array([0, 800, n], dtype=np.int64)
+    _equal(inc.compute_batch(offs, xyz, rad, 1.4), cold.compute_batch(offs, xyz, rad, 1.4), "batch")
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    X, _ = _local_move(xyz, rng)
+    _equal(inc.compute(X, rad, 1.4), cold.compute(X, rad, 1.4), "after batch")
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    # a smaller molecule, then the first again
+    _equal(inc.compute(X[:1500], rad[:1500], 1.4), cold.compute(X[:1500], rad[:1500], 1.4), "smaller")
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    _equal(inc.compute(X, rad, 1.4), cold.compute(X, rad, 1.4), "size back")
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    # a call that fails on the device (NaN coordinate in device memory)
+    dev = torch.device("cuda:0")
+    Xd = torch.tensor(X, device=dev)
+    Rd = torch.tensor(rad, device=dev)
+    Xbad = Xd.clone()
+    Xbad[7, 1] = float("nan")
+    with pytest.raises(Exception):
+        inc.compute(Xbad, Rd, 1.4)
+    X3, _ = _local_move(X, rng)
+    _equal(inc.compute(X3, rad, 1.4), cold.compute(X3, rad, 1.4), "after a failed call")
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    X4, _ = _local_move(X3, rng)
+    _equal(inc.compute(X4, rad, 1.4), cold.compute(X4, rad, 1.4), "kept again")
+    assert inc.diagnostics()["skipped_atoms"] > n // 2
+    inc.close()
+    cold.close()
+
+
+def test_incremental_device_forces_and_frames():
+    """Device tensors and forces (the MD-like use); with SASA_FLAG_FRAMES too."""
+    import torch
+    xyz, rad = globule(1000, 6, hydrogens=True)
+    n = len(rad)
+    print(f"incremental device forces {n} atoms", flush=True)
+    dev = torch.device("cuda:0")
+    Rd = torch.tensor(rad, device=dev)
+    inc, cold = _ctx(precision="mixed", incremental=True), _ctx(precision="mixed")
+    both = _ctx(precision="mixed", incremental=True, frames=True)
+    rng = np.random.default_rng(8)
+    X = xyz
+    for f in range(6):
+        if f:
+            X, _ = _local_move(X, rng, radius=5.0)
+        Xd = torch.tensor(X, device=dev)
+        ai, fi = inc.forces(Xd, Rd, 0.005, 1.4)
+        ac, fc = cold.forces(Xd, Rd, 0.005, 1.4)
+        ab, fb = both.forces(Xd, Rd, 0.005, 1.4)
+        torch.cuda.synchronize()
+        assert torch.equal(ai, ac) and torch.equal(fi, fc), f"frame {f}"
+        # hinted clipping orders the terms differently: equal up to rounding
+        assert torch.allclose(ab, ac, rtol=1e-12, atol=1e-12) and torch.allclose(fb, fc, rtol=1e-12, atol=1e-12)
+        if f:
+            assert inc.diagnostics()["skipped_atoms"] > n // 2
+    for c in (inc, cold, both):
+        c.close()

@@ -16,8 +16,9 @@ import sys
 
 import pytest
 
+from paper_2401_10462_amd import build as lib_build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_2401_10462_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ASAN_RT = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
 
@@ -53,7 +54,7 @@ print("sanitized host paths ok", flush=True)
 @pytest.mark.skipif(not ASAN_RT or not os.path.exists(HIPCC), reason="no hipcc or clang AddressSanitizer runtime")
 def test_host_code_clean_under_asan_ubsan(tmp_path):
     lib = str(tmp_path / "libsasa_hip_hostsan.so")
-    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "volume.hip", "sorted_extract.hip", "api.hip")]
+    srcs = lib_build.SOURCES
     # sanitizers on the host compilation only
     cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-mcode-object-version=5",
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
