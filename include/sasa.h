@@ -91,6 +91,15 @@ enum {
                                 probe starts afresh.  Costs 77 bytes of device memory per atom. */
 };
 
+/* Opaque context: device buffers, the complex kept from the last compute and
+ * the diagnostics of the last call.  Created by sasa_create, freed by
+ * sasa_destroy; one per host thread or stream slot. */
+typedef struct sasa_context sasa_context;
+
+/* Context options.  There is no tolerance to set: every decision that builds
+ * the complex is the exact sign of its predicate, with a symbolic tie rule, so
+ * no tangency epsilon exists; the per-atom capacities are fixed
+ * (sasa_capacity). */
 typedef struct {
   int32_t device;       /* HIP device ordinal */
   int32_t precision;    /* sasa_precision */
@@ -98,15 +107,24 @@ typedef struct {
                            sized for max_atoms atoms in up to min(max_atoms, 8192) molecules per call, so
                            calls within that size never reallocate (which would wait for the device) */
   uint32_t flags;       /* SASA_FLAG_* */
-  uint32_t reserved;
+  uint32_t reserved;    /* must be 0 */
 } sasa_options;
 
-/* Create a context on opt->device (NULL opt: device 0, FP64, synchronous). */
-int sasa_create(const sasa_options* opt, void** ctx_out);
-void sasa_destroy(void* ctx);
+/*
+ * Create a context on opt->device (NULL opt: device 0, FP64, synchronous) and
+ * store it in *ctx_out (NULL on failure).  SASA_E_INVAL for a bad precision,
+ * unknown flag bits or a non-zero reserved field, SASA_E_DEVICE for a missing
+ * device, SASA_E_NOMEM if the max_atoms pre-allocation fails.
+ */
+int sasa_create(const sasa_options* opt, sasa_context** ctx_out);
+/* Wait for the context's device work and free it (NULL is ignored). */
+void sasa_destroy(sasa_context* ctx);
 
 /*
- * Per-atom SASA of one molecule and the gradient of the molecular SASA.
+ * Per-atom SASA of one molecule and the gradient of the molecular SASA
+ * (Methods, "dSASA: an analytical method for SASA"): the dual complex K of the
+ * weighted points (Steps 1 and 2), its exterior simplices, the area of Eq. 1
+ * with the terms of Eqs. 3, 4 and 6, and its gradient, Eq. 2 with Eqs. 5 and 7.
  *   n       number of atoms (0 is allowed and returns at once; at most 100,000,000,
  *           else SASA_E_INVAL)
  *   xyz     n*3 doubles, row-major (x0 y0 z0 x1 ...)
@@ -116,9 +134,11 @@ void sasa_destroy(void* ctx);
  *           hidden atoms); may be NULL
  *   dA_dx   n*3 doubles out: d(sum_i A_i)/dp_m; may be NULL
  * The context keeps the dual complex K of this call (indices only) for
- * sasa_backward and sasa_complex_export.
+ * sasa_backward and sasa_complex_export.  Errors: SASA_E_INVAL (see the codes),
+ * SASA_E_CAPACITY (an atom beyond sasa_capacity), SASA_E_NOMEM (buffers could
+ * not grow), SASA_E_DEVICE; a failed call keeps no complex.
  */
-int sasa_compute(void* ctx, int64_t n, const double* xyz, const double* radii, double probe,
+int sasa_compute(sasa_context* ctx, int64_t n, const double* xyz, const double* radii, double probe,
                  double* area, double* dA_dx, int32_t mem, void* hip_stream);
 
 /*
@@ -128,7 +148,7 @@ int sasa_compute(void* ctx, int64_t n, const double* xyz, const double* radii, d
  * never interact; every per-atom result equals the one sasa_compute gives for
  * that molecule alone.
  */
-int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const double* xyz,
+int sasa_compute_batch(sasa_context* ctx, int32_t nmol, const int64_t* offsets, const double* xyz,
                        const double* radii, double probe, double* area, double* dA_dx,
                        int32_t mem, void* hip_stream);
 
@@ -140,16 +160,17 @@ int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const do
  *   gamma   surface tension (e.g. 0.005 kcal/mol/A^2); forces in its energy unit per A
  *   forces  n*3 doubles out (required)
  */
-int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* radii, double probe,
+int sasa_compute_forces(sasa_context* ctx, int64_t n, const double* xyz, const double* radii, double probe,
                         double gamma, double* area, double* forces, int32_t mem, void* hip_stream);
 
 /*
- * Vector-Jacobian product of the last compute: dL_dx[m] = sum_i dL_dA[i] dA_i/dp_m
- * (n*3 doubles).  Recomputes the simplex geometry from the kept complex and the
+ * Vector-Jacobian product of the last compute through the derivatives of
+ * Eq. 2 (Eqs. 5 and 7 for the edge and triangle terms):
+ * dL_dx[m] = sum_i dL_dA[i] dA_i/dp_m (n doubles in, n*3 doubles out).  Recomputes the simplex geometry from the kept complex and the
  * coordinates of that compute; the coordinates are the context's own copy, so the
  * caller's input buffers may have changed.  SASA_E_STATE without a kept compute.
  */
-int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream);
+int sasa_backward(sasa_context* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream);
 
 /*
  * Volumes of the last compute (the Discussion's extension of the method to
@@ -165,7 +186,7 @@ int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, vo
  * molecular volume, not a per-atom Jacobian.  SASA_E_STATE without a kept
  * compute, SASA_E_INVAL for NULL outputs.
  */
-int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream);
+int sasa_volume(sasa_context* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream);
 
 /*
  * Vector-Jacobian product of the per-atom volumes of the last compute:
@@ -178,13 +199,16 @@ int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip
  * dL_dV = 1 gives the molecular-volume gradient of sasa_volume.  Buffers and
  * errors as sasa_backward.
  */
-int sasa_volume_backward(void* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream);
+int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream);
 
 /*
- * Sizes of the kept complex: counts[0..7] = vertices in K, edges, triangles,
- * tetrahedra, exterior vertices, exterior edges, exterior triangles, atoms.
+ * Sizes of the kept complex K of the last compute (Methods, Steps 1 and 2)
+ * and of its exterior part (GPU section, extraction of exterior simplices):
+ * counts[0..7] = vertices in K, edges, triangles, tetrahedra, exterior
+ * vertices, exterior edges, exterior triangles, atoms.  SASA_E_STATE without
+ * a kept compute.
  */
-int sasa_complex_counts(void* ctx, int64_t counts[8]);
+int sasa_complex_counts(sasa_context* ctx, int64_t counts[8]);
 
 /*
  * The unique K-triangles of the last compute and their n_t, found the way the
@@ -204,7 +228,7 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]);
  * capacity, SASA_E_INVAL for 2^21 atoms or more, SASA_E_STATE without a kept
  * compute.
  */
-int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
+int sasa_triangles_by_sort(sasa_context* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms);
 
 /*
@@ -233,23 +257,28 @@ int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t 
  * or more, SASA_E_STATE without a kept compute, SASA_E_DEVICE if the sorted
  * counts disagree with the complex's counters.
  */
-int sasa_edges_vertices_by_sort(void* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
+int sasa_edges_vertices_by_sort(sasa_context* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
                                 int64_t* edge_count, int32_t* verts, uint8_t* vert_ext, int64_t vert_capacity,
                                 int64_t* vert_count, float* ms);
 
 /*
- * Copy the kept complex to host arrays sized by sasa_complex_counts: each
- * simplex once, vertex indices ascending inside a tuple (batch-global atom
- * indices), in no particular order between tuples.
+ * Copy the kept complex K of the last compute (Methods, Steps 1 and 2; the
+ * exterior flags and n_t of the GPU section's classification) to host arrays
+ * sized by sasa_complex_counts, in canonical order: each simplex once, its
+ * atom indices ascending (batch-global), the tuples sorted lexicographically.
  *   edges (E*2), tris (T*3), tri_ntet (T: number of K-tetrahedra on the
- *   triangle), tets (Q*4), vert_flags (n: bit0 in K, bit1 exterior).
- * Any pointer may be NULL to skip that list.
+ *   triangle, in the order of tris), tets (Q*4), vert_flags (n: bit0 in K,
+ *   bit1 exterior).
+ * Any pointer may be NULL to skip that list.  Synchronous (null stream).
+ * SASA_E_STATE without a kept compute, SASA_E_NOMEM, SASA_E_DEVICE.
  */
-int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
+int sasa_complex_export(sasa_context* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
                         uint8_t* vert_flags);
 
 /*
- * Diagnostics of the last call (fills as many bytes as given, up to the struct).
+ * Diagnostics of the last call (not an operation of the method: sizes, work
+ * counts and errors of the kernels; fills as many bytes as given, up to the
+ * struct, so an older, shorter struct stays valid).
  * The size and work counts of a compute (and sasa_complex_counts) are summed
  * from per-atom records on the device the first time they are asked for after
  * that compute: one small launch on the call's stream and a synchronisation,
@@ -262,7 +291,8 @@ typedef struct {
   int64_t max_cell_vertices;  /* largest polytope size met while clipping */
   int64_t near_ties;          /* clipping side tests within their FP64 rounding bound, decided exactly */
   int64_t lost_pairs;         /* K-edges seen from one side only (near-degenerate inputs) */
-  int64_t capacity_retries;   /* star storage regrown and recomputed */
+  int64_t capacity_retries;   /* always 0: the per-atom capacities are fixed, and an atom beyond
+                                 them ends the call with SASA_E_CAPACITY (no retry) */
   int64_t input_errors;       /* NaN/Inf coordinates, radii <= 0 or equal coincident atoms seen by the device */
   int64_t overflow;           /* atoms beyond the kernels' neighbour / vertex capacity */
   double ms_total;            /* wall time of the last synchronous call */
@@ -286,19 +316,22 @@ typedef struct {
                                  the previous call (all atoms when the call started afresh) */
   int64_t skipped_atoms;      /* SASA_FLAG_INCREMENTAL: atoms whose star was kept from the previous call */
 } sasa_diag;
-int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size);
+int sasa_diagnostics(sasa_context* ctx, sasa_diag* out, int64_t size);
 
 /*
  * Error status of the last call: for a SASA_FLAG_ASYNC call, waits for its
  * stream and returns SASA_E_CAPACITY / SASA_E_INVAL as sasa_diagnostics would,
  * without summing the diagnostics counts; SASA_OK otherwise.
  */
-int sasa_status(void* ctx);
+int sasa_status(sasa_context* ctx);
 
 /*
  * Device bytes a context needs for a call of n atoms in total (all molecules of
  * a batch): the admission model of a server that packs requests by HBM
- * footprint.  Host-pointer calls add no device memory beyond this.
+ * footprint.  The same for both precisions (the buffers do not depend on
+ * them); SASA_FLAG_FRAMES adds 516 and SASA_FLAG_INCREMENTAL 77 bytes per atom,
+ * which this figure leaves out.  Host-pointer calls add no device memory
+ * beyond it.  SASA_E_INVAL for n < 0 or a NULL bytes.
  */
 int sasa_footprint(int64_t n, int64_t* bytes);
 
@@ -327,7 +360,7 @@ int sasa_compute_noalloc(int device, int64_t n, const double* xyz, const double*
                          double* area, double* dA_dx, int precision, void* hip_stream);
 
 const char* sasa_strerror(int32_t code);
-const char* sasa_last_error(void* ctx);
+const char* sasa_last_error(sasa_context* ctx);
 
 #ifdef __cplusplus
 }

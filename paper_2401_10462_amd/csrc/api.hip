@@ -7,6 +7,7 @@
 // (errors, capacity, diagnostics) back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,9 +22,8 @@
 
 using namespace sasa;
 
-namespace {
-
-struct Ctx {
+// The context behind the C-ABI's opaque handle.
+struct sasa_context {
   int device = 0;
   int precision = SASA_FP64;
   uint32_t flags = 0;
@@ -70,6 +70,10 @@ struct Ctx {
   sasa_diag diag{};
   std::string err;
 };
+
+namespace {
+
+using Ctx = sasa_context;
 
 thread_local std::string g_err;
 
@@ -411,11 +415,29 @@ int run(Ctx* c, int nmol, const int64_t* offsets, const double* xyz, const doubl
   return rc;
 }
 
+// Sorts m tuples of K atom ids (row-major) lexicographically, carrying one
+// byte per tuple along (if given).
+template <int K>
+void sort_tuples(int32_t* ids, uint8_t* tag, int64_t m) {
+  std::vector<int64_t> ord((size_t)m);
+  for (int64_t k = 0; k < m; ++k) ord[(size_t)k] = k;
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    return std::lexicographical_compare(ids + a * K, ids + a * K + K, ids + b * K, ids + b * K + K);
+  });
+  std::vector<int32_t> t(ids, ids + m * K);
+  std::vector<uint8_t> g;
+  if (tag) g.assign(tag, tag + m);
+  for (int64_t k = 0; k < m; ++k) {
+    std::memcpy(ids + k * K, t.data() + ord[(size_t)k] * K, K * sizeof(int32_t));
+    if (tag) tag[k] = g[(size_t)ord[(size_t)k]];
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
-int sasa_create(const sasa_options* opt, void** ctx_out) {
+int sasa_create(const sasa_options* opt, sasa_context** ctx_out) {
   if (!ctx_out) return fail(nullptr, SASA_E_INVAL, "ctx_out == NULL");
   *ctx_out = nullptr;
   auto* c = new (std::nothrow) Ctx;
@@ -427,6 +449,11 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
     if (c->precision != SASA_FP64 && c->precision != SASA_MIXED) {
       delete c;
       return fail(nullptr, SASA_E_INVAL, "precision must be SASA_FP64 or SASA_MIXED");
+    }
+    constexpr uint32_t kKnownFlags = SASA_FLAG_ASYNC | SASA_FLAG_TIMING | SASA_FLAG_FRAMES | SASA_FLAG_INCREMENTAL;
+    if ((opt->flags & ~kKnownFlags) || opt->reserved) {
+      delete c;
+      return fail(nullptr, SASA_E_INVAL, "unknown flag bits or non-zero reserved field in sasa_options");
     }
   }
   int ndev = 0;
@@ -465,8 +492,8 @@ int sasa_create(const sasa_options* opt, void** ctx_out) {
   return SASA_OK;
 }
 
-void sasa_destroy(void* ctx) {
-  auto* c = (Ctx*)ctx;
+void sasa_destroy(sasa_context* ctx) {
+  Ctx* c = ctx;
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
@@ -494,25 +521,25 @@ void sasa_destroy(void* ctx) {
   delete c;
 }
 
-int sasa_compute(void* ctx, int64_t n, const double* xyz, const double* radii, double probe, double* area,
+int sasa_compute(sasa_context* ctx, int64_t n, const double* xyz, const double* radii, double probe, double* area,
                  double* dA_dx, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   if (n < 0) return fail(c, SASA_E_INVAL, "n < 0");
   const int64_t off[2] = {0, n};
   return run(c, 1, off, xyz, radii, probe, area, dA_dx, mem, (hipStream_t)hip_stream);
 }
 
-int sasa_compute_batch(void* ctx, int32_t nmol, const int64_t* offsets, const double* xyz, const double* radii,
+int sasa_compute_batch(sasa_context* ctx, int32_t nmol, const int64_t* offsets, const double* xyz, const double* radii,
                        double probe, double* area, double* dA_dx, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   return run(c, nmol, offsets, xyz, radii, probe, area, dA_dx, mem, (hipStream_t)hip_stream);
 }
 
-int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* radii, double probe, double gamma,
+int sasa_compute_forces(sasa_context* ctx, int64_t n, const double* xyz, const double* radii, double probe, double gamma,
                         double* area, double* forces, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   if (n < 0) return fail(c, SASA_E_INVAL, "n < 0");
   if (!std::isfinite(gamma)) return fail(c, SASA_E_INVAL, "gamma must be finite");
@@ -521,8 +548,8 @@ int sasa_compute_forces(void* ctx, int64_t n, const double* xyz, const double* r
   return run(c, 1, off, xyz, radii, probe, area, forces, mem, (hipStream_t)hip_stream, -gamma);
 }
 
-int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+int sasa_backward(sasa_context* ctx, const double* dL_dA, double* dL_dx, int32_t mem, void* hip_stream) {
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
   if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
@@ -552,8 +579,8 @@ int sasa_backward(void* ctx, const double* dL_dA, double* dL_dx, int32_t mem, vo
   return SASA_OK;
 }
 
-int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+int sasa_volume(sasa_context* ctx, double* volume, double* dV_dx, int32_t mem, void* hip_stream) {
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
   if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
@@ -583,8 +610,8 @@ int sasa_volume(void* ctx, double* volume, double* dV_dx, int32_t mem, void* hip
   return SASA_OK;
 }
 
-int sasa_volume_backward(void* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream) {
-  auto* c = (Ctx*)ctx;
+int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream) {
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
   if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
@@ -612,9 +639,9 @@ int sasa_volume_backward(void* ctx, const double* dL_dV, double* dL_dx, int32_t 
   return SASA_OK;
 }
 
-int sasa_triangles_by_sort(void* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
+int sasa_triangles_by_sort(sasa_context* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c || !count) return fail(c, SASA_E_INVAL, "NULL argument");
   int64_t cnt[8];
   int rc = sasa_complex_counts(ctx, cnt);
@@ -710,10 +737,10 @@ int ensure_ev(Ctx* c, SortedEV& w, int64_t n) {
 }
 }  // namespace
 
-int sasa_edges_vertices_by_sort(void* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
+int sasa_edges_vertices_by_sort(sasa_context* ctx, int32_t* edges, uint8_t* edge_ext, int64_t edge_capacity,
                                 int64_t* edge_count, int32_t* verts, uint8_t* vert_ext, int64_t vert_capacity,
                                 int64_t* vert_count, float* ms) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c || !edge_count || !vert_count) return fail(c, SASA_E_INVAL, "NULL argument");
   int64_t m = 0;
   float t_tri = 0.0f;
@@ -794,8 +821,8 @@ int sasa_edges_vertices_by_sort(void* ctx, int32_t* edges, uint8_t* edge_ext, in
   return done(SASA_OK);
 }
 
-int sasa_complex_counts(void* ctx, int64_t counts[8]) {
-  auto* c = (Ctx*)ctx;
+int sasa_complex_counts(sasa_context* ctx, int64_t counts[8]) {
+  Ctx* c = ctx;
   if (!c || !counts) return fail(c, SASA_E_INVAL, "NULL argument");
   if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
   if (c->pending) {
@@ -816,9 +843,9 @@ int sasa_complex_counts(void* ctx, int64_t counts[8]) {
   return SASA_OK;
 }
 
-int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
+int sasa_complex_export(sasa_context* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_ntet, int32_t* tets,
                         uint8_t* vert_flags) {
-  auto* c = (Ctx*)ctx;
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   int64_t cnt[8];
   int rc = sasa_complex_counts(ctx, cnt);
@@ -867,16 +894,30 @@ int sasa_complex_export(void* ctx, int32_t* edges, int32_t* tris, uint8_t* tri_n
   c->stats_due = false;
   rc = read_counters(c, s);
   if (rc) return rc;
-  if (edges && cnt[1]) HIP_TRY(c, hipMemcpy(edges, b.ex_edges, (size_t)cnt[1] * 2 * sizeof(int), hipMemcpyDeviceToHost));
-  if (tris && cnt[2]) HIP_TRY(c, hipMemcpy(tris, b.ex_tris, (size_t)cnt[2] * 3 * sizeof(int), hipMemcpyDeviceToHost));
-  if (tri_ntet && cnt[2]) HIP_TRY(c, hipMemcpy(tri_ntet, b.ex_ntet, (size_t)cnt[2], hipMemcpyDeviceToHost));
-  if (tets && cnt[3]) HIP_TRY(c, hipMemcpy(tets, b.ex_tets, (size_t)cnt[3] * 4 * sizeof(int), hipMemcpyDeviceToHost));
+  // the kernels emit in arrival order; the lists are returned sorted
+  if (edges && cnt[1]) {
+    HIP_TRY(c, hipMemcpy(edges, b.ex_edges, (size_t)cnt[1] * 2 * sizeof(int), hipMemcpyDeviceToHost));
+    sort_tuples<2>(edges, nullptr, cnt[1]);
+  }
+  if ((tris || tri_ntet) && cnt[2]) {
+    std::vector<int32_t> t((size_t)cnt[2] * 3);
+    std::vector<uint8_t> nt((size_t)cnt[2]);
+    HIP_TRY(c, hipMemcpy(t.data(), b.ex_tris, t.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(nt.data(), b.ex_ntet, nt.size(), hipMemcpyDeviceToHost));
+    sort_tuples<3>(t.data(), nt.data(), cnt[2]);
+    if (tris) std::memcpy(tris, t.data(), t.size() * sizeof(int32_t));
+    if (tri_ntet) std::memcpy(tri_ntet, nt.data(), nt.size());
+  }
+  if (tets && cnt[3]) {
+    HIP_TRY(c, hipMemcpy(tets, b.ex_tets, (size_t)cnt[3] * 4 * sizeof(int), hipMemcpyDeviceToHost));
+    sort_tuples<4>(tets, nullptr, cnt[3]);
+  }
   if (vert_flags && c->n) HIP_TRY(c, hipMemcpy(vert_flags, b.vflag, (size_t)c->n, hipMemcpyDeviceToHost));
   return SASA_OK;
 }
 
-int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
-  auto* c = (Ctx*)ctx;
+int sasa_diagnostics(sasa_context* ctx, sasa_diag* out, int64_t size) {
+  Ctx* c = ctx;
   if (!c || !out || size < 0) return fail(c, SASA_E_INVAL, "NULL argument");
   int rc = SASA_OK;
   if (c->pending) rc = read_counters(c, c->last_stream);
@@ -885,8 +926,8 @@ int sasa_diagnostics(void* ctx, sasa_diag* out, int64_t size) {
   return rc;
 }
 
-int sasa_status(void* ctx) {
-  auto* c = (Ctx*)ctx;
+int sasa_status(sasa_context* ctx) {
+  Ctx* c = ctx;
   if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
   return c->pending ? read_counters(c, c->last_stream, false) : SASA_OK;
 }
@@ -923,8 +964,8 @@ const char* sasa_strerror(int32_t code) {
   return "unknown error";
 }
 
-const char* sasa_last_error(void* ctx) {
-  auto* c = (Ctx*)ctx;
+const char* sasa_last_error(sasa_context* ctx) {
+  Ctx* c = ctx;
   return c ? c->err.c_str() : g_err.c_str();
 }
 

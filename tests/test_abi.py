@@ -42,3 +42,14 @@ def test_create_without_gpu_fails_cleanly():
     from paper_2401_10462_amd import _lib
     with pytest.raises(_lib.SasaError):
         _lib.sasa_create(0)
+
+
+def test_create_refuses_unknown_options():
+    """Unknown flag bits and a non-zero reserved word are refused before any device call."""
+    from paper_2401_10462_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    for flags, reserved in ((1 << 10, 0), (0, 1)):
+        opt = _lib.sasa_options(0, _lib.SASA_FP64, 0, flags, reserved)
+        assert lib.sasa_create(ctypes.byref(opt), ctypes.byref(h)) == -1  # SASA_E_INVAL
+        assert not h.value

@@ -31,6 +31,12 @@ def _sets_gpu(ctx):
     T = {tuple(x): int(k) for x, k in zip(t.tolist(), nt.tolist())}
     Q = set(map(tuple, q.tolist()))
     assert len(E) == len(e) and len(T) == len(t) and len(Q) == len(q), "duplicate simplices"
+    # canonical order: ids ascending inside a tuple, tuples sorted
+    for a in (e, t, q):
+        if len(a):
+            assert (np.diff(a, axis=1) > 0).all(), "ids not ascending inside a tuple"
+            keys = [tuple(x) for x in a.tolist()]
+            assert keys == sorted(keys), "tuples not in lexicographic order"
     return E, T, Q, vf
 
 
