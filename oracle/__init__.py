@@ -10,7 +10,10 @@ weighted points (p_i, (r_i + probe)^2) of arXiv 2401.10462 (Methods):
 * the alpha = 0 dual complex K (vertices, edges, triangles, tetrahedra),
   each simplex decided from its definition (Steps 1-2);
 * the exterior classification (GPU section, extraction of exterior simplices);
-* per-atom SASA by Eq. 1 and the Jacobian dA_i/dp_m by Eq. 2.
+* per-atom SASA by Eq. 1 and the Jacobian dA_i/dp_m by Eq. 2;
+* per-atom volumes of the same cells (``volume``) and the integrated mean
+  curvature of the surface (``mean_curvature``), the measures the Introduction
+  and the Discussion extend the method to.
 """
 import ctypes
 import os
@@ -60,6 +63,10 @@ def lib():
         L.oracle_facet_centroid.restype = ctypes.c_double
         L.oracle_facet_centroid.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, dp]
         L.oracle_volume_vjp.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp]
+        L.oracle_exposed_arc.restype = ctypes.c_double
+        L.oracle_exposed_arc.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, dp,
+                                         dp]
+        L.oracle_mean_curvature.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp, dp]
         L.oracle_triple_term.restype = ctypes.c_double
         L.oracle_triple_term.argtypes = [dp, ctypes.c_double, dp, ctypes.c_double, dp, ctypes.c_double]
         _lib = L
@@ -226,3 +233,35 @@ def volume_vjp(xyz, radii, probe, u):
     out = np.zeros((len(radii), 3))
     lib().oracle_volume_vjp(len(radii), _dp(xyz), _dp(radii), probe, _dp(u), _dp(out))
     return out
+
+
+def exposed_arc(xyz, radii, probe, i, j):
+    """(L_ij, gamma_ij, rho_ij): exposed length of the circle where spheres i and j meet, the angle
+    between their outward normals along it and its radius (all 0 when the spheres do not cross)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    g, r = np.zeros(1), np.zeros(1)
+    L = lib().oracle_exposed_arc(len(radii), _dp(xyz), _dp(radii), probe, int(i), int(j), _dp(g), _dp(r))
+    return L, float(g[0]), float(r[0])
+
+
+def mean_curvature(xyz, radii, probe=1.4, area=None):
+    """Per-atom integrated mean curvature C_i = A_i / R_i - 1/4 sum_j L_ij gamma_ij (A) of the surface
+    of the union of the inflated balls, and (sum L gamma, sum L tan(gamma / 2)) over all pairs."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    if area is None:
+        area = run(xyz, radii, probe).area
+    area = np.ascontiguousarray(area, dtype=np.float64)
+    curv = np.zeros(len(radii))
+    sums = np.zeros(2)
+    lib().oracle_mean_curvature(len(radii), _dp(xyz), _dp(radii), probe, _dp(area), _dp(curv), _dp(sums))
+    return curv, (float(sums[0]), float(sums[1]))
+
+
+def euler_characteristic(res):
+    """V - E + T - Q of the dual complex of an oracle result: the Euler characteristic of the union of
+    the balls (the complex is homotopy equivalent to it), so its integrated Gaussian curvature is 4 pi
+    times this (Gauss-Bonnet)."""
+    c = res.counts
+    return c["vertices"] - c["edges"] + c["triangles"] - c["tetrahedra"]

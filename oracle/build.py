@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sasa_oracle.cc")
-SOURCES = [SRC, os.path.join(HERE, "predicates.cc"), os.path.join(HERE, "volume_oracle.cc")]
+SOURCES = [SRC, os.path.join(HERE, "predicates.cc"), os.path.join(HERE, "volume_oracle.cc"),
+           os.path.join(HERE, "curvature_oracle.cc")]
 HEADERS = [os.path.join(HERE, "sasa_oracle.h"), os.path.join(HERE, "predicates.h")]
 LIB = os.path.join(HERE, "libsasa_oracle.so")
 
