@@ -18,6 +18,7 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -443,6 +444,17 @@ def main():
         tb += time.perf_counter() - s
     volume = {"ms_per_call": 1e3 * tv / kv, "atoms_per_s": n * kv / tv, "calls": kv,
               "volume_A3": float(vol.sum().item()), "vjp_ms_per_call": 1e3 * tb / kv}
+    # ---- curvature measures of the same surface: per-atom integrated mean
+    # curvature (FP64) and the Euler characteristic of the union
+    ctx.compute(X, R, 1.4)
+    ctx.curvature()
+    tc = 0.0
+    for _ in range(kv):
+        s = time.perf_counter()
+        cmean, chi = ctx.curvature()
+        tc += time.perf_counter() - s
+    curvature = {"ms_per_call": 1e3 * tc / kv, "calls": kv, "mean_curvature_A": float(cmean.sum().item()),
+                 "euler_characteristic": chi, "gaussian_curvature": 4.0 * math.pi * chi}
 
     # ---- the paper's sorted extraction of the same complex (A/B against the
     # classification the star kernel does per atom): triangles, then also the
@@ -538,6 +550,7 @@ def main():
         "other_precision": other_precision,
         "host_pointers": host,
         "volume": volume,
+        "curvature": curvature,
         "sorted_extraction": sorted_extraction,
         "roofline": roofline,
         "cpu_baseline": cpu,

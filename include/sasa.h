@@ -14,7 +14,8 @@
  *     triangle terms of Eqs. 3, 4 and 6, and the derivatives of Eqs. 2, 5, 7;
  *   - the volumes of the same cells, the molecular-volume gradient and the
  *     per-atom volume VJP (sasa_volume, sasa_volume_backward; the
- *     Discussion's extension to volumes);
+ *     Discussion's extension to volumes), and the surface's integrated mean
+ *     and Gaussian curvatures (sasa_curvature; the Introduction's);
  *   - the paper's sort-based extraction of unique triangles, edges and
  *     vertices, for comparison (sasa_triangles_by_sort,
  *     sasa_edges_vertices_by_sort).
@@ -200,6 +201,30 @@ int sasa_volume(sasa_context* ctx, double* volume, double* dV_dx, int32_t mem, v
  * errors as sasa_backward.
  */
 int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, int32_t mem, void* hip_stream);
+
+/*
+ * Curvature measures of the last compute's solvent accessible surface (the
+ * Introduction extends the method from areas to volumes and to mean and
+ * Gaussian curvatures; the paper gives no formula, these are the standard
+ * ones for the piecewise smooth boundary of a union of balls):
+ *   mean[i]  n doubles out (host or device per mem; may be NULL): the
+ *            integrated mean curvature of atom i's share of the surface (A),
+ *            C_i = A_i / R_i - 1/4 sum_j L_ij gamma_ij, with L_ij the exposed
+ *            length of the circle where spheres i and j meet (a concave
+ *            crease) and gamma_ij the angle between their outward normals
+ *            along it; sum_i C_i is the integral of (k1 + k2) / 2 over the
+ *            surface, creases included.  The arcs come from the kept complex
+ *            by the inclusion-exclusion of sasa_volume; FP64 in both
+ *            precisions.
+ *   euler    host int64 out (may be NULL): V - E + T - Q of K, the Euler
+ *            characteristic of the union of the balls (K is homotopy
+ *            equivalent to it), so the integrated Gaussian curvature of the
+ *            surface is 4 pi * euler (Gauss-Bonnet).
+ * Synchronous.  SASA_E_STATE without a kept compute, SASA_E_INVAL for a bad
+ * mem or both outputs NULL.  Uses the input staging buffers of the context
+ * as scratch (the last compute's results and complex stay).
+ */
+int sasa_curvature(sasa_context* ctx, double* mean, int64_t* euler, int32_t mem, void* hip_stream);
 
 /*
  * Sizes of the kept complex K of the last compute (Methods, Steps 1 and 2)

@@ -78,6 +78,13 @@ class SasaContext:
         _lib.sasa_volume(self._h, vol, grad)
         return vol, grad
 
+    def curvature(self):
+        """Per-atom integrated mean curvature (n,) of the last compute's surface (A, FP64, like its inputs)
+        and the Euler characteristic chi of the union (integrated Gaussian curvature 4 pi chi)."""
+        mean = _like(self._like_last, (self._n,))
+        chi = _lib.sasa_curvature(self._h, mean)
+        return mean, chi
+
     def volume_backward(self, dL_dV):
         """sum_i dL_dV[i] dV_i/dx of the last compute's cell volumes (FP64)."""
         n = dL_dV.shape[0]

@@ -639,6 +639,38 @@ int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, 
   return SASA_OK;
 }
 
+int sasa_curvature(sasa_context* ctx, double* mean, int64_t* euler, int32_t mem, void* hip_stream) {
+  Ctx* c = ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (c->n > 0 && !mean && !euler) return fail(c, SASA_E_INVAL, "mean and euler must not both be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (mean && c->n) {
+    Bufs b = c->b;
+    b.n = (int)c->n;
+    b.nmol = std::max(c->nmol, 1);
+    b.area = c->area_d;  // the areas again, in FP64
+    double* cv = mem == SASA_MEM_HOST ? c->u_d : mean;
+    // the volume kernel walks the same exposed arcs; its volumes go to scratch
+    // (the input staging of the last compute, no longer needed)
+    launch_terms(b, SASA_FP64, 0, s);
+    launch_volume(b, c->xyz_d, c->out_d, s, cv);
+    HIP_TRY(c, hipGetLastError());
+    if (mem == SASA_MEM_HOST)
+      HIP_TRY(c, hipMemcpyAsync(mean, cv, (size_t)c->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  if (euler) {
+    int64_t cnt[8];
+    int rc = sasa_complex_counts(ctx, cnt);
+    if (rc) return rc;
+    *euler = cnt[0] - cnt[1] + cnt[2] - cnt[3];
+  }
+  return SASA_OK;
+}
+
 int sasa_triangles_by_sort(sasa_context* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms) {
   Ctx* c = ctx;

@@ -173,8 +173,9 @@ void launch_moved(const Bufs& b, bool mark, hipStream_t s);
 void launch_mark(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
 void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
-// Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64).
-void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s);
+// Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64),
+// and with curv the per-atom integrated mean curvature of the surface.
+void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s, double* curv = nullptr);
 // out[m] = sum_i u_i dV_i/dp_m (faces' areas and first moments).
 void launch_volume_vjp(const Bufs& b, const double* u, double* out, hipStream_t s);
 

@@ -43,6 +43,16 @@
 // triple points count, each with the sign of the arc it ends or starts), and
 // each edge's integral is its chord's, 2 a_t (y_t - c), less the parts cut off
 // at its K-tetrahedra, through the same decomposition as the lengths.
+//
+// The same exposed arcs give the integrated mean curvature of the surface
+// (the Introduction lists mean curvature beside volume as a measure the method
+// extends to; the formula is the standard one for a piecewise smooth surface):
+// the spherical patches contribute A_i / R_i, and each exposed arc of a
+// circle where two spheres meet, a concave crease of length L = rho theta,
+// contributes -L gamma / 2, gamma the angle between the two spheres' outward
+// normals along it (sin gamma = d rho / (R_i R_j), cos gamma = (R_i^2 + R_j^2 -
+// d^2) / (2 R_i R_j)).  Each arc is shared equally by its two atoms:
+//   C_i = A_i / R_i - 1/4 sum_j rho_j theta_j gamma_j.
 #include <hip/hip_runtime.h>
 
 #include "sasa_internal.h"
@@ -112,10 +122,11 @@ __device__ inline double plane_offset(const LT& L, int k, double wi) {
   return (d2 + wi - L.pw[k]) / (2.0 * sqrt(d2));
 }
 
-// MOM = false: vol[i] and the molecular-volume gradient grad[i].
+// MOM = false: vol[i] and the molecular-volume gradient grad[i], and (curv not
+// null) the integrated mean curvature curv[i].
 // MOM = true: grad[i] = sum_k u_k dV_k/dp_i for the weights u (vol unused).
 template <bool MOM>
-__global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* vol, double* grad) {
+__global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* vol, double* grad, double* curv) {
   __shared__ VolLds<MOM> L;
   const int i = blockIdx.x;
   if (i >= b.n) return;
@@ -123,6 +134,7 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* 
   const uint8_t vf = b.vflag[i];
   if (!(vf & VF_IN)) {
     if (!MOM && lane == 0) vol[i] = 0.0;
+    if (!MOM && curv && lane == 0) curv[i] = 0.0;
     if (lane < 3) grad[3 * (size_t)i + lane] = 0.0;
     return;
   }
@@ -256,7 +268,7 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* 
   }
   __syncthreads();
   // faces: one K-edge per lane (KN_CAP = 64), sums in a fixed order
-  double hv = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  double hv = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, crease = 0.0;
   const int k = lane;
   if (k < nk) {
     double phi = 0.0, seg = 0.0, arc = 0.0;
@@ -284,6 +296,10 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* 
     const double theta = kTwoPi * (1.0 - phi - arc);
     const double F = 0.5 * (rho2 * theta + seg);
     hv = h * F;
+    if (!MOM && curv) {
+      const double rho = sqrt(rho2);
+      crease = rho * theta * atan2(d * rho, 0.5 * (wi + L.pw[k] - d * d));
+    }
     if (MOM) {
       // F (cbar - p_i) = F c + M, c = h P / d the disk centre
       const double ui = u[i], uj = u[b.knbr[(size_t)i * KN_CAP + k]];
@@ -298,9 +314,11 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* 
     gx += __shfl_xor(gx, off, 64);
     gy += __shfl_xor(gy, off, 64);
     gz += __shfl_xor(gz, off, 64);
+    if (!MOM && curv) crease += __shfl_xor(crease, off, 64);
   }
   if (lane == 0) {
     if (!MOM) vol[i] = (Ri * b.area[i] + hv) / 3.0;
+    if (!MOM && curv) curv[i] = b.area[i] / Ri - 0.25 * crease;
     grad[3 * (size_t)i] = gx;
     grad[3 * (size_t)i + 1] = gy;
     grad[3 * (size_t)i + 2] = gz;
@@ -309,12 +327,12 @@ __global__ __launch_bounds__(64) void k_volume(Bufs b, const double* u, double* 
 
 }  // namespace
 
-void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s) {
-  if (b.n) k_volume<false><<<b.n, 64, 0, s>>>(b, nullptr, vol, grad);
+void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s, double* curv) {
+  if (b.n) k_volume<false><<<b.n, 64, 0, s>>>(b, nullptr, vol, grad, curv);
 }
 
 void launch_volume_vjp(const Bufs& b, const double* u, double* out, hipStream_t s) {
-  if (b.n) k_volume<true><<<b.n, 64, 0, s>>>(b, u, nullptr, out);
+  if (b.n) k_volume<true><<<b.n, 64, 0, s>>>(b, u, nullptr, out, nullptr);
 }
 
 }  // namespace sasa
