@@ -51,8 +51,9 @@ enum {
   SASA_E_NOMEM = -2,    /* device allocation failed */
   SASA_E_DEVICE = -3,   /* HIP runtime error; the context should be destroyed */
   SASA_E_STATE = -4,    /* backward / export without a preceding compute on this context */
-  SASA_E_CAPACITY = -5  /* an atom has more overlapping neighbours or cell vertices than the
-                           kernels hold (see sasa_capacity) */
+  SASA_E_CAPACITY = -5  /* an atom has more overlapping neighbours (512) or cell vertices (128) than
+                           the kernels hold (sasa_capacity), or more than 64 K-neighbours or 160
+                           K-tetrahedra or exterior K-triangles */
 };
 
 typedef enum { SASA_FP64 = 0, SASA_MIXED = 1 } sasa_precision;
@@ -360,7 +361,8 @@ int sasa_status(sasa_context* ctx);
  */
 int sasa_footprint(int64_t n, int64_t* bytes);
 
-/* Fixed per-atom kernel capacities: [0] overlapping neighbours, [1] cell vertices. */
+/* Fixed per-atom kernel capacities (those of the second pass, which takes every atom beyond the
+ * first's): [0] overlapping neighbours, [1] cell vertices. */
 void sasa_capacity(int64_t caps[2]);
 
 /*

@@ -980,7 +980,7 @@ int sasa_footprint(int64_t n, int64_t* bytes) {
 
 void sasa_capacity(int64_t caps[2]) {
   if (!caps) return;
-  caps[0] = NB_CAP;
+  caps[0] = NB_CAP_WIDE;
   caps[1] = V_CAP;
 }
 

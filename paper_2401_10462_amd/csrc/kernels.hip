@@ -864,83 +864,138 @@ __device__ bool star_atom(const Bufs& b, StarLds<NBC, VC, NPL>& L, int sidx, boo
   // s holds candidates s, s + 64, s + 128 in registers, ranks each against all
   // others (their order keys read back from LDS) and writes its plane at its
   // rank; the candidates' positions are fetched while the ranks are counted.
-  const int nsets = (nn + 63) >> 6;
-  double ck0 = 0.0, ck1 = 0.0, ck2 = 0.0;
-  int ci0 = -1, ci1 = -1, ci2 = -1;
-  if (lane < nn) ck0 = L.u.app.key[lane], ci0 = L.u.app.id[lane];
-  if (lane + 64 < nn) ck1 = L.u.app.key[lane + 64], ci1 = L.u.app.id[lane + 64];
-  if (lane + 128 < nn) ck2 = L.u.app.key[lane + 128], ci2 = L.u.app.id[lane + 128];
-  double4 cp0 = make_double4(0.0, 0.0, 0.0, 0.0), cp1 = cp0, cp2 = cp0;
-  if (ci0 >= 0) cp0 = b.pos[ci0];
-  if (ci1 >= 0) cp1 = b.pos[ci1];
-  if (ci2 >= 0) cp2 = b.pos[ci2];
-  // a neighbour whose plane bounded the previous frame's cell is clipped before
-  // all others: its key is lowered by far more than any plane distance (the
-  // order among such neighbours stays nearest plane first, ties by atom id).
-  // The cell is the same in any clipping order; this one makes few cuts and
-  // few vertices that a later cut removes.
+  constexpr int SL = (NBC + 63) / 64;  // candidates per lane
   int nfirst = 0;
-  int ft0 = -1, ft1 = -1, ft2 = -1;  // facet-list position of each candidate
-  if (HINTS && npf > 0) {
-    for (int t = 0; t < npf; ++t) {
-      const int id = rdl(pf, t);
-      if (id == ci0) ft0 = t;
-      if (id == ci1) ft1 = t;
-      if (id == ci2) ft2 = t;
+  if constexpr (SL > 3) {
+    // the wide pass's larger capacity: the same ranking over SL candidates
+    // per lane (s, s + 64, ...); their positions are fetched at the end
+    double ck[SL];
+    int ci[SL], ft[SL], rk[SL];
+    unsigned long long ok[SL];
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      ck[q] = 0.0, ci[q] = -1, ft[q] = -1, rk[q] = 0;
+      if (lane + 64 * q < nn) ck[q] = L.u.app.key[lane + 64 * q], ci[q] = L.u.app.id[lane + 64 * q];
     }
-    if (ci0 < 0) ft0 = -1;
-    if (ci1 < 0) ft1 = -1;
-    if (ci2 < 0) ft2 = -1;
-    if (ft0 >= 0) ck0 -= kFirstShift;
-    if (ft1 >= 0) ck1 -= kFirstShift;
-    if (ft2 >= 0) ck2 -= kFirstShift;
-    nfirst = __popcll(__ballot(ft0 >= 0)) + __popcll(__ballot(ft1 >= 0)) + __popcll(__ballot(ft2 >= 0));
-  }
-  const unsigned long long ok0 = order_key(ck0, ci0), ok1 = order_key(ck1, ci1), ok2 = order_key(ck2, ci2);
-  // The keys go to LDS (each lane overwrites the arrival slots it has just
-  // read), padded to an even count with a key above every candidate's; each
-  // lane then counts the keys below its own, two keys per (broadcast) read.
-  unsigned long long* okey = reinterpret_cast<unsigned long long*>(L.u.app.key);
-  if (lane < nn) okey[lane] = ok0;
-  if (lane + 64 < nn) okey[lane + 64] = ok1;
-  if (lane + 128 < nn) okey[lane + 128] = ok2;
-  if (lane == 0 && (nn & 1)) okey[nn] = ~0ull;
-  __syncthreads();
-  const ulonglong2* okp = reinterpret_cast<const ulonglong2*>(okey);
-  const int npair = (nn + 1) >> 1;
-  int rk0 = 0, rk1 = 0, rk2 = 0;
-  if (nsets == 1) {
+    if (HINTS && npf > 0) {
+      for (int t = 0; t < npf; ++t) {
+        const int id = rdl(pf, t);
+#pragma unroll
+        for (int q = 0; q < SL; ++q)
+          if (ci[q] >= 0 && id == ci[q]) ft[q] = t;
+      }
+#pragma unroll
+      for (int q = 0; q < SL; ++q) {
+        if (ft[q] >= 0) ck[q] -= kFirstShift;
+        nfirst += __popcll(__ballot(ft[q] >= 0));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SL; ++q) ok[q] = order_key(ck[q], ci[q]);
+    unsigned long long* okey = reinterpret_cast<unsigned long long*>(L.u.app.key);
+#pragma unroll
+    for (int q = 0; q < SL; ++q)
+      if (lane + 64 * q < nn) okey[lane + 64 * q] = ok[q];
+    if (lane == 0 && (nn & 1)) okey[nn] = ~0ull;
+    __syncthreads();
+    const ulonglong2* okp = reinterpret_cast<const ulonglong2*>(okey);
+    const int npair = (nn + 1) >> 1;
     for (int t = 0; t < npair; ++t) {
       const ulonglong2 kt = okp[t];
-      rk0 += (kt.x < ok0) + (kt.y < ok0);
+#pragma unroll
+      for (int q = 0; q < SL; ++q) rk[q] += (kt.x < ok[q]) + (kt.y < ok[q]);
     }
-  } else if (nsets == 2) {
-    for (int t = 0; t < npair; ++t) {
-      const ulonglong2 kt = okp[t];
-      rk0 += (kt.x < ok0) + (kt.y < ok0);
-      rk1 += (kt.x < ok1) + (kt.y < ok1);
+#pragma unroll
+    for (int q = 0; q < SL; ++q) {
+      if (ci[q] < 0) continue;
+      const int r = rk[q];
+      L.idx[r] = ci[q];
+      if (r < NPL) {
+        const Pl pl = radical_plane(pi, wi, b.pos[ci[q]]);
+        L.nx[r] = pl.x, L.ny[r] = pl.y, L.nz[r] = pl.z, L.nb[r] = pl.b;
+      }
+      L.sf.b[r] = 0;
+      L.kidx[r] = -1;
+      if (ft[q] >= 0) fslot[ft[q]] = (unsigned char)r;
     }
   } else {
-    for (int t = 0; t < npair; ++t) {
-      const ulonglong2 kt = okp[t];
-      rk0 += (kt.x < ok0) + (kt.y < ok0);
-      rk1 += (kt.x < ok1) + (kt.y < ok1);
-      rk2 += (kt.x < ok2) + (kt.y < ok2);
+    const int nsets = (nn + 63) >> 6;
+    double ck0 = 0.0, ck1 = 0.0, ck2 = 0.0;
+    int ci0 = -1, ci1 = -1, ci2 = -1;
+    if (lane < nn) ck0 = L.u.app.key[lane], ci0 = L.u.app.id[lane];
+    if (lane + 64 < nn) ck1 = L.u.app.key[lane + 64], ci1 = L.u.app.id[lane + 64];
+    if (lane + 128 < nn) ck2 = L.u.app.key[lane + 128], ci2 = L.u.app.id[lane + 128];
+    double4 cp0 = make_double4(0.0, 0.0, 0.0, 0.0), cp1 = cp0, cp2 = cp0;
+    if (ci0 >= 0) cp0 = b.pos[ci0];
+    if (ci1 >= 0) cp1 = b.pos[ci1];
+    if (ci2 >= 0) cp2 = b.pos[ci2];
+    // a neighbour whose plane bounded the previous frame's cell is clipped before
+    // all others: its key is lowered by far more than any plane distance (the
+    // order among such neighbours stays nearest plane first, ties by atom id).
+    // The cell is the same in any clipping order; this one makes few cuts and
+    // few vertices that a later cut removes.
+    int ft0 = -1, ft1 = -1, ft2 = -1;  // facet-list position of each candidate
+    if (HINTS && npf > 0) {
+      for (int t = 0; t < npf; ++t) {
+        const int id = rdl(pf, t);
+        if (id == ci0) ft0 = t;
+        if (id == ci1) ft1 = t;
+        if (id == ci2) ft2 = t;
+      }
+      if (ci0 < 0) ft0 = -1;
+      if (ci1 < 0) ft1 = -1;
+      if (ci2 < 0) ft2 = -1;
+      if (ft0 >= 0) ck0 -= kFirstShift;
+      if (ft1 >= 0) ck1 -= kFirstShift;
+      if (ft2 >= 0) ck2 -= kFirstShift;
+      nfirst = __popcll(__ballot(ft0 >= 0)) + __popcll(__ballot(ft1 >= 0)) + __popcll(__ballot(ft2 >= 0));
     }
-  }
-  for (int hb = 0; hb < 3; ++hb) {
-    const int id = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
-    if (id < 0) continue;
-    const int r = hb == 0 ? rk0 : (hb == 1 ? rk1 : rk2);
-    L.idx[r] = id;
-    if (r < NPL) {
-      const Pl q = radical_plane(pi, wi, hb == 0 ? cp0 : (hb == 1 ? cp1 : cp2));
-      L.nx[r] = q.x, L.ny[r] = q.y, L.nz[r] = q.z, L.nb[r] = q.b;
+    const unsigned long long ok0 = order_key(ck0, ci0), ok1 = order_key(ck1, ci1), ok2 = order_key(ck2, ci2);
+    // The keys go to LDS (each lane overwrites the arrival slots it has just
+    // read), padded to an even count with a key above every candidate's; each
+    // lane then counts the keys below its own, two keys per (broadcast) read.
+    unsigned long long* okey = reinterpret_cast<unsigned long long*>(L.u.app.key);
+    if (lane < nn) okey[lane] = ok0;
+    if (lane + 64 < nn) okey[lane + 64] = ok1;
+    if (lane + 128 < nn) okey[lane + 128] = ok2;
+    if (lane == 0 && (nn & 1)) okey[nn] = ~0ull;
+    __syncthreads();
+    const ulonglong2* okp = reinterpret_cast<const ulonglong2*>(okey);
+    const int npair = (nn + 1) >> 1;
+    int rk0 = 0, rk1 = 0, rk2 = 0;
+    if (nsets == 1) {
+      for (int t = 0; t < npair; ++t) {
+        const ulonglong2 kt = okp[t];
+        rk0 += (kt.x < ok0) + (kt.y < ok0);
+      }
+    } else if (nsets == 2) {
+      for (int t = 0; t < npair; ++t) {
+        const ulonglong2 kt = okp[t];
+        rk0 += (kt.x < ok0) + (kt.y < ok0);
+        rk1 += (kt.x < ok1) + (kt.y < ok1);
+      }
+    } else {
+      for (int t = 0; t < npair; ++t) {
+        const ulonglong2 kt = okp[t];
+        rk0 += (kt.x < ok0) + (kt.y < ok0);
+        rk1 += (kt.x < ok1) + (kt.y < ok1);
+        rk2 += (kt.x < ok2) + (kt.y < ok2);
+      }
     }
-    L.sf.b[r] = 0;
-    L.kidx[r] = -1;
-    const int ft = hb == 0 ? ft0 : (hb == 1 ? ft1 : ft2);
-    if (ft >= 0) fslot[ft] = (unsigned char)r;
+    for (int hb = 0; hb < 3; ++hb) {
+      const int id = hb == 0 ? ci0 : (hb == 1 ? ci1 : ci2);
+      if (id < 0) continue;
+      const int r = hb == 0 ? rk0 : (hb == 1 ? rk1 : rk2);
+      L.idx[r] = id;
+      if (r < NPL) {
+        const Pl q = radical_plane(pi, wi, hb == 0 ? cp0 : (hb == 1 ? cp1 : cp2));
+        L.nx[r] = q.x, L.ny[r] = q.y, L.nz[r] = q.z, L.nb[r] = q.b;
+      }
+      L.sf.b[r] = 0;
+      L.kidx[r] = -1;
+      const int ft = hb == 0 ? ft0 : (hb == 1 ? ft1 : ft2);
+      if (ft >= 0) fslot[ft] = (unsigned char)r;
+    }
   }
   // ---- 2. clip the cube [-h, h]^3 (h = 1.1 R_i, so it holds B_i strictly) by
   // the planes in order.  Each lane keeps cell vertices lane and lane + 64 in
@@ -1750,7 +1805,7 @@ constexpr int WIDE_BLOCKS = 64;
 
 template <bool HINTS>
 __global__ __launch_bounds__(64) void k_star_wide(Bufs b) {
-  __shared__ StarLds<NB_CAP, V_CAP, NB_CAP> L;
+  __shared__ StarLds<NB_CAP_WIDE, V_CAP, NB_CAP_WIDE> L;
   __shared__ exact::Work W;
   const int cnt = (int)b.ctr[ctr_slot(C_WIDE)];
   for (int q = blockIdx.x; q < cnt; q += gridDim.x) {

@@ -7,7 +7,8 @@
 namespace sasa {
 
 // Per-atom capacities of the star kernel (local data in LDS).
-constexpr int NB_CAP = 160;  // overlapping neighbours of one atom
+constexpr int NB_CAP = 160;  // overlapping neighbours of one atom in the fast pass
+constexpr int NB_CAP_WIDE = 512;  // ... in the second pass (large probes on dense molecules)
 constexpr int V_CAP = 128;   // vertices of the clipped power cell (two slots per lane)
 // Per-atom capacities of the kept complex (HBM).
 // A cell kept per atom between the frames of a trajectory: up to 64 facets and
@@ -33,7 +34,7 @@ enum Counter {
   C_MAX_NB,        // max overlapping neighbours (atomicMax)
   C_MAX_V,         // max polytope vertices (atomicMax)
   C_NEAR_TIE,      // near-degenerate decisions
-  C_OVERFLOW,      // atoms past NB_CAP / V_CAP / KN_CAP / KT_CAP / KTR_CAP
+  C_OVERFLOW,      // atoms past NB_CAP_WIDE / V_CAP / KN_CAP / KT_CAP / KTR_CAP
   C_BAD_INPUT,     // NaN / Inf / radius <= 0
   C_LOST_PAIR,     // K-edge seen from one side only (gather)
   C_RMAX_BITS,     // bits of max R (positive doubles order like integers)

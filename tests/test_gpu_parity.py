@@ -189,6 +189,30 @@ def test_large_cell_takes_the_wide_pass(ctxs, prec):
     _check_values(area, dadx, ref, TOL[prec])
 
 
+_LARGE_PROBE = {"600 heavy, probe 3.5": (600, False, 3.5), "400 heavy + H, probe 3.0": (400, True, 3.0)}
+_large_probe_refs = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", list(_LARGE_PROBE))
+def test_large_probe_beyond_neighbour_capacity(ctxs, case, prec):
+    """Large probes on dense globules give atoms more overlapping neighbours than the kernels hold
+    (up to 310 against 160): the second pass keeps the nearest planes and proves that the others
+    lie beyond the cell.  Same complex and values as the oracle."""
+    n, hyd, probe = _LARGE_PROBE[case]
+    xyz, rad = globule(n, 2, hydrogens=hyd)
+    print(f"large probe: {case} ({len(rad)} atoms) {prec}", flush=True)
+    if case not in _large_probe_refs:
+        _large_probe_refs[case] = oracle.run(xyz, rad, probe)
+    ref = _large_probe_refs[case]
+    ctx = ctxs[prec]
+    area, dadx = ctx.compute(xyz, rad, probe)
+    d = ctx.diagnostics()
+    assert d["max_neighbours"] > 160 and d["overflow"] == 0 and d["second_pass_atoms"] > 0
+    _check_complex(ctx, ref)
+    _check_values(area, dadx, ref, TOL[prec])
+
+
 def test_cell_beyond_every_capacity_is_an_error(ctxs):
     from paper_2401_10462_amd import _lib
     xyz, rad = _shell(90, R_center=5.0, dist=6.0)
