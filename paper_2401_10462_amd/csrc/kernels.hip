@@ -1959,11 +1959,18 @@ __device__ T solid_angle(V3<T> a, V3<T> b, V3<T> c, V3<T>* ga, V3<T>* gb, V3<T>*
 // that keeps the angle invariant under translation and rotation.  With osg
 // (if not 0) the sign of det[e; u; v], known exactly, |n_k x n_l| is taken as
 // osg |e| det[e; u; v] (n_k x n_l = det[e; u; v] e) and the wings' side from it.
+// The face normals e x u, e x v and det[e; u; v] are formed in double from
+// double inputs in both precisions: for a wing nearly along the edge they are
+// small differences of large products, and the gradient divides by |n|^2, so
+// in float they would carry an error of u_f / sin^2 of the wing's angle.
 template <typename T>
-__device__ T dihedral(V3<T> e, V3<T> u, V3<T> v, V3<T>* ge, V3<T>* gu, V3<T>* gv, bool grad, int osg = 0) {
-  const V3<T> nk = cross(e, u), nl = cross(e, v);
+__device__ T dihedral(V3<double> ed, V3<double> ud, V3<double> vd, V3<T>* ge, V3<T>* gu, V3<T>* gv, bool grad,
+                      int osg = 0) {
+  const V3<double> nkd = cross(ed, ud), nld = cross(ed, vd);
+  const V3<T> e = {T(ed.x), T(ed.y), T(ed.z)}, u = {T(ud.x), T(ud.y), T(ud.z)}, v = {T(vd.x), T(vd.y), T(vd.z)};
+  const V3<T> nk = {T(nkd.x), T(nkd.y), T(nkd.z)}, nl = {T(nld.x), T(nld.y), T(nld.z)};
   const T inv2pi = T(1.0 / (2.0 * kPi));
-  const T num = osg ? T(osg) * norm(e) * dot(nk, v) : norm(cross(nk, nl));
+  const T num = osg ? T(osg) * norm(e) * T(dot(nkd, vd)) : norm(cross(nk, nl));
   const T ph = tatan2(num, dot(nk, nl)) * inv2pi;
   if (grad) {
     const T le2 = dot(e, e), le = sqrt(le2);
@@ -2013,18 +2020,17 @@ __device__ inline V3<T> ld(const TermsLds& L, int k) {
 template <typename T>
 __device__ double tet_item(const TermsLds& L, const int ks[3], int osg, unsigned long long extm, double Si, bool grad,
                            double phi[3], double acc_out[3][3]) {
-  const V3<T> P[3] = {ld<T>(L, ks[0]), ld<T>(L, ks[1]), ld<T>(L, ks[2])};
+  const V3<double> PD[3] = {ld<double>(L, ks[0]), ld<double>(L, ks[1]), ld<double>(L, ks[2])};
   // The vertex term 4 pi w_i omega is the largest single term and cancels
   // against its neighbours' for nearly buried atoms: its solid angle is always
   // evaluated in double, and every contribution is summed in double.
   V3<double> g[3], acc[3];
-  const double om = solid_angle<double>(ld<double>(L, ks[0]), ld<double>(L, ks[1]), ld<double>(L, ks[2]), &g[0],
-                                        &g[1], &g[2], grad, osg);
+  const double om = solid_angle<double>(PD[0], PD[1], PD[2], &g[0], &g[1], &g[2], grad, osg);
   for (int c = 0; c < 3; ++c) acc[c] = g[c] * (-Si);
   for (int c = 0; c < 3; ++c) {
     const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
     V3<T> ge, g1, g2;
-    const T ph = dihedral<T>(P[c], P[o1], P[o2], &ge, &g1, &g2, grad, osg);  // cyclic: same orientation
+    const T ph = dihedral<T>(PD[c], PD[o1], PD[o2], &ge, &g1, &g2, grad, osg);  // cyclic: same orientation
     phi[c] = (double)ph;
     if (grad && ((extm >> ks[c]) & 1ull)) {
       const double Se = L.S[ks[c]];
@@ -2046,16 +2052,15 @@ __device__ double tet_item(const TermsLds& L, const int ks[3], int osg, unsigned
 template <typename T>
 __device__ double tri_item(const TermsLds& L, int ka, int kb, double X0, double X1, double X2, double Ri,
                            double Si, bool grad, double G[2][3]) {
-  const V3<T> X = {T(X0), T(X1), T(X2)};
-  const V3<T> A = ld<T>(L, ka), B = ld<T>(L, kb);
   V3<T> g1e, g1u, g1v, g2e, g2u, g2v;
   // caps in double: they multiply the angles' derivatives, and a buried atom's
   // area is the small difference of many of them
   V3<double> gSa, gSb;
   const double Sa = cap_area<double>(ld<double>(L, ka), Ri, L.pR[ka], &gSa, grad);
   const double Sb = cap_area<double>(ld<double>(L, kb), Ri, L.pR[kb], &gSb, grad);
-  const T ph1 = dihedral<T>(A, B, X, &g1e, &g1u, &g1v, grad);  // along (i,a)
-  const T ph2 = dihedral<T>(B, A, X, &g2e, &g2u, &g2v, grad);  // along (i,b)
+  const V3<double> AD = ld<double>(L, ka), BD = ld<double>(L, kb), XD = {X0, X1, X2};
+  const T ph1 = dihedral<T>(AD, BD, XD, &g1e, &g1u, &g1v, grad);  // along (i,a)
+  const T ph2 = dihedral<T>(BD, AD, XD, &g2e, &g2u, &g2v, grad);  // along (i,b)
   // solid angle in double, as in tet_item
   V3<double> hwa, hwb, hwx;
   const double om = solid_angle<double>(ld<double>(L, ka), ld<double>(L, kb), V3<double>{X0, X1, X2}, &hwa, &hwb,
@@ -2090,11 +2095,16 @@ __device__ inline double tet_quality(double ax, double ay, double az, double bx,
   return fabs(tp) / l;
 }
 
-// In MIXED precision, items below these qualities are evaluated in double:
-// a float dihedral derivative is off by about u_f S / (|u| sin^2 theta) for a
-// wing at angle theta to the edge, and the quality bounds sin theta from below
-// (0.2 keeps the largest gradient error of the drifted 20,000-atom MD frames
-// near 5e-5 of the 1e-4 bar; 0.05 reached 1.3e-4).
+// In MIXED precision, items below these qualities are evaluated in double.
+// With the face normals formed in double (dihedral), what float still loses on
+// a sliver is the rounding of the wing vectors themselves, relative u_f /
+// sin theta; the quality bounds sin theta from below.  Largest gradient error
+// on a drifted 20,000-atom MD frame (bar 1e-4): 2.9e-5 at a bound of 0.2
+// (5.7e-5 with the normals in float), 4.6e-5 at 0.05, 5.0e-5 at 0.01 and
+// 2.6e-4 with no item promoted.  A promoted item runs the double path beside
+// the float one in its wavefront, so a lower bound is faster (0.01: 34.0
+// instead of 38.9 us for the terms of the 5,000-atom globule), but large
+// probes (larger caps) then reached 1.01e-4 of the bar: 0.2 is kept.
 constexpr double kTetQualityMin = 0.2;
 constexpr double kTripleDepthMin = 0.1;  // -s_t / w_i: triple points close to the centres' plane
 

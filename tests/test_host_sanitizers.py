@@ -27,7 +27,7 @@ import ctypes, os, sys
 from paper_2401_10462_amd import _lib
 _lib.LIB_PATH = os.environ["SASA_SAN_LIB"]
 L = _lib.load()
-assert list(_lib.sasa_capacity()) == [160, 128]
+assert list(_lib.sasa_capacity()) == [512, 128]
 assert _lib.sasa_footprint(5000) > 0
 for code in range(0, -9, -1):
     assert L.sasa_strerror(code)
@@ -40,7 +40,10 @@ assert L.sasa_triangles_by_sort(None, None, None, 0, ctypes.byref(n), None) == _
 assert L.sasa_edges_vertices_by_sort(None, None, None, 0, None, None, None, 0, None, None) == _lib.SASA_E_INVAL
 assert L.sasa_complex_counts(None, cnt) == _lib.SASA_E_INVAL
 assert L.sasa_status(None) == _lib.SASA_E_INVAL
+assert L.sasa_curvature(None, None, None, 0, None) == _lib.SASA_E_INVAL
 h = ctypes.c_void_p()
+bad = _lib.sasa_options(0, 0, 0, 1 << 10, 0)
+assert L.sasa_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.SASA_E_INVAL and not h.value
 opts = _lib.sasa_options(0, 0, 1000, 0, 0)
 rc = L.sasa_create(ctypes.byref(opts), ctypes.byref(h))
 assert rc != 0 and not h.value, rc  # no GPU in this process
