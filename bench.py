@@ -160,10 +160,11 @@ def local_moves(args, precision):
             ctx.forces(X, R, 0.005, 1.4)
         torch.cuda.synchronize()
         lat, kept = [], []
+        out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev))
         for idx, d in moves[args.warmup:]:
             t = time.perf_counter()
             X.index_add_(0, idx, d)
-            a, f = ctx.forces(X, R, 0.005, 1.4)
+            a, f = ctx.forces(X, R, 0.005, 1.4, out=out)
             torch.cuda.synchronize()
             lat.append(1e3 * (time.perf_counter() - t))
             if inc and len(kept) < 20:
@@ -218,15 +219,17 @@ def small(args):
     dev = torch.device("cuda:0")
     X, R = torch.tensor(xyz, device=dev), torch.tensor(rad, device=dev)
     ctx = SasaContext(precision="fp64", max_atoms=len(rad))
+    out = (torch.empty(len(rad), dtype=torch.float64, device=dev),
+           torch.empty((len(rad), 3), dtype=torch.float64, device=dev))
     for _ in range(max(args.warmup, 3)):
-        ctx.compute(X, R, 1.4)
+        ctx.compute(X, R, 1.4, out=out)
     torch.cuda.synchronize()
     lat = []
     steps = max(args.steps, 100)
     t0 = time.perf_counter()
     for _ in range(steps):
         s = time.perf_counter()
-        ctx.compute(X, R, 1.4)
+        ctx.compute(X, R, 1.4, out=out)
         lat.append(time.perf_counter() - s)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -383,15 +386,20 @@ def main():
     ctx = SasaContext(precision=args.precision, max_atoms=n * max(args.batch, 1))
     tctx = SasaContext(precision=args.precision, max_atoms=n, timing=True)
 
-    # ---- plain form: one molecule per launch sequence
+    # ---- plain form: one molecule per launch sequence (results into the same
+    # device buffers every call, as a loop over frames or requests would)
+    def f64(*shape):
+        return torch.empty(shape, dtype=torch.float64, device=dev)
+
+    outp = (f64(n), f64(n, 3))
     for _ in range(args.warmup):
-        ctx.compute(X, R, 1.4)
+        ctx.compute(X, R, 1.4, out=outp)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s = time.perf_counter()
-        area, dadx = ctx.compute(X, R, 1.4)
+        area, dadx = ctx.compute(X, R, 1.4, out=outp)
         lat.append(time.perf_counter() - s)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -494,13 +502,14 @@ def main():
         XB = torch.tensor(np.vstack(mats), device=dev)
         RB = torch.tensor(np.tile(rad, args.batch), device=dev)
         offs = np.arange(args.batch + 1, dtype=np.int64) * n
+        outb = (f64(n * args.batch), f64(n * args.batch, 3))
         for _ in range(max(1, args.warmup)):
-            ctx.compute_batch(offs, XB, RB, 1.4)
+            ctx.compute_batch(offs, XB, RB, 1.4, out=outb)
         torch.cuda.synchronize()
         kb = max(3, args.steps // 4)
         tb = time.perf_counter()
         for _ in range(kb):
-            ab, gb = ctx.compute_batch(offs, XB, RB, 1.4)
+            ab, gb = ctx.compute_batch(offs, XB, RB, 1.4, out=outb)
         torch.cuda.synchronize()
         eb = time.perf_counter() - tb
         # the first molecule of the batch equals the plain result (rotated gradient aside)
@@ -513,12 +522,13 @@ def main():
     # ---- the same plain loop in the other precision
     other = "fp64" if args.precision == "mixed" else "mixed"
     octx = SasaContext(precision=other, max_atoms=n)
+    outo = (f64(n), f64(n, 3))  # (the plain loop's results stay in outp)
     for _ in range(args.warmup):
-        octx.compute(X, R, 1.4)
+        octx.compute(X, R, 1.4, out=outo)
     torch.cuda.synchronize()
     to = time.perf_counter()
     for _ in range(args.steps):
-        octx.compute(X, R, 1.4)
+        octx.compute(X, R, 1.4, out=outo)
     torch.cuda.synchronize()
     eo = time.perf_counter() - to
     other_precision = {"precision": other, "atoms_per_s": n * args.steps / eo, "ms_per_step": 1e3 * eo / args.steps}

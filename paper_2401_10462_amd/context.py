@@ -25,7 +25,7 @@ class SasaContext:
         flags = ((_lib.SASA_FLAG_ASYNC if async_calls else 0) | (_lib.SASA_FLAG_TIMING if timing else 0)
                  | (_lib.SASA_FLAG_FRAMES if frames else 0) | (_lib.SASA_FLAG_INCREMENTAL if incremental else 0))
         self._h = _lib.sasa_create(device, prec, max_atoms, flags)
-        self._n, self._like_last = 0, np.zeros(0)
+        self._n, self._kind_last = 0, None
 
     def close(self):
         if self._h is not None:
@@ -39,28 +39,31 @@ class SasaContext:
             pass
 
     # -------------------------------------------------------------- compute
-    def compute(self, xyz, radii, probe=1.4, grad=True):
+    # out: optional (area, gradient) buffers to fill, float64, contiguous, in
+    # the inputs' memory space (the gradient may be None with grad=False);
+    # a loop that passes the same buffers every call allocates nothing
+    def compute(self, xyz, radii, probe=1.4, grad=True, out=None):
         """Per-atom areas (n,) and d(sum A)/dx (n, 3); torch HIP tensors or numpy arrays."""
         n = xyz.shape[0]
-        area, dadx = self._outputs(xyz, n, grad)
+        area, dadx = self._outputs(xyz, n, grad, out)
         _lib.sasa_compute(self._h, n, _c(xyz), _c(radii), probe, area, dadx)
-        self._n, self._like_last = n, _like(xyz, (0,))
+        self._n, self._kind_last = n, _kind(xyz)
         return area, dadx
 
-    def compute_batch(self, offsets, xyz, radii, probe=1.4, grad=True):
+    def compute_batch(self, offsets, xyz, radii, probe=1.4, grad=True, out=None):
         """Many molecules (atoms offsets[k]..offsets[k+1]-1) in one launch sequence."""
         n = xyz.shape[0]
-        area, dadx = self._outputs(xyz, n, grad)
+        area, dadx = self._outputs(xyz, n, grad, out)
         _lib.sasa_compute_batch(self._h, offsets, _c(xyz), _c(radii), probe, area, dadx)
-        self._n, self._like_last = n, _like(xyz, (0,))
+        self._n, self._kind_last = n, _kind(xyz)
         return area, dadx
 
-    def forces(self, xyz, radii, gamma, probe=1.4):
+    def forces(self, xyz, radii, gamma, probe=1.4, out=None):
         """Per-atom areas and nonpolar forces F = -gamma dA/dx (one molecule)."""
         n = xyz.shape[0]
-        area, f = self._outputs(xyz, n, True)
+        area, f = self._outputs(xyz, n, True, out)
         _lib.sasa_compute_forces(self._h, n, _c(xyz), _c(radii), probe, gamma, area, f)
-        self._n, self._like_last = n, _like(xyz, (0,))
+        self._n, self._kind_last = n, _kind(xyz)
         return area, f
 
     def backward(self, dL_dA):
@@ -73,15 +76,14 @@ class SasaContext:
     def volume(self):
         """Per-atom cell volumes (n,) of the last compute and d(sum V)/dx (n, 3), FP64, like its inputs."""
         n = self._n
-        like = self._like_last
-        vol, grad = _like(like, (n,)), _like(like, (n, 3))
+        vol, grad = _alloc(self._kind_last, (n,)), _alloc(self._kind_last, (n, 3))
         _lib.sasa_volume(self._h, vol, grad)
         return vol, grad
 
     def curvature(self):
         """Per-atom integrated mean curvature (n,) of the last compute's surface (A, FP64, like its inputs)
         and the Euler characteristic chi of the union (integrated Gaussian curvature 4 pi chi)."""
-        mean = _like(self._like_last, (self._n,))
+        mean = _alloc(self._kind_last, (self._n,))
         chi = _lib.sasa_curvature(self._h, mean)
         return mean, chi
 
@@ -118,15 +120,45 @@ class SasaContext:
         _lib.sasa_status(self._h)
 
     @staticmethod
-    def _outputs(xyz, n, grad):
-        return _like(xyz, (n,)), (_like(xyz, (n, 3)) if grad else None)
+    def _outputs(xyz, n, grad, out=None):
+        if out is None:
+            kind = _kind(xyz)
+            return _alloc(kind, (n,)), (_alloc(kind, (n, 3)) if grad else None)
+        area, g = out
+        if area.shape != (n,) or (grad and (g is None or g.shape != (n, 3))):
+            raise ValueError("out buffers must have shapes (n,) and (n, 3)")
+        for a in (area, g if grad else None):
+            if a is not None and not _is_f64_contiguous(a):
+                raise ValueError("out buffers must be contiguous float64")
+        return area, (g if grad else None)
+
+
+def _is_f64_contiguous(a):
+    if type(a).__module__.startswith("torch"):
+        import torch
+        return a.dtype == torch.float64 and a.is_contiguous()
+    return a.dtype == np.float64 and a.flags.c_contiguous
 
 
 def _c(a):
     if type(a).__module__.startswith("torch"):
         import torch
+        if a.dtype == torch.float64 and not a.requires_grad and a.is_contiguous():
+            return a  # already what the library takes
         return a.detach().to(torch.float64).contiguous()
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _kind(a):
+    """Where results like a's go: None for numpy, else the torch device."""
+    return a.device if type(a).__module__.startswith("torch") else None
+
+
+def _alloc(kind, shape):
+    if kind is None:
+        return np.empty(shape, dtype=np.float64)
+    import torch
+    return torch.empty(shape, dtype=torch.float64, device=kind)
 
 
 def _like(a, shape):

@@ -66,6 +66,9 @@ class _Slot:
         # it only after the previous one has been finished
         self.cap = max(int(max_atoms), 1)
         self._pin = self._pinned(self.cap)
+        # device result buffers for a full slot (a batch fills a prefix)
+        self._dev = (torch.empty(self.cap, dtype=torch.float64, device=device),
+                     torch.empty((self.cap, 3), dtype=torch.float64, device=device))
 
     @staticmethod
     def _pinned(n):
@@ -86,7 +89,8 @@ class _Slot:
         with torch.cuda.stream(self.stream):
             X = xyz.to(self.device, non_blocking=True)
             R = rad.to(self.device, non_blocking=True)
-            area, grad = self.ctx.compute_batch(offs, X, R, self.probe, grad=True)
+            out = (self._dev[0][:n], self._dev[1][:n]) if n <= self.cap else None
+            area, grad = self.ctx.compute_batch(offs, X, R, self.probe, grad=True, out=out)
             self.host_out = (pin["area"][:n], pin["grad"][:n])
             self.host_out[0].copy_(area, non_blocking=True)
             self.host_out[1].copy_(grad, non_blocking=True)

@@ -219,3 +219,38 @@ def test_cell_beyond_every_capacity_is_an_error(ctxs):
     with pytest.raises(_lib.SasaError) as e:
         ctxs["fp64"].compute(xyz, rad, 1.4)
     assert e.value.code == _lib.SASA_E_CAPACITY
+
+
+def test_reused_output_buffers(ctxs):
+    """Results written into caller-given buffers, call after call, equal freshly allocated ones
+    (device and host, compute, forces and batch); buffers of the wrong shape or type are refused."""
+    import torch
+    x, r = globule(300, 1)
+    n = len(r)
+    dev = torch.device("cuda:0")
+    X, R = torch.tensor(x, device=dev), torch.tensor(r, device=dev)
+    ctx = ctxs["fp64"]
+    a0, g0 = ctx.compute(X, R, 1.4)
+    f0 = ctx.forces(X, R, 0.005, 1.4)[1]
+    out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev))
+    for _ in range(3):
+        a1, g1 = ctx.compute(X, R, 1.4, out=out)
+        assert a1.data_ptr() == out[0].data_ptr() and g1.data_ptr() == out[1].data_ptr()
+        assert torch.equal(a1, a0) and torch.equal(g1, g0)
+        assert torch.equal(ctx.forces(X, R, 0.005, 1.4, out=out)[1], f0)
+    a2, g2 = ctx.compute(X, R, 1.4, grad=False, out=(out[0], None))
+    assert g2 is None and torch.equal(a2, a0)
+    hout = (np.empty(n), np.empty((n, 3)))
+    ha, hg = ctx.compute(x, r, 1.4, out=hout)
+    assert ha is hout[0] and np.array_equal(ha, a0.cpu().numpy()) and np.array_equal(hg, g0.cpu().numpy())
+    offs = np.array([0, n, 2 * n], dtype=np.int64)
+    bout = (torch.empty(2 * n, dtype=torch.float64, device=dev), torch.empty((2 * n, 3), dtype=torch.float64, device=dev))
+    X2 = X + 50.0  # (a translated copy rounds differently: compared with its own call alone)
+    a3, g3 = ctx.compute(X2, R, 1.4)
+    ab, gb = ctx.compute_batch(offs, torch.cat([X, X2]), torch.cat([R, R]), 1.4, out=bout)
+    assert torch.equal(ab[:n], a0) and torch.equal(gb[:n], g0) and torch.equal(ab[n:], a3) and torch.equal(gb[n:], g3)
+    for bad in ((out[0][:10], out[1]), (out[0].float(), out[1]), (out[0], None)):
+        with pytest.raises(ValueError):
+            ctx.compute(X, R, 1.4, out=bad)
+    with pytest.raises(ValueError):  # host buffers for device inputs
+        ctx.compute(X, R, 1.4, out=hout)
