@@ -145,9 +145,13 @@ def mem_of(*arrays):
 
 
 def stream_of(arrays):
+    """torch's current stream on the device of the first device tensor (None: host arrays)."""
     for a in arrays:
         if a is not None and _is_torch(a) and a.is_cuda:
             import torch
+            raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)  # the handle without a Stream object
+            if raw is not None:
+                return ctypes.c_void_p(raw(a.device.index))
             return ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream)
     return None
 

@@ -254,3 +254,15 @@ def test_reused_output_buffers(ctxs):
             ctx.compute(X, R, 1.4, out=bad)
     with pytest.raises(ValueError):  # host buffers for device inputs
         ctx.compute(X, R, 1.4, out=hout)
+
+
+def test_stream_handle_is_torch_current_stream():
+    """The binding hands the library torch's current stream (default and inside a stream context)."""
+    import torch
+    from paper_2401_10462_amd import _lib
+    X = torch.zeros((4, 3), dtype=torch.float64, device="cuda:0")
+    assert _lib.stream_of((X,)).value == (torch.cuda.current_stream().cuda_stream or None)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert _lib.stream_of((X,)).value == s.cuda_stream
+    assert _lib.stream_of((np.zeros(3),)) is None
