@@ -186,3 +186,26 @@ def test_incremental_device_forces_and_frames():
             assert inc.diagnostics()["skipped_atoms"] > n // 2
     for c in (inc, cold, both):
         c.close()
+
+
+def test_incremental_with_second_pass_atoms():
+    """A large probe puts many atoms past the fast pass (more than 160 overlapping neighbours):
+    the kept and rebuilt stars still equal a cold context's, including the second pass's."""
+    xyz, rad = globule(400, 2, hydrogens=True)
+    n = len(rad)
+    print(f"incremental, probe 3.0, {n} atoms", flush=True)
+    inc, cold = _ctx(precision="mixed", incremental=True), _ctx(precision="mixed")
+    rng = np.random.default_rng(12)
+    X = xyz
+    for f in range(4):
+        if f:
+            X, _ = _local_move(X, rng, radius=4.0)
+        _equal(inc.compute(X, rad, 3.0), cold.compute(X, rad, 3.0), f"frame {f}")
+        di, dc = inc.diagnostics(), cold.diagnostics()
+        assert dc["second_pass_atoms"] > 0 and di["overflow"] == 0
+        if f:
+            assert 0 < di["skipped_atoms"] < n
+            assert di["second_pass_atoms"] < dc["second_pass_atoms"]  # only rebuilt stars are queued
+        assert inc.counts() == cold.counts()
+    inc.close()
+    cold.close()
