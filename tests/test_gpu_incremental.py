@@ -209,3 +209,45 @@ def test_incremental_with_second_pass_atoms():
         assert inc.counts() == cold.counts()
     inc.close()
     cold.close()
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_incremental_random_sequence(seed):
+    """A seeded random sequence of calls (moves of 1 to 400 atoms, radius changes, areas-only calls,
+    probe changes, unchanged repeats) on one incremental context, each compared bit for bit with a
+    cold context."""
+    xyz, rad = globule(1000, 7, hydrogens=True)
+    n = len(rad)
+    print(f"incremental random sequence, seed {seed}, {n} atoms", flush=True)
+    inc, cold = _ctx(precision="fp64", incremental=True), _ctx(precision="fp64")
+    rng = np.random.default_rng(seed)
+    X, R, probe = xyz.copy(), rad.copy(), 1.4
+    skipped = []
+    for step in range(24):
+        op = rng.integers(6)
+        grad = True
+        if op == 0:  # a group of 1..400 atoms near a random centre
+            c = X[rng.integers(n)]
+            order = np.argsort(np.linalg.norm(X - c, axis=1))[: int(rng.integers(1, 400))]
+            X = X.copy()
+            X[order] += rng.normal(0.0, float(rng.choice([0.01, 0.3, 2.0])), size=(len(order), 3))
+        elif op == 1:  # scattered single atoms
+            X = X.copy()
+            idx = rng.choice(n, size=int(rng.integers(1, 30)), replace=False)
+            X[idx] += rng.normal(0.0, 0.5, size=(len(idx), 3))
+        elif op == 2:  # radii of a few atoms
+            R = R.copy()
+            idx = rng.choice(n, size=int(rng.integers(1, 5)), replace=False)
+            R[idx] *= rng.uniform(0.9, 1.1, size=len(idx))
+        elif op == 3:
+            grad = False
+        elif op == 4 and rng.random() < 0.3:
+            probe = float(rng.choice([1.2, 1.4, 1.6]))
+        # op 5: the same input again
+        _equal(inc.compute(X, R, probe, grad=grad), cold.compute(X, R, probe, grad=grad), f"step {step} (op {op})")
+        skipped.append(inc.diagnostics()["skipped_atoms"])
+        assert inc.counts() == cold.counts()
+    print(f"kept stars per step: {skipped}", flush=True)
+    assert max(skipped) > n // 2
+    inc.close()
+    cold.close()
