@@ -228,6 +228,23 @@ int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, 
 int sasa_curvature(sasa_context* ctx, double* mean, int64_t* euler, int32_t mem, void* hip_stream);
 
 /*
+ * Vector-Jacobian product of the per-atom integrated mean curvature of the
+ * last compute (sasa_curvature; the Introduction's extension to curvatures):
+ *   dL_dx[m] = sum_i dL_dC[i] dC_i/dp_m   (n doubles in, n*3 doubles out, FP64)
+ * C_i = A_i / R_i + C_i', where C_i' = -1/4 sum_j L_ij gamma_ij is the crease
+ * part.  The first term is the area VJP (Eq. 2) with weights dL_dC[i] / R_i.
+ * The exposed share of crease circle ij, theta / 2 pi, is the edge and triangle
+ * part of the same inclusion-exclusion as Eq. 1: Phi_ij - sum_t c_t 2
+ * phi_ij(T_x).  So C_i' is the Eq. 1 edge and triangle sum with
+ * W = (pi / 2) rho gamma in place of the cap areas and no vertex term, and its
+ * gradient is Eq. 2 with the same substitution; dW/dd = (pi / 2)
+ * (gamma drho/dd + 1).  Buffers and errors as sasa_backward.  Rewrites the
+ * context's gradient blocks, so an incremental context starts afresh
+ * afterwards.
+ */
+int sasa_curvature_backward(sasa_context* ctx, const double* dL_dC, double* dL_dx, int32_t mem, void* hip_stream);
+
+/*
  * Sizes of the kept complex K of the last compute (Methods, Steps 1 and 2)
  * and of its exterior part (GPU section, extraction of exterior simplices):
  * counts[0..7] = vertices in K, edges, triangles, tetrahedra, exterior

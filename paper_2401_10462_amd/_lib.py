@@ -32,7 +32,7 @@ EXPORTS = (
     "sasa_create", "sasa_destroy", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
     "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts", "sasa_complex_export",
     "sasa_diagnostics", "sasa_status", "sasa_footprint", "sasa_capacity", "sasa_strerror", "sasa_last_error",
-    "sasa_compute_noalloc", "sasa_edges_vertices_by_sort", "sasa_curvature",
+    "sasa_compute_noalloc", "sasa_edges_vertices_by_sort", "sasa_curvature", "sasa_curvature_backward",
 )
 
 
@@ -92,6 +92,7 @@ def load():
     L.sasa_volume.argtypes = [P, P, P, I32, P]
     L.sasa_volume_backward.argtypes = [P, P, P, I32, P]
     L.sasa_curvature.argtypes = [P, P, P, I32, P]
+    L.sasa_curvature_backward.argtypes = [P, P, P, I32, P]
     L.sasa_triangles_by_sort.argtypes = [P, P, P, I64, P, P]
     L.sasa_edges_vertices_by_sort.argtypes = [P, P, P, I64, P, P, P, I64, P, P]
     L.sasa_complex_counts.argtypes = [P, P]
@@ -109,7 +110,8 @@ def load():
     L.sasa_last_error.restype = ctypes.c_char_p
     for name in ("sasa_create", "sasa_compute", "sasa_compute_batch", "sasa_compute_forces", "sasa_backward",
                  "sasa_volume", "sasa_volume_backward", "sasa_triangles_by_sort", "sasa_complex_counts",
-                 "sasa_complex_export", "sasa_diagnostics", "sasa_status", "sasa_curvature"):
+                 "sasa_complex_export", "sasa_diagnostics", "sasa_status", "sasa_curvature",
+                 "sasa_curvature_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -235,6 +237,13 @@ def sasa_curvature(ctx, mean, mem=None, stream=None):
     e = ctypes.c_int64(0)
     check(load().sasa_curvature(ctx, ptr(mean), ctypes.byref(e), mem, stream), ctx)
     return int(e.value)
+
+
+def sasa_curvature_backward(ctx, dL_dC, dL_dx, mem=None, stream=None):
+    arrs = (dL_dC, dL_dx)
+    mem = mem_of(*arrs) if mem is None else mem
+    stream = stream_of(arrs) if stream is None else stream
+    return check(load().sasa_curvature_backward(ctx, ptr(dL_dC), ptr(dL_dx), mem, stream), ctx)
 
 
 def sasa_triangles_by_sort(ctx):

@@ -87,6 +87,13 @@ class SasaContext:
         chi = _lib.sasa_curvature(self._h, mean)
         return mean, chi
 
+    def curvature_backward(self, dL_dC):
+        """sum_i dL_dC[i] dC_i/dx of the last compute's per-atom integrated mean curvature (FP64)."""
+        n = dL_dC.shape[0]
+        out = _like(dL_dC, (n, 3))
+        _lib.sasa_curvature_backward(self._h, _c(dL_dC), out)
+        return out
+
     def volume_backward(self, dL_dV):
         """sum_i dL_dV[i] dV_i/dx of the last compute's cell volumes (FP64)."""
         n = dL_dV.shape[0]

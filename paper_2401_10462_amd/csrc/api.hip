@@ -671,6 +671,45 @@ int sasa_curvature(sasa_context* ctx, double* mean, int64_t* euler, int32_t mem,
   return SASA_OK;
 }
 
+int sasa_curvature_backward(sasa_context* ctx, const double* dL_dC, double* dL_dx, int32_t mem, void* hip_stream) {
+  Ctx* c = ctx;
+  if (!c) return fail(nullptr, SASA_E_INVAL, "ctx == NULL");
+  if (!c->kept) return fail(c, SASA_E_STATE, "no kept compute on this context");
+  if (mem != SASA_MEM_HOST && mem != SASA_MEM_DEVICE) return fail(c, SASA_E_INVAL, "bad mem");
+  if (c->n > 0 && (!dL_dC || !dL_dx)) return fail(c, SASA_E_INVAL, "dL_dC / dL_dx must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->inc_valid = false;  // the gradient blocks are rewritten below
+  if (c->n) {
+    Bufs b = c->b;
+    b.n = (int)c->n;
+    b.nmol = std::max(c->nmol, 1);
+    b.area = c->area_d;
+    const double* u = dL_dC;
+    double* out = dL_dx;
+    if (mem == SASA_MEM_HOST) {
+      HIP_TRY(c, hipMemcpyAsync(c->u_d, dL_dC, (size_t)c->n * sizeof(double), hipMemcpyHostToDevice, s));
+      u = c->u_d;
+      out = c->out_d;
+    }
+    // sum_i u_i / R_i dA_i/dp (the spheres), then + sum_i u_i dC_i^crease/dp;
+    // scratch: the input staging buffers of the last compute
+    double* ur = c->xyz_d;
+    launch_recip_radius(b, u, ur, s);
+    launch_terms(b, SASA_FP64, 1, s);
+    launch_gather(b, ur, out, 1.0, s);
+    Bufs bc = b;
+    bc.area = c->rad_d;
+    launch_terms_crease(bc, 1, s);
+    launch_gather(bc, u, out, 1.0, s, 1);
+    HIP_TRY(c, hipGetLastError());
+    if (mem == SASA_MEM_HOST)
+      HIP_TRY(c, hipMemcpyAsync(dL_dx, out, (size_t)c->n * 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  if (mem == SASA_MEM_HOST || !(c->flags & SASA_FLAG_ASYNC)) HIP_TRY(c, hipStreamSynchronize(s));
+  return SASA_OK;
+}
+
 int sasa_triangles_by_sort(sasa_context* ctx, int32_t* tris, uint8_t* tri_ntet, int64_t capacity, int64_t* count,
                            float* ms) {
   Ctx* c = ctx;

@@ -1994,6 +1994,38 @@ __device__ T cap_area(V3<T> a, T R, T Ra, V3<T>* g, bool grad) {
   return T(2.0 * kPi) * R * h;
 }
 
+// Crease weight of the circle where sphere i (radius R, centre at the origin)
+// meets sphere a (centre a, radius Ra): W = (pi / 2) rho gamma, rho the
+// circle's radius and gamma the angle between the two spheres' outward normals
+// along it (sin gamma = d rho / (R Ra), cos gamma = (R^2 + Ra^2 - d^2) /
+// (2 R Ra)), and its gradient with respect to a.  The integrated mean
+// curvature of the surface has, besides the spheres' A_i / R_i, the part
+// -1/4 L gamma of each exposed crease arc of length L = rho theta per atom;
+// with theta / 2 pi = Phi - sum_t c_t 2 phi(T_x) (the exposed share of the
+// circle, as the volume kernel uses it) that part is the Eq. 1 edge and
+// triangle sums with W in place of the cap areas and no vertex term.  With
+// dgamma/dd = 1 / rho, dW/dd = (pi / 2) (gamma drho/dd + 1).
+__device__ inline double crease_weight(V3<double> a, double R, double Ra, V3<double>* g, bool grad) {
+  const double d2 = dot(a, a), d = sqrt(d2), w = R * R, wa = Ra * Ra;
+  const double h = (d2 + w - wa) / (2.0 * d);
+  const double rho = sqrt(fmax(w - h * h, 0.0));
+  const double gam = atan2(d * rho, 0.5 * (w + wa - d2));
+  if (grad) {
+    const double dh = 0.5 * (1.0 - (w - wa) / d2);
+    const double drho = rho > 0.0 ? -h * dh / rho : 0.0;
+    *g = a * (0.5 * kPi * (gam * drho + 1.0) / d);
+  }
+  return 0.5 * kPi * rho * gam;
+}
+
+// Edge weight of the terms: the cap area (the area, Eq. 1), or the crease
+// weight (CR: the mean curvature's crease part).
+template <bool CR>
+__device__ inline double edge_weight(V3<double> a, double R, double Ra, V3<double>* g, bool grad) {
+  if constexpr (CR) return crease_weight(a, R, Ra, g, grad);
+  else return cap_area<double>(a, R, Ra, g, grad);
+}
+
 struct TermsLds {
   double px[KN_CAP], py[KN_CAP], pz[KN_CAP], pR[KN_CAP];
   unsigned tet[KT_CAP];
@@ -2049,15 +2081,15 @@ __device__ double tet_item(const TermsLds& L, const int ks[3], int osg, unsigned
 // gradient (Eq. 7) includes the chain rule through the triple point x, whose
 // derivative follows from |x - p_m|^2 = w_m:  M dx = [(x - p_m) . dp_m]_m with
 // rows of M = (x - p_m)^T, so dS/dp_m += lambda_m (x - p_m), M^T lambda = dS/dx.
-template <typename T>
+template <typename T, bool CR = false>
 __device__ double tri_item(const TermsLds& L, int ka, int kb, double X0, double X1, double X2, double Ri,
                            double Si, bool grad, double G[2][3]) {
   V3<T> g1e, g1u, g1v, g2e, g2u, g2v;
   // caps in double: they multiply the angles' derivatives, and a buried atom's
   // area is the small difference of many of them
   V3<double> gSa, gSb;
-  const double Sa = cap_area<double>(ld<double>(L, ka), Ri, L.pR[ka], &gSa, grad);
-  const double Sb = cap_area<double>(ld<double>(L, kb), Ri, L.pR[kb], &gSb, grad);
+  const double Sa = edge_weight<CR>(ld<double>(L, ka), Ri, L.pR[ka], &gSa, grad);
+  const double Sb = edge_weight<CR>(ld<double>(L, kb), Ri, L.pR[kb], &gSb, grad);
   const V3<double> AD = ld<double>(L, ka), BD = ld<double>(L, kb), XD = {X0, X1, X2};
   const T ph1 = dihedral<T>(AD, BD, XD, &g1e, &g1u, &g1v, grad);  // along (i,a)
   const T ph2 = dihedral<T>(BD, AD, XD, &g2e, &g2u, &g2v, grad);  // along (i,b)
@@ -2108,7 +2140,9 @@ __device__ inline double tet_quality(double ax, double ay, double az, double bx,
 constexpr double kTetQualityMin = 0.2;
 constexpr double kTripleDepthMin = 0.1;  // -s_t / w_i: triple points close to the centres' plane
 
-template <typename T>
+// CR: the crease part of the integrated mean curvature instead of the area
+// (edge weights W, no vertex term; b.area receives the per-atom part).
+template <typename T, bool CR = false>
 __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   __shared__ TermsLds L;
   if ((int)blockIdx.x >= b.n) return;
@@ -2148,7 +2182,7 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   for (int t = lane; t < nt; t += 64) L.tet[t] = b.ktet[(size_t)i * KT_CAP + t];
   for (int t = lane; t < nr; t += 64) L.tri[t] = b.ktri[(size_t)i * KTR_CAP + t];
   __syncthreads();
-  const double Si = 4.0 * kPi * wi;
+  const double Si = CR ? 0.0 : 4.0 * kPi * wi;
   // edges: cap areas, in double in both precisions (they multiply the
   // dihedral angles and their derivatives, and a buried atom's area is the
   // small difference of many of them)
@@ -2157,7 +2191,7 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
   const int k = lane;  // one K-neighbour per lane (KN_CAP = 64)
   const bool kext = k < nk && ((extm >> k) & 1ull);
   if (kext) {
-    Sk = cap_area<double>(ld<double>(L, k), Ri, L.pR[k], &gS, grad);
+    Sk = edge_weight<CR>(ld<double>(L, k), Ri, L.pR[k], &gS, grad);
     L.S[k] = Sk;
   }
   __syncthreads();
@@ -2239,8 +2273,8 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
           bool dbl = sizeof(T) == sizeof(double);
           if (!dbl)
             dbl = (-s < kTripleDepthMin * wi) || tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin;
-          St = dbl ? tri_item<double>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
-                   : tri_item<T>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
+          St = dbl ? tri_item<double, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
+                   : tri_item<T, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
         }
       }
       area_part += ct * St;
@@ -2301,7 +2335,7 @@ __device__ inline double sum16(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* out, double scale) {
+__global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* out, double scale, int accumulate) {
   const int sub = threadIdx.x & 15;
   const int m = blockIdx.x * 4 + (threadIdx.x >> 4);
   double gx = 0, gy = 0, gz = 0;
@@ -2342,11 +2376,24 @@ __global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* 
   gz = sum16(gz);
   for (int off = 8; off > 0; off >>= 1) lost += __shfl_xor(lost, off, 64);
   if (m < b.n && sub == 0) {
-    out[3 * m] = scale * gx;
-    out[3 * m + 1] = scale * gy;
-    out[3 * m + 2] = scale * gz;
+    if (accumulate) {
+      out[3 * m] += scale * gx;
+      out[3 * m + 1] += scale * gy;
+      out[3 * m + 2] += scale * gz;
+    } else {
+      out[3 * m] = scale * gx;
+      out[3 * m + 1] = scale * gy;
+      out[3 * m + 2] = scale * gz;
+    }
     if (lost) atomicAdd(&b.ctr[ctr_slot(C_LOST_PAIR)], (unsigned long long)lost);
   }
+}
+
+// out[i] = u[i] / R_i (u = NULL: 1 / R_i): the weights that turn the area
+// VJP into that of sum_i u_i A_i / R_i.
+__global__ void k_recip_radius(Bufs b, const double* u, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < b.n) out[i] = (u ? u[i] : 1.0) / b.pos[i].w;
 }
 
 __global__ void k_zero(unsigned* p, size_t words) {
@@ -2406,8 +2453,14 @@ void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s) {
   if (precision == 1) k_terms<float><<<b.n, 64, 0, s>>>(b, with_grad);
   else k_terms<double><<<b.n, 64, 0, s>>>(b, with_grad);
 }
-void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s) {
-  if (b.n) k_gather<<<blocks(b.n, 4), 64, 0, s>>>(b, u, out, scale);
+void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s, int accumulate) {
+  if (b.n) k_gather<<<blocks(b.n, 4), 64, 0, s>>>(b, u, out, scale, accumulate);
+}
+void launch_terms_crease(const Bufs& b, int with_grad, hipStream_t s) {
+  if (b.n) k_terms<double, true><<<b.n, 64, 0, s>>>(b, with_grad);
+}
+void launch_recip_radius(const Bufs& b, const double* u, double* out, hipStream_t s) {
+  if (b.n) k_recip_radius<<<blocks(b.n, 256), 256, 0, s>>>(b, u, out);
 }
 
 }  // namespace sasa

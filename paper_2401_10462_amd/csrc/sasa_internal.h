@@ -173,7 +173,13 @@ void launch_stats(const Bufs& b, hipStream_t s);
 void launch_moved(const Bufs& b, bool mark, hipStream_t s);
 void launch_mark(const Bufs& b, hipStream_t s);
 void launch_terms(const Bufs& b, int precision, int with_grad, hipStream_t s);
-void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s);
+// out[m] (+)= scale sum_i u_i dA_i/dp_m (accumulate: added to out, else stored)
+void launch_gather(const Bufs& b, const double* u, double* out, double scale, hipStream_t s, int accumulate = 0);
+// The crease part of the integrated mean curvature per atom into b.area, and
+// (with_grad) its gradient blocks into b.rows; FP64.
+void launch_terms_crease(const Bufs& b, int with_grad, hipStream_t s);
+// out[i] = u[i] / R_i (u may be NULL: 1 / R_i).
+void launch_recip_radius(const Bufs& b, const double* u, double* out, hipStream_t s);
 // Per-atom cell volumes and the molecular-volume gradient (needs b.area in FP64),
 // and with curv the per-atom integrated mean curvature of the surface.
 void launch_volume(const Bufs& b, double* vol, double* grad, hipStream_t s, double* curv = nullptr);

@@ -84,3 +84,49 @@ def test_device_tensors_batch_and_state():
     assert np.array_equal(cab, np.concatenate([ca.cpu().numpy(), cb]))
     assert eab == ea + eb
     ctx.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mean_curvature_vjp_vs_finite_differences(seed):
+    """sum_i u_i dC_i/dx against central differences of the oracle's sum_i u_i C_i, whose crease arcs
+    come from interval unions on the circles (no complex, no dihedral angles); the gradient's sum over
+    atoms vanishes (translation)."""
+    x, r = random_cluster(24, seed, box=7.0)
+    n = len(r)
+    u = np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+    ctx = _ctx(precision="mixed")
+    ctx.compute(x, r, 1.4)
+    g = ctx.curvature_backward(u)
+    h = 1e-5
+    fd = np.zeros((n, 3))
+    for m in range(n):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[m, a] += h
+            xm[m, a] -= h
+            fd[m, a] = (u @ oracle.mean_curvature(xp, r, 1.4)[0] - u @ oracle.mean_curvature(xm, r, 1.4)[0]) / (2 * h)
+    err = np.linalg.norm(g - fd, axis=1) / np.maximum(np.linalg.norm(fd, axis=1), 1.0)
+    assert err.max() <= 1e-5, f"VJP differs from finite differences by {err.max():.2e} at atom {err.argmax()}"
+    assert np.abs(g.sum(axis=0)).max() <= 1e-9 * max(np.abs(g).max(), 1.0)
+    ctx.close()
+
+
+def test_mean_curvature_vjp_device_and_incremental():
+    """Device tensors give the host result; an incremental context starts afresh after the VJP
+    (it rewrites the gradient blocks) and still equals a cold one."""
+    import torch
+    x, r = globule(300, 1)
+    n = len(r)
+    u = np.linspace(-1.0, 1.0, n)
+    inc, cold = _ctx(precision="fp64", incremental=True), _ctx(precision="fp64")
+    inc.compute(x, r, 1.4)
+    gh = inc.curvature_backward(u)
+    dev = torch.device("cuda:0")
+    gd = inc.curvature_backward(torch.tensor(u, device=dev))
+    assert np.array_equal(gd.cpu().numpy(), gh)
+    a1, g1 = inc.compute(x, r, 1.4)
+    assert inc.diagnostics()["skipped_atoms"] == 0
+    a0, g0 = cold.compute(x, r, 1.4)
+    assert np.array_equal(a1, a0) and np.array_equal(g1, g0)
+    inc.close()
+    cold.close()

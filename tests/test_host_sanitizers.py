@@ -41,6 +41,7 @@ assert L.sasa_edges_vertices_by_sort(None, None, None, 0, None, None, None, 0, N
 assert L.sasa_complex_counts(None, cnt) == _lib.SASA_E_INVAL
 assert L.sasa_status(None) == _lib.SASA_E_INVAL
 assert L.sasa_curvature(None, None, None, 0, None) == _lib.SASA_E_INVAL
+assert L.sasa_curvature_backward(None, None, None, 0, None) == _lib.SASA_E_INVAL
 h = ctypes.c_void_p()
 bad = _lib.sasa_options(0, 0, 0, 1 << 10, 0)
 assert L.sasa_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.SASA_E_INVAL and not h.value
