@@ -122,3 +122,46 @@ class VolumeFunction(torch.autograd.Function):
 def volume(xyz, radii, probe=1.4, offsets=None):
     """Differentiable per-atom cell volumes (A^3) of one molecule, or of a batch with ``offsets``."""
     return VolumeFunction.apply(xyz, radii, probe, offsets)
+
+
+class CurvatureFunction(torch.autograd.Function):
+    """C = CurvatureFunction.apply(xyz, radii, probe, offsets, precision) -> per-atom integrated mean
+    curvature (float64, A) of the accessible surface.
+
+    Forward computes the complex (``sasa_compute``) and C_i = A_i / R_i - 1/4 sum_j L_ij gamma_ij
+    (``sasa_curvature``); backward is the library's curvature VJP (``sasa_curvature_backward``).
+    The Euler characteristic is a topological invariant and carries no gradient, so it is not an
+    output here; ``SasaContext.curvature`` returns it.
+    """
+
+    @staticmethod
+    def forward(fctx, xyz, radii, probe=1.4, offsets=None, precision="fp64"):
+        if not xyz.is_cuda:
+            raise ValueError("CurvatureFunction needs HIP tensors (the library has no CPU path)")
+        dev = xyz.device.index if xyz.device.index is not None else torch.cuda.current_device()
+        held = _Held(_pool.acquire(dev, precision))
+        x = xyz.detach().to(torch.float64).contiguous()
+        r = radii.detach().to(torch.float64, copy=False).contiguous()
+        if offsets is None:
+            held.ctx.compute(x, r, probe, grad=False)
+        else:
+            held.ctx.compute_batch(offsets, x, r, probe, grad=False)
+        curv, _ = held.ctx.curvature()
+        fctx.held = held
+        fctx.dtype = xyz.dtype
+        return curv
+
+    @staticmethod
+    def backward(fctx, grad_curv):
+        held = fctx.held
+        if held is None:
+            raise RuntimeError("CurvatureFunction.backward called twice on one graph (retain_graph is not supported)")
+        g = held.ctx.curvature_backward(grad_curv.detach().to(torch.float64).contiguous())
+        fctx.held = None
+        held.done()
+        return g.to(fctx.dtype), None, None, None, None
+
+
+def mean_curvature(xyz, radii, probe=1.4, offsets=None, precision="fp64"):
+    """Differentiable per-atom integrated mean curvature (A) of one molecule, or of a batch with ``offsets``."""
+    return CurvatureFunction.apply(xyz, radii, probe, offsets, precision)

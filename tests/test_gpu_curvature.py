@@ -130,3 +130,30 @@ def test_mean_curvature_vjp_device_and_incremental():
     assert np.array_equal(a1, a0) and np.array_equal(g1, g0)
     inc.close()
     cold.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mean_curvature_autograd_batch(prec):
+    """CurvatureFunction over a batch of two molecules: the forward against the oracle, the backward
+    equal to each molecule's VJP taken alone (itself checked against finite differences above)."""
+    import torch
+    from paper_2401_10462_amd.autograd import mean_curvature
+    xa, ra = globule(300, 2)
+    xb, rb = random_cluster(80, 6)
+    offs = np.array([0, len(ra), len(ra) + len(rb)], dtype=np.int64)
+    X = torch.tensor(np.vstack([xa, xb]), device="cuda", requires_grad=True)
+    R = torch.tensor(np.concatenate([ra, rb]), device="cuda")
+    w = np.random.default_rng(5).uniform(-1.0, 1.0, len(R))
+    print(f"curvature autograd batch 300 + 80 {prec}", flush=True)
+    C = mean_curvature(X, R, 1.4, offsets=offs, precision=prec)
+    (torch.tensor(w, device="cuda") * C).sum().backward()
+    c, g = C.detach().cpu().numpy(), X.grad.cpu().numpy()
+    for s, (x, r) in ((slice(0, len(ra)), (xa, ra)), (slice(len(ra), None), (xb, rb))):
+        ref, _ = oracle.mean_curvature(x, r, 1.4)
+        _check(c[s], ref)
+        ctx = _ctx(precision=prec)
+        ctx.compute(x, r, 1.4)
+        alone = ctx.curvature_backward(w[s])
+        ctx.close()
+        err = np.linalg.norm(g[s] - alone, axis=1) / np.maximum(np.linalg.norm(alone, axis=1), 1.0)
+        assert err.max() <= 1e-9, f"batched VJP differs from the molecule alone by {err.max():.2e}"
