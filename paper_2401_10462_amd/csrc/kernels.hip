@@ -296,9 +296,14 @@ __global__ void k_scatter(Bufs b) {
 // The whole cell-list stage of a call with one molecule in one block: clears
 // the counters, weights + box, grid, per-cell counts (in LDS when the grid
 // fits), their scan and the scatter into cell order.  It replaces the ten
-// launches of the batched path for the common single-molecule call.
+// launches of the batched path for the common single-molecule call.  Its
+// memory traffic all goes through one CU, so the scatter into cell order is
+// staged in LDS and leaves in coalesced stores (a direct scatter touches one
+// cache line per atom and store, and the CU's address unit then sets the pace).
 constexpr int ONE_T = 1024;
 constexpr int ONE_LDS_CELLS = 32768;
+// atoms per staging pass: a 32-byte position and two ints each in the count array's LDS
+constexpr int ONE_STAGE = ONE_LDS_CELLS * (int)sizeof(int) / 40;
 
 // Every atom of the call stays in the registers of one thread (n <= PER *
 // ONE_T); larger molecules take the multi-kernel cell list, which spreads over
@@ -307,9 +312,9 @@ template <int PER>
 __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   static_assert(PER > 0, "atoms in registers");
   constexpr int R = PER;
-  __shared__ int lcnt[ONE_LDS_CELLS];
+  __shared__ __align__(32) int lcnt[ONE_LDS_CELLS];
   __shared__ double red[ONE_T / 64][7];
-  __shared__ int scan_lds[ONE_T];
+  __shared__ int scan_lds[ONE_T / 64];
   __shared__ int s_cells;
   const int t = threadIdx.x, lane = t & 63;
   for (int k = t; k < C_COUNT * CTR_STRIDE; k += ONE_T) b.ctr[k] = 0ull;
@@ -334,7 +339,6 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     }
     r += b.probe;
     b.pos[i] = make_double4(x, y, z, r);
-    b.mol[i] = 0;
     v[0] = fmin(v[0], x), v[1] = fmin(v[1], y), v[2] = fmin(v[2], z);
     v[3] = fmax(v[3], x), v[4] = fmax(v[4], y), v[5] = fmax(v[5], z);
     v[6] = fmax(v[6], r);
@@ -395,7 +399,6 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     const int i = t + k * ONE_T;
     if (i < b.n) {
       rc[k] = cell_of(rx[k], ry[k], rz[k]);
-      b.cellid[i] = rc[k];
       atomicAdd(&cnt[rc[k]], 1);
     }
   }
@@ -405,42 +408,60 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   const int c0 = min(t * per, cells), c1 = min(c0 + per, cells);
   int sum = 0;
   for (int c = c0; c < c1; ++c) sum += cnt[c];
-  scan_lds[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < ONE_T; off <<= 1) {
-    const int x = t >= off ? scan_lds[t - off] : 0;
-    __syncthreads();
-    scan_lds[t] += x;
-    __syncthreads();
+  // inclusive scan of the threads' sums: within each wave by lane shifts, then
+  // across the waves' totals (two barriers in all)
+  int incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int x = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += x;
   }
-  int run = scan_lds[t] - sum;
+  if (lane == 63) scan_lds[t >> 6] = incl;
+  __syncthreads();
+  for (int w = 0; w < (t >> 6); ++w) incl += scan_lds[w];
+  int run = incl - sum;
   for (int c = c0; c < c1; ++c) {
     const int k = cnt[c];
     if (!in_lds) b.start[c] = run;
     cnt[c] = run;  // becomes the fill cursor of the cell
     run += k;
   }
-  if (t == ONE_T - 1) b.start[cells] = scan_lds[ONE_T - 1];
+  if (t == ONE_T - 1) b.start[cells] = incl;
   __syncthreads();
   if (in_lds) {  // the cell starts leave LDS in coalesced stores (a thread's own cells are strided)
     for (int c = t; c < cells; c += ONE_T) b.start[c] = lcnt[c];
     __syncthreads();
   }
-  // every slot first (the cursor atomics then are all in flight together),
-  // then the stores
+  // every slot first (the cursor atomics then are all in flight together)
   int slot[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int i = t + k * ONE_T;
-    if (i < b.n) slot[k] = atomicAdd(&cnt[rc[k]], 1);
+    slot[k] = i < b.n ? atomicAdd(&cnt[rc[k]], 1) : -1;
   }
+  // then the scatter, ONE_STAGE slots per pass: each atom of the pass's slot
+  // range goes to LDS (the counts are no longer needed), and the range leaves
+  // in slot order
+  double4* st_pos = reinterpret_cast<double4*>(lcnt);
+  int* st_id = reinterpret_cast<int*>(st_pos + ONE_STAGE);
+  int* st_cell = st_id + ONE_STAGE;
+  for (int base = 0; base < b.n; base += ONE_STAGE) {
+    __syncthreads();  // the slot atomics, or the last pass's stores, have read LDS
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int i = t + k * ONE_T;
-    if (i < b.n) {
-      b.sorted[slot[k]] = i;
-      b.spos[slot[k]] = make_double4(rx[k], ry[k], rz[k], rr[k]);
-      b.smc[slot[k]] = make_int2(0, rc[k]);
+    for (int k = 0; k < R; ++k) {
+      const int i = t + k * ONE_T;
+      const int j = slot[k] - base;
+      if (i < b.n && j >= 0 && j < ONE_STAGE) {
+        st_pos[j] = make_double4(rx[k], ry[k], rz[k], rr[k]);
+        st_id[j] = i;
+        st_cell[j] = rc[k];
+      }
+    }
+    __syncthreads();
+    const int m = min(ONE_STAGE, b.n - base);
+    for (int j = t; j < m; j += ONE_T) {
+      b.sorted[base + j] = st_id[j];
+      b.spos[base + j] = st_pos[j];
+      b.smc[base + j] = make_int2(0, st_cell[j]);
     }
   }
 }
