@@ -305,6 +305,37 @@ constexpr int ONE_LDS_CELLS = 32768;
 // atoms per staging pass: a 32-byte position and two ints each in the count array's LDS
 constexpr int ONE_STAGE = ONE_LDS_CELLS * (int)sizeof(int) / 40;
 
+// A double moved N lanes up within each row of 16 lanes (DPP); a lane with no
+// source in its row keeps its own value, which min and max ignore.
+template <int N>
+__device__ inline double row_shr(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = (int)(u & 0xffffffffll), hi = (int)(u >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x110 + N, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x110 + N, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned)l2);
+}
+// min (or max) over the 64 lanes, in every lane: four DPP steps leave each
+// row's result in its last lane, and the four rows meet in scalar reads
+template <bool MAX>
+__device__ inline double wave_minmax(double x) {
+  auto op = [](double a, double c) { return MAX ? fmax(a, c) : fmin(a, c); };
+  x = op(x, row_shr<1>(x));
+  x = op(x, row_shr<2>(x));
+  x = op(x, row_shr<4>(x));
+  x = op(x, row_shr<8>(x));
+  const long long u = __double_as_longlong(x);
+  const int lo = (int)(u & 0xffffffffll), hi = (int)(u >> 32);
+  double r = 0.0;
+#pragma unroll
+  for (int l = 15; l < 64; l += 16) {
+    const double y = __longlong_as_double(((long long)__builtin_amdgcn_readlane(hi, l) << 32) |
+                                          (unsigned)__builtin_amdgcn_readlane(lo, l));
+    r = l == 15 ? y : op(r, y);
+  }
+  return r;
+}
+
 // Every atom of the call stays in the registers of one thread (n <= PER *
 // ONE_T); larger molecules take the multi-kernel cell list, which spreads over
 // the whole GPU.
@@ -315,7 +346,6 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   __shared__ __align__(32) int lcnt[ONE_LDS_CELLS];
   __shared__ double red[ONE_T / 64][7];
   __shared__ int scan_lds[ONE_T / 64];
-  __shared__ int s_cells;
   const int t = threadIdx.x, lane = t & 63;
   for (int k = t; k < C_COUNT * CTR_STRIDE; k += ONE_T) b.ctr[k] = 0ull;
   // weights, box and R_max
@@ -353,43 +383,36 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     const int i = t + k * ONE_T;
     if (i < b.n) weigh(i, rx[k], ry[k], rz[k], rr[k]);
   }
-  // (the seven reductions step together: six dependent exchanges in all)
-  for (int off = 32; off > 0; off >>= 1) {
+  // box and R_max: each wave reduces its lanes, and after the barrier every
+  // wave reduces the waves' results itself (no second barrier to hand them out)
+  auto minmax7 = [&](double* w) {
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      const double o = __shfl_xor(v[q], off, 64);
-      v[q] = q < 3 ? fmin(v[q], o) : fmax(v[q], o);
-    }
-    bad += __shfl_xor(bad, off, 64);
-  }
+    for (int q = 0; q < 3; ++q) w[q] = wave_minmax<false>(w[q]);
+#pragma unroll
+    for (int q = 3; q < 7; ++q) w[q] = wave_minmax<true>(w[q]);
+  };
+  minmax7(v);
   if (lane == 0)
     for (int q = 0; q < 7; ++q) red[t >> 6][q] = v[q];
   __syncthreads();  // also orders the counter clearing before the stores below
-  if (lane == 0 && bad) atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], (unsigned long long)bad);
+  if (bad) atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], (unsigned long long)bad);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) v[q] = lane < ONE_T / 64 ? red[lane][q] : (q < 3 ? inf : -inf);
+  minmax7(v);
+  const double rmax = v[6];
+  double4 geo;
+  int dx, dy, dz;
+  const int cells = grid_dims(v[0], v[1], v[2], v[3], v[4], v[5], b.n, rmax, geo, dx, dy, dz);
   if (t == 0) {
-    for (int w = 1; w < ONE_T / 64; ++w)
-      for (int q = 0; q < 7; ++q) v[q] = q < 3 ? fmin(v[q], red[w][q]) : fmax(v[q], red[w][q]);
-    const double rmax = v[6];
     b.ctr[ctr_slot(C_RMAX_BITS)] = (unsigned long long)__double_as_longlong(rmax);
-    double4 geo;
-    int nx, ny, nz;
-    const int cells = grid_dims(v[0], v[1], v[2], v[3], v[4], v[5], b.n, rmax, geo, nx, ny, nz);
     b.mol_geo[0] = geo;
-    b.mol_dim[0] = make_int4(nx, ny, nz, 0);
+    b.mol_dim[0] = make_int4(dx, dy, dz, 0);
     b.ctr[ctr_slot(C_CELLS)] = (unsigned long long)cells;
-    s_cells = cells;
-    red[0][0] = geo.x, red[0][1] = geo.y, red[0][2] = geo.z, red[0][3] = geo.w;
-    red[0][4] = __longlong_as_double(((long long)nx << 32) | (unsigned)ny);
-    red[0][5] = __longlong_as_double((long long)nz);
   }
-  __syncthreads();
-  const int cells = s_cells;
   const bool in_lds = cells <= ONE_LDS_CELLS;
   int* cnt = in_lds ? lcnt : b.cnt;
   for (int c = t; c < cells; c += ONE_T) cnt[c] = 0;
-  const double gx = red[0][0], gy = red[0][1], gz = red[0][2], inv_s = 1.0 / red[0][3];
-  const long long d01 = __double_as_longlong(red[0][4]);
-  const int dx = (int)(d01 >> 32), dy = (int)(d01 & 0xffffffffll), dz = (int)__double_as_longlong(red[0][5]);
+  const double gx = geo.x, gy = geo.y, gz = geo.z, inv_s = 1.0 / geo.w;
   __syncthreads();
   auto cell_of = [&](double x, double y, double z) {
     return (cell_index(z, gz, inv_s, dz) * dy + cell_index(y, gy, inv_s, dy)) * dx + cell_index(x, gx, inv_s, dx);
