@@ -2373,10 +2373,25 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
 // 16 lanes per receiving atom m (4 atoms per wavefront): lane l takes the
 // K-neighbours l, l + 16, ... of m, finds m among each neighbour i's sorted
 // K-neighbours and adds u_i dA_i/dp_m; a fixed xor tree sums the 16 partials,
-// so the result does not depend on scheduling.
+// so the result does not depend on scheduling.  The search compares 16 entries
+// of i's list at a time, loaded together with i's flag and count (the rows are
+// KN_CAP entries wide and 16-byte aligned), so that finding m takes one memory
+// round trip for lists of up to 16 entries instead of a chain of dependent loads.
 __device__ inline double sum16(double v) {
   for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+// the slot of m among entries [c, c + 16) of a K-list of nk entries, or s
+__device__ inline int find16(const int4 (&q)[4], int m, int c, int nk, int s) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int j = c + 4 * e;
+    if (q[e].x == m && j < nk) s = j;
+    if (q[e].y == m && j + 1 < nk) s = j + 1;
+    if (q[e].z == m && j + 2 < nk) s = j + 2;
+    if (q[e].w == m && j + 3 < nk) s = j + 3;
+  }
+  return s;
 }
 
 __global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* out, double scale, int accumulate) {
@@ -2393,18 +2408,18 @@ __global__ __launch_bounds__(64) void k_gather(Bufs b, const double* u, double* 
     const int nk = b.kn_cnt[m];
     for (int k = sub; k < nk; k += 16) {
       const int i = b.knbr[(size_t)m * KN_CAP + k];
-      if (!(b.vflag[i] & VF_EXT)) continue;
-      const int* li = b.knbr + (size_t)i * KN_CAP;
-      int lo = 0, hi = b.kn_cnt[i] - 1, s = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = li[mid];
-        if (v == m) {
-          s = mid;
-          break;
-        }
-        if (v < m) lo = mid + 1;
-        else hi = mid - 1;
+      const int4* li = reinterpret_cast<const int4*>(b.knbr + (size_t)i * KN_CAP);
+      const uint8_t fl = b.vflag[i];
+      const int nki = b.kn_cnt[i];
+      int4 q[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) q[e] = li[e];
+      if (!(fl & VF_EXT)) continue;
+      int s = find16(q, m, 0, nki, -1);
+      for (int c = 16; s < 0 && c < nki; c += 16) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = li[c / 4 + e];
+        s = find16(q, m, c, nki, s);
       }
       if (s < 0) {
         ++lost;
