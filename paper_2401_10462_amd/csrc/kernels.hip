@@ -336,18 +336,19 @@ __device__ inline double wave_minmax(double x) {
   return r;
 }
 
-// Every atom of the call stays in the registers of one thread (n <= PER *
-// ONE_T); larger molecules take the multi-kernel cell list, which spreads over
-// the whole GPU.
-template <int PER>
-__global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
+// Every atom of the call stays in the registers of one thread (n <= PER * NT,
+// NT threads); larger molecules take the multi-kernel cell list, which spreads
+// over the whole GPU.  Small molecules take fewer waves and fewer atoms per
+// thread: the block's barriers then wait on fewer waves, and less code runs.
+template <int PER, int NT>
+__global__ __launch_bounds__(NT) void k_cells_one(Bufs b) {
   static_assert(PER > 0, "atoms in registers");
   constexpr int R = PER;
   __shared__ __align__(32) int lcnt[ONE_LDS_CELLS];
-  __shared__ double red[ONE_T / 64][7];
-  __shared__ int scan_lds[ONE_T / 64];
+  __shared__ double red[NT / 64][7];
+  __shared__ int scan_lds[NT / 64];
   const int t = threadIdx.x, lane = t & 63;
-  for (int k = t; k < C_COUNT * CTR_STRIDE; k += ONE_T) b.ctr[k] = 0ull;
+  for (int k = t; k < C_COUNT * CTR_STRIDE; k += NT) b.ctr[k] = 0ull;
   // weights, box and R_max
   const double inf = __longlong_as_double(0x7ff0000000000000ll);
   double v[7] = {inf, inf, inf, -inf, -inf, -inf, 0.0};
@@ -375,12 +376,12 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   };
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int i = t + k * ONE_T;
+    const int i = t + k * NT;
     if (i < b.n) load(i, rx[k], ry[k], rz[k], rr[k]);
   }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int i = t + k * ONE_T;
+    const int i = t + k * NT;
     if (i < b.n) weigh(i, rx[k], ry[k], rz[k], rr[k]);
   }
   // box and R_max: each wave reduces its lanes, and after the barrier every
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   __syncthreads();  // also orders the counter clearing before the stores below
   if (bad) atomicAdd(&b.ctr[ctr_slot(C_BAD_INPUT)], (unsigned long long)bad);
 #pragma unroll
-  for (int q = 0; q < 7; ++q) v[q] = lane < ONE_T / 64 ? red[lane][q] : (q < 3 ? inf : -inf);
+  for (int q = 0; q < 7; ++q) v[q] = lane < NT / 64 ? red[lane][q] : (q < 3 ? inf : -inf);
   minmax7(v);
   const double rmax = v[6];
   double4 geo;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   }
   const bool in_lds = cells <= ONE_LDS_CELLS;
   int* cnt = in_lds ? lcnt : b.cnt;
-  for (int c = t; c < cells; c += ONE_T) cnt[c] = 0;
+  for (int c = t; c < cells; c += NT) cnt[c] = 0;
   const double gx = geo.x, gy = geo.y, gz = geo.z, inv_s = 1.0 / geo.w;
   __syncthreads();
   auto cell_of = [&](double x, double y, double z) {
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   };
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int i = t + k * ONE_T;
+    const int i = t + k * NT;
     if (i < b.n) {
       rc[k] = cell_of(rx[k], ry[k], rz[k]);
       atomicAdd(&cnt[rc[k]], 1);
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
   }
   __syncthreads();
   // exclusive scan: thread t owns the contiguous cells [t*per, (t+1)*per)
-  const int per = (cells + ONE_T - 1) / ONE_T;
+  const int per = (cells + NT - 1) / NT;
   const int c0 = min(t * per, cells), c1 = min(c0 + per, cells);
   int sum = 0;
   for (int c = c0; c < c1; ++c) sum += cnt[c];
@@ -448,17 +449,17 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     cnt[c] = run;  // becomes the fill cursor of the cell
     run += k;
   }
-  if (t == ONE_T - 1) b.start[cells] = incl;
+  if (t == NT - 1) b.start[cells] = incl;
   __syncthreads();
   if (in_lds) {  // the cell starts leave LDS in coalesced stores (a thread's own cells are strided)
-    for (int c = t; c < cells; c += ONE_T) b.start[c] = lcnt[c];
+    for (int c = t; c < cells; c += NT) b.start[c] = lcnt[c];
     __syncthreads();
   }
   // every slot first (the cursor atomics then are all in flight together)
   int slot[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int i = t + k * ONE_T;
+    const int i = t + k * NT;
     slot[k] = i < b.n ? atomicAdd(&cnt[rc[k]], 1) : -1;
   }
   // then the scatter, ONE_STAGE slots per pass: each atom of the pass's slot
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     __syncthreads();  // the slot atomics, or the last pass's stores, have read LDS
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const int i = t + k * ONE_T;
+      const int i = t + k * NT;
       const int j = slot[k] - base;
       if (i < b.n && j >= 0 && j < ONE_STAGE) {
         st_pos[j] = make_double4(rx[k], ry[k], rz[k], rr[k]);
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(ONE_T) void k_cells_one(Bufs b) {
     }
     __syncthreads();
     const int m = min(ONE_STAGE, b.n - base);
-    for (int j = t; j < m; j += ONE_T) {
+    for (int j = t; j < m; j += NT) {
       b.sorted[base + j] = st_id[j];
       b.spos[base + j] = st_pos[j];
       b.smc[base + j] = make_int2(0, st_cell[j]);
@@ -2492,7 +2493,11 @@ void launch_scatter(const Bufs& b, hipStream_t s) {
 void launch_cells_one(const Bufs& b, hipStream_t s) {
   if (!b.n) return;
   static_assert(ONE_BLOCK_MAX_ATOMS <= 8 * ONE_T, "one block holds its atoms in registers");
-  k_cells_one<8><<<1, ONE_T, 0, s>>>(b);
+  if (b.n <= 512) k_cells_one<2, 256><<<1, 256, 0, s>>>(b);
+  else if (b.n <= ONE_T) k_cells_one<1, ONE_T><<<1, ONE_T, 0, s>>>(b);
+  else if (b.n <= 2 * ONE_T) k_cells_one<2, ONE_T><<<1, ONE_T, 0, s>>>(b);
+  else if (b.n <= 5 * ONE_T) k_cells_one<5, ONE_T><<<1, ONE_T, 0, s>>>(b);
+  else k_cells_one<8, ONE_T><<<1, ONE_T, 0, s>>>(b);
 }
 void launch_star(const Bufs& b, hipStream_t s) {
   if (!b.n) return;
