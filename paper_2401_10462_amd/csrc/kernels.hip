@@ -2178,10 +2178,13 @@ __device__ inline double tet_quality(double ax, double ay, double az, double bx,
 // sin theta; the quality bounds sin theta from below.  Largest gradient error
 // on a drifted 20,000-atom MD frame (bar 1e-4): 2.9e-5 at a bound of 0.2
 // (5.7e-5 with the normals in float), 4.6e-5 at 0.05, 5.0e-5 at 0.01 and
-// 2.6e-4 with no item promoted.  A promoted item runs the double path beside
-// the float one in its wavefront, so a lower bound is faster (0.01: 34.0
-// instead of 38.9 us for the terms of the 5,000-atom globule), but large
-// probes (larger caps) then reached 1.01e-4 of the bar: 0.2 is kept.
+// 2.6e-4 with no item promoted; large probes (larger caps) reached 1.01e-4 at
+// 0.01, so 0.2 is kept.  One item below the bound puts its wavefront's whole
+// chunk of 64 items in double: with item-wise promotion the wavefront ran both
+// paths whenever one lane needed double, which was nearly always, and FP64
+// runs at the FP32 rate on this GPU, so the double path costs no more than the
+// float one (terms of the 5,000-atom globule 38.9 -> 33.3 us, and the errors
+// only fall).
 constexpr double kTetQualityMin = 0.2;
 constexpr double kTripleDepthMin = 0.1;  // -s_t / w_i: triple points close to the centres' plane
 
@@ -2255,9 +2258,9 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
         for (int c = 0; c < 3; ++c) L.c.t.tg[lane][c][0] = L.c.t.tg[lane][c][1] = L.c.t.tg[lane][c][2] = 0.0;
       } else {
         bool dbl = sizeof(T) == sizeof(double);
-        if (!dbl)
-          dbl = tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
-                            L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin;
+        if (!dbl)  // one poorly shaped tetrahedron puts the wave's whole chunk in double (see below)
+          dbl = __ballot(tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
+                                     L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin) != 0ull;
         double ph[3];
         const int osg = (w >> 24) & 1u ? -1 : 1;  // orientation of (i, ks[0], ks[1], ks[2]), decided exactly
         const double om = dbl ? tet_item<double>(L, ks, osg, extm, Si, grad, ph, L.c.t.tg[lane])
@@ -2317,7 +2320,8 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
           const double X0 = yx + f * nx, X1 = yy + f * ny, X2 = yz + f * nz;
           bool dbl = sizeof(T) == sizeof(double);
           if (!dbl)
-            dbl = (-s < kTripleDepthMin * wi) || tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin;
+            dbl = __ballot((-s < kTripleDepthMin * wi) ||
+                           tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin) != 0ull;
           St = dbl ? tri_item<double, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
                    : tri_item<T, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
         }
