@@ -160,11 +160,11 @@ def local_moves(args, precision):
             ctx.forces(X, R, 0.005, 1.4)
         torch.cuda.synchronize()
         lat, kept = [], []
-        out = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev))
+        bufs = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev))
         for idx, d in moves[args.warmup:]:
             t = time.perf_counter()
             X.index_add_(0, idx, d)
-            a, f = ctx.forces(X, R, 0.005, 1.4, out=out)
+            a, f = ctx.forces(X, R, 0.005, 1.4, out=bufs)
             torch.cuda.synchronize()
             lat.append(1e3 * (time.perf_counter() - t))
             if inc and len(kept) < 20:
