@@ -2163,13 +2163,14 @@ __device__ double tri_item(const TermsLds& L, int ka, int kb, double X0, double 
   return St;
 }
 
-// Conditioning of a tetrahedron seen from the origin: |a.(b x c)| / (|a||b||c|),
-// small for slivers, whose angle derivatives lose accuracy in float.
-__device__ inline double tet_quality(double ax, double ay, double az, double bx, double by, double bz, double cx,
-                                     double cy, double cz) {
+// Conditioning of a tetrahedron seen from the origin, |a.(b x c)| / (|a||b||c|),
+// small for slivers, whose angle derivatives lose accuracy in float: true when
+// it is below q (compared squared, without a root or a division).
+__device__ inline bool tet_below(double ax, double ay, double az, double bx, double by, double bz, double cx,
+                                 double cy, double cz, double q) {
   const double tp = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
-  const double l = sqrt((ax * ax + ay * ay + az * az) * (bx * bx + by * by + bz * bz) * (cx * cx + cy * cy + cz * cz));
-  return fabs(tp) / l;
+  const double l2 = (ax * ax + ay * ay + az * az) * (bx * bx + by * by + bz * bz) * (cx * cx + cy * cy + cz * cz);
+  return tp * tp < q * q * l2;
 }
 
 // In MIXED precision, items below these qualities are evaluated in double.
@@ -2259,8 +2260,8 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
       } else {
         bool dbl = sizeof(T) == sizeof(double);
         if (!dbl)  // one poorly shaped tetrahedron puts the wave's whole chunk in double (see below)
-          dbl = __ballot(tet_quality(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
-                                     L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]]) < kTetQualityMin) != 0ull;
+          dbl = __ballot(tet_below(L.px[ks[0]], L.py[ks[0]], L.pz[ks[0]], L.px[ks[1]], L.py[ks[1]], L.pz[ks[1]],
+                                   L.px[ks[2]], L.py[ks[2]], L.pz[ks[2]], kTetQualityMin)) != 0ull;
         double ph[3];
         const int osg = (w >> 24) & 1u ? -1 : 1;  // orientation of (i, ks[0], ks[1], ks[2]), decided exactly
         const double om = dbl ? tet_item<double>(L, ks, osg, extm, Si, grad, ph, L.c.t.tg[lane])
@@ -2321,7 +2322,7 @@ __global__ __launch_bounds__(64) void k_terms(Bufs b, int with_grad) {
           bool dbl = sizeof(T) == sizeof(double);
           if (!dbl)
             dbl = __ballot((-s < kTripleDepthMin * wi) ||
-                           tet_quality(ax, ay, az, bx, by, bz, X0, X1, X2) < kTetQualityMin) != 0ull;
+                           tet_below(ax, ay, az, bx, by, bz, X0, X1, X2, kTetQualityMin)) != 0ull;
           St = dbl ? tri_item<double, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G)
                    : tri_item<T, CR>(L, ka, kb, X0, X1, X2, Ri, Si, grad, G);
         }
