@@ -33,3 +33,25 @@ def test_one_block_equals_multi_kernel(prec):
         assert np.array_equal(g1, g2[:n]), f"gradients differ at n = {n}"
         assert np.all(np.isfinite(a1)) and np.all(np.isfinite(g1))
     ctx.close()
+
+
+@pytest.mark.parametrize("n,box", [(5000, 400.0), (8192, 500.0)])
+def test_one_block_sparse_grid_counts_in_global_memory(n, box):
+    """A sparse molecule whose grid has more cells than the one-block kernel keeps in LDS (32,768): the cell counts
+    and cursors then live in global memory; still bitwise the multi-kernel result."""
+    from paper_2401_10462_amd import SasaContext
+    x, r = random_cluster(n, 7, box=box)
+    xb = np.vstack([x, x[:3] + 5000.0])
+    rb = np.concatenate([r, r[:3]])
+    offs = np.array([0, n, n + 3], dtype=np.int64)
+    # the grid rule (cell side R_max, enlarged by 1.25 until at most 8 n + 8 cells) gives more than 32,768 cells here
+    ext, s = x.max(axis=0) - x.min(axis=0), r.max() + 1.4
+    while np.prod(np.floor(ext / s) + 1) > 8 * n + 8:
+        s *= 1.25
+    assert np.prod(np.floor(ext / s) + 1) > 32768
+    ctx = SasaContext(precision="fp64", max_atoms=n + 3)
+    print(f"sparse cell list: n = {n}, box {box} A", flush=True)
+    a1, g1 = ctx.compute(x, r, 1.4)
+    a2, g2 = ctx.compute_batch(offs, xb, rb, 1.4)
+    assert np.array_equal(a1, a2[:n]) and np.array_equal(g1, g2[:n])
+    ctx.close()
