@@ -251,3 +251,37 @@ def test_incremental_random_sequence(seed):
     assert max(skipped) > n // 2
     inc.close()
     cold.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_incremental_with_volume_and_curvature(prec):
+    """Volumes, curvatures and their VJPs taken between incremental calls: bitwise those of a cold context, and the
+    incremental calls after them still equal cold ones (the volume and curvature kernels recompute FP64 areas of
+    every atom and must not disturb the kept stars; the curvature VJP rewrites the gradient blocks, so the next
+    call starts afresh)."""
+    x, r = globule(600, 4, hydrogens=True)
+    n = len(r)
+    rng = np.random.default_rng(21)
+    u = rng.uniform(-1.0, 1.0, n)
+    inc, cold = _ctx(precision=prec, incremental=True), _ctx(precision=prec)
+    cur = x
+    for step in range(6):
+        cur, moved = _local_move(cur, rng)
+        print(f"incremental + volume/curvature {prec}: step {step}, {moved} atoms moved", flush=True)
+        _equal(inc.compute(cur, r, 1.4), cold.compute(cur, r, 1.4), f"step {step} compute")
+        kept = inc.diagnostics()["skipped_atoms"]
+        if step in (1, 2, 4):
+            assert kept > n // 2, f"step {step}: only {kept} stars kept"
+        else:  # the first call, and the calls after a curvature VJP
+            assert kept == 0
+        if step == 0:
+            continue
+        (v1, vg1), (v0, vg0) = inc.volume(), cold.volume()
+        assert np.array_equal(v1, v0) and np.array_equal(vg1, vg0), f"step {step}: volumes differ"
+        assert np.array_equal(inc.volume_backward(u), cold.volume_backward(u))
+        (c1, e1), (c0, e0) = inc.curvature(), cold.curvature()
+        assert np.array_equal(c1, c0) and e1 == e0, f"step {step}: curvatures differ"
+        if step % 2 == 0:
+            assert np.array_equal(inc.curvature_backward(u), cold.curvature_backward(u))
+    inc.close()
+    cold.close()
