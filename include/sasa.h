@@ -220,7 +220,12 @@ int sasa_volume_backward(sasa_context* ctx, const double* dL_dV, double* dL_dx, 
  *   euler    host int64 out (may be NULL): V - E + T - Q of K, the Euler
  *            characteristic of the union of the balls (K is homotopy
  *            equivalent to it), so the integrated Gaussian curvature of the
- *            surface is 4 pi * euler (Gauss-Bonnet).
+ *            surface is 4 pi * euler (Gauss-Bonnet).  At exact ties where
+ *            more than four cells meet at one point and the stars split the
+ *            point differently (a regular octahedron of equal balls), the
+ *            counts are not those of one complex and euler can be off; the
+ *            per-atom measures (areas, volumes, mean curvature) are not
+ *            affected.
  * Synchronous.  SASA_E_STATE without a kept compute, SASA_E_INVAL for a bad
  * mem or both outputs NULL.  Uses the input staging buffers of the context
  * as scratch (the last compute's results and complex stay).
